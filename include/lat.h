@@ -1,0 +1,214 @@
+/*
+ * lat.h -- C ABI of the MI355X principal-cell lattice library (liblat.so, gfx950).
+ *
+ * The library implements, on one GPU, the data-parallel hot path of the reduced-order
+ * lattice solver of "Efficient Fine-Scale Simulation of Nonlinear Hyperelastic Lattice
+ * Structures" (Sec. 3.1-3.2):
+ *   - local-to-global DOF maps of voxelised unit cells           (eq. residualvector)
+ *   - per-cell neo-Hookean residual, energy and tangent          (eq. internalloadvec,
+ *     Sec. 3.1.4, eq. fullquadraturerule, eq. snapshots)
+ *   - greedy selection of principal cells and RB coefficients    (Algorithm 1, Sec. 3.2.2)
+ *   - the ROM operator apply Y_i = sum_k alpha_ik K_k X_i         (eq. romstiffnessmatrix)
+ *   - the plain per-cell apply Y_i = K_i X_i (the standard operator, Sec. 3.1.4)
+ *   - reverse-mode (adjoint) forms of the residual and of the ROM apply.
+ *
+ * General conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless its comment says
+ *     HOST.  The library never frees or keeps caller memory.
+ *   - Every call is enqueued on the given HIP stream and returns without waiting, unless
+ *     stated otherwise.  Argument and shape errors are detected on the host and returned
+ *     synchronously; nothing is enqueued then.
+ *   - Data-dependent failures (an inverted element, a non-finite value) are written to a
+ *     caller-provided device status word `dev_status` int32[2] = {code, first bad cell}
+ *     (initialise it with lat_status_reset); the caller reads it after synchronising.
+ *   - A plan owns immutable tables and a scratch workspace; calls on one plan must not
+ *     overlap in time (use one stream per plan, or synchronise).
+ *   - Indices are 0-based.  Geometry: cell edge 1, n Q1 elements per cell axis, h = 1/n;
+ *     element e = ex + n(ey + n ez); local node a = ix + (n+1)(iy + (n+1) iz); element
+ *     corners x-fastest; cells numbered x-fastest over the lattice ("canonical" order).
+ *   - Stencil entry index e = ((o * d) + i) * d + j with offset index
+ *     o = (ox+1) + 3(oy+1) + 9(oz+1); entry (a, o, i, j) = K[(a,i),(a+o,j)].  E = 3^d d^2.
+ *
+ * Layouts defined by a plan (query the sizes with lat_plan_info):
+ *   plan lanes   cells are sorted by a mask-similarity key and grouped 64 at a time;
+ *                plan lane p = 64 g + l (group g, lane l); ld = 64 * n_groups; the map
+ *                lane -> canonical cell (or -1 for padding) is returned by lat_dofmap.
+ *   CIL(k)       cell-interleaved local field: element (a, c) of cell s at
+ *                [(a * k + c) * ld + lane(s)], a < (n+1)^d, c < k.  The snapshot matrix T is
+ *                CIL(E): row index (a, e) = the canonical snapshot index, column = lane.
+ *   packed       operator-apply vectors: for group g the union of its cells' active nodes
+ *                (n_packed nodes in total); element (node q, i, r, l) at
+ *                [((q * d + i) * m + r) * 64 + l].  Entries at DOFs a cell does not own are
+ *                ignored on input and written as 0 on output.
+ *   plain ops    per-cell stencils in packed form: [(q * E + e) * 64 + l].
+ *   principal    stack of principal stencils: [(a * E + e) * cap + k], a over all (n+1)^d
+ *                local nodes, k < cap principal slots (slots >= n_r hold zeros).
+ */
+#ifndef LAT_H
+#define LAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAT_OK = 0,
+    LAT_E_ARG = 1,        /* bad argument (null pointer, out-of-range value) */
+    LAT_E_SHAPE = 2,      /* sizes inconsistent with the plan */
+    LAT_E_DEVICE = 3,     /* a HIP runtime call failed */
+    LAT_E_NOMEM = 4,      /* device allocation failed */
+    LAT_E_INVERTED = 5,   /* (device status) J <= 0 at a Gauss point */
+    LAT_E_NONFINITE = 6,  /* (device status) non-finite displacement or Jacobian */
+    LAT_W_CAP = 7         /* (device status) greedy stopped at the cap above the tolerance */
+} lat_status;
+
+typedef enum { LAT_RULE_FULL = 0, LAT_RULE_REDUCED = 1 } lat_rule;   /* 2^d Gauss points / 1 point */
+typedef enum { LAT_F64 = 0, LAT_F32 = 1, LAT_BF16 = 2 } lat_prec;
+
+typedef struct lat_plan lat_plan;
+
+enum {
+    LAT_INFO_DIM = 0, LAT_INFO_NEL, LAT_INFO_NCELLS, LAT_INFO_NLOC, LAT_INFO_NELEM, LAT_INFO_E,
+    LAT_INFO_NSNAP, LAT_INFO_LD, LAT_INFO_NGROUPS, LAT_INFO_NPACKED, LAT_INFO_NGLOBAL, LAT_INFO_CAP,
+    LAT_INFO_N
+};
+
+/* Human-readable text of a status code (static storage). */
+const char *lat_status_string(lat_status s);
+
+/* Builds a plan for a lattice of ncell[0] x ncell[1] (x ncell[2]) congruent cells of
+ * nel^dim Q1 elements.  keep_host: HOST uint8 [N_s][nel^dim], 1 = element kept.
+ * cap: maximum number of principal cells any later call will use (1..64).
+ * Runs the DOF-map kernels (active nodes, global numbering, local-to-global maps;
+ * eq. residualvector) on `stream`, then derives the plan's lane grouping and packed
+ * layout on the host.  Synchronises `stream`.  Allocates device memory.
+ * On error *out is NULL. */
+lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, const uint8_t *keep_host,
+                           int32_t cap, hipStream_t stream, lat_plan **out);
+lat_status lat_plan_destroy(lat_plan *plan);
+/* info: HOST int64[LAT_INFO_N], filled with the sizes above. */
+lat_status lat_plan_info(const lat_plan *plan, int64_t *info);
+
+/* Writes {LAT_OK, INT32_MAX} to the device status word. */
+lat_status lat_status_reset(int32_t *dev_status, hipStream_t stream);
+
+/* DOF maps (eq. residualvector; A^s is the Boolean matrix of l2g).  Recomputes them from the
+ * plan's element masks with the DOF-map kernels.  Outputs (any may be NULL):
+ *   l2g      int32 [N_s][(n+1)^d]  global active-node id of local node a of cell s, or -1
+ *   n_active int32 [N_s]           number of active local nodes per cell
+ *   g2bg     int64 [n_global]      background-grid id of each global node (lexicographic over
+ *                                  the lattice's (C_x n+1) x ... node grid, x fastest)
+ *   perm     int32 [ld]            canonical cell of each plan lane, -1 for padding lanes */
+lat_status lat_dofmap(const lat_plan *plan, int32_t *l2g, int32_t *n_active, int64_t *g2bg, int32_t *perm,
+                      hipStream_t stream);
+
+/* Residual, energy and tangent of every cell at the global displacement
+ * u_global [n_global][d] (u^s = A^{sT} u), per-cell Lame parameters mu, lam [N_s] (canonical).
+ * Material-form neo-Hookean law W = mu/2 (I1-3) - mu ln J + lam/2 (ln J)^2 (plane strain in 2D).
+ * Outputs (any may be NULL):
+ *   f_int     CIL(d)   internal force f^{int,s} (eq. internalloadvec), cell-local, full rule
+ *   energy    [N_s]    stored energy per cell (canonical order), full rule
+ *   snap      CIL(E)   snapshot matrix T: the assembled cell tangent in stencil layout
+ *                      (eq. snapshots), quadrature `snap_rule`
+ *   plain_ops packed   every cell's full-rule tangent in stencil form (for lat_apply_plain)
+ * Errors J <= 0 / non-finite go to dev_status. */
+lat_status lat_residual_tangent(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
+                                lat_rule snap_rule, double *f_int, double *energy, double *snap, double *plain_ops,
+                                int32_t *dev_status, hipStream_t stream);
+
+/* Principal operators K^r = K^{s_r}(u^{s_r}) (eq. reducedbasis), full rule, in the principal
+ * stack layout, for the cells S[0..n_r) (device int32 [cap], canonical ids; n_r <= cap is a
+ * HOST value).  K = mu K_mu + lam K_lam at fixed u; K_mu / K_lam (may be NULL) receive those
+ * parts, for the adjoint.  Slots k >= n_r are zeroed. */
+lat_status lat_principal_ops(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
+                             const int32_t *S, int32_t n_r, double *K, double *K_mu, double *K_lam,
+                             int32_t *dev_status, hipStream_t stream);
+
+/* Greedy selection of principal cells (Algorithm 1) on the snapshot matrix `snap` (CIL(E),
+ * overwritten by the residuals Delta), tolerance tol > 0, at most cap <= plan cap selections.
+ * Ties of the arg-max go to the lowest canonical cell id; a zero snapshot is never selected.
+ * Dot products use a fixed order: chunks of 256 consecutive snapshot entries accumulated by
+ * fma from 0, chunk sums combined by a pairwise tree; so results are reproducible bit for bit.
+ * Outputs (device):
+ *   S        int32 [cap]      principal cells (canonical ids), -1 past n_r
+ *   n_r      int32 [1]        number selected
+ *   alpha    f64 [N_s][cap]   RB coefficients (least-squares coordinates, via R alpha = nu beta)
+ *   beta     f64 [N_s][cap]   greedy coordinates beta_i^s              (may be NULL)
+ *   nu       f64 [N_s]        snapshot 2-norms                           (may be NULL)
+ *   R        f64 [cap][cap]   R[j][k] = nu_{s_k} beta_j^{s_k}, j <= k
+ *   Z        f64 [cap][n_snap] orthonormal basis zeta_i                   (may be NULL)
+ *   achieved f64 [1]          max_s ||Delta^s||_inf at exit
+ * LAT_W_CAP goes to dev_status when the cap stops the loop above tol. */
+lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, int32_t cap, int32_t *S,
+                                int32_t *n_r, double *alpha, double *beta, double *nu, double *R, double *Z,
+                                double *achieved, int32_t *dev_status, hipStream_t stream);
+
+/* ROM apply (eq. romstiffnessmatrix): Y_i = M_i (sum_k alpha_ik K_k) M_i X_i for every cell at
+ * once, M_i the active-DOF mask of cell i.  K: principal stack (cap slots), n_r HOST value,
+ * alpha [N_s][cap] (canonical), X, Y packed with m right-hand sides.
+ * prec = LAT_F64 only in this version (others return LAT_E_ARG).  transpose != 0 applies the
+ * transposed operator (used by the adjoint). */
+lat_status lat_apply_combo(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
+                           const double *X, double *Y, int32_t m, lat_prec prec, int32_t transpose,
+                           hipStream_t stream);
+
+/* Plain per-cell apply Y_i = M_i K_i M_i X_i with every cell's own full-rule tangent
+ * (plain_ops from lat_residual_tangent).  X, Y packed. */
+lat_status lat_apply_plain(const lat_plan *plan, const double *plain_ops, const double *X, double *Y, int32_t m,
+                           hipStream_t stream);
+
+/* Adjoint of the ROM apply for a cotangent Ybar (packed), with S frozen:
+ *   Xbar      packed            Xbar_i = M_i Ktilde_i^T M_i Ybar_i               (may be NULL)
+ *   alpha_bar f64 [N_s][cap]    alpha_bar_ik = <M_i Ybar_i, K_k M_i X_i>          (may be NULL)
+ *   mu_bar, lam_bar f64 [N_s]   the part through the principal tangents:
+ *                               lam/mu_bar_{s_k} = sum_i alpha_ik <Ybar_i, K_{mu/lam,k} X_i>
+ *                               (written, not accumulated; zero for non-principal cells).
+ *                               Requires K_mu / K_lam from lat_principal_ops. */
+lat_status lat_apply_combo_adjoint(const lat_plan *plan, const double *K, const double *K_mu, const double *K_lam,
+                                   const int32_t *S, int32_t n_r, const double *alpha, const double *X,
+                                   const double *Ybar, int32_t m, double *Xbar, double *alpha_bar, double *mu_bar,
+                                   double *lam_bar, hipStream_t stream);
+
+/* Reverse mode of the RB coefficients alpha = (T_S^T T_S)^{-1} T_S^T t (least squares, S frozen),
+ * chained to the per-cell Lame parameters through the snapshots t_s = mu_s t^mu_s + lam_s t^lam_s.
+ * Uses the greedy's outputs: Delta (= snap after lat_select_principal), Z, R, nu, and the snapshot
+ * parts snap_mu, snap_lam (CIL(E), from lat_residual_tangent with mu = 1, lam = 0 and mu = 0,
+ * lam = 1).  alpha_bar [N_s][cap].  ACCUMULATES into mu_bar, lam_bar [N_s]. */
+lat_status lat_alpha_adjoint(const lat_plan *plan, const double *delta, const double *Z, const double *R,
+                             const double *nu, const int32_t *S, int32_t n_r, const double *alpha,
+                             const double *alpha_bar, const double *snap_mu, const double *snap_lam,
+                             double *mu_bar, double *lam_bar, hipStream_t stream);
+
+/* Reverse mode of the residual r = sum_s A^s f^{int,s}(u^s) for a cell-local cotangent
+ * w (CIL(d)):  ubar_local = K_s^T w_s (CIL(d), may be NULL), ubar_global = sum_s A^s ubar_local
+ * ([n_global][d], may be NULL), mu_bar_s = <w_s, f^mu_s>, lam_bar_s = <w_s, f^lam_s> ([N_s],
+ * written; may be NULL), with f = mu f^mu + lam f^lam at fixed u. */
+lat_status lat_residual_adjoint(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
+                                const double *w, double *ubar_local, double *ubar_global, double *mu_bar,
+                                double *lam_bar, int32_t *dev_status, hipStream_t stream);
+
+/* Assembly r = sum_s A^s v_s of a cell-local field v (CIL(k)) into out [n_global][k], summing the
+ * cells that share a node in ascending canonical order (deterministic). */
+lat_status lat_assemble(const lat_plan *plan, const double *local, int32_t k, double *out, hipStream_t stream);
+
+/* Gather w^s = A^{sT} w of a global field global [n_global][k] into CIL(k) (zero at nodes a cell
+ * does not own). */
+lat_status lat_gather(const lat_plan *plan, const double *global, int32_t k, double *local, hipStream_t stream);
+
+/* Layout conversions.  canon: [N_s][(n+1)^d][d][m] (cell-major); packed as above. */
+lat_status lat_pack(const lat_plan *plan, const double *canon, double *packed, int32_t m, hipStream_t stream);
+lat_status lat_unpack(const lat_plan *plan, const double *packed, double *canon, int32_t m, hipStream_t stream);
+/* CIL(k) <-> canonical [N_s][(n+1)^d][k]. */
+lat_status lat_cil_to_canon(const lat_plan *plan, const double *cil, int64_t k, double *canon, hipStream_t stream);
+lat_status lat_canon_to_cil(const lat_plan *plan, const double *canon, int64_t k, double *cil, hipStream_t stream);
+/* Packed plain-ops -> canonical stencils [N_s][n_snap] (zero outside each group's union). */
+lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, double *canon, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAT_H */

@@ -1,0 +1,268 @@
+"""ctypes binding of liblat.so (the C ABI declared in include/lat.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP stream, every
+step of the computation runs in the library's kernels.  There is no fallback: if the
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblat.so")
+
+LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP = range(8)
+RULE_FULL, RULE_REDUCED = 0, 1
+F64, F32, BF16 = 0, 1, 2
+INFO_KEYS = ["dim", "nel", "ncells", "nloc", "nelem", "E", "nsnap", "ld", "ngroups", "npacked", "nglobal", "cap"]
+
+
+class LatError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = int(code)
+        super().__init__(f"liblat {where}: {_lib().lat_status_string(int(code)).decode()} (status {int(code)})")
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              f"python -m paper_2603_10741_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "lat_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "lat_plan_create": (ctypes.c_int, [I32, P, I32, P, I32, P, P]),
+            "lat_plan_destroy": (ctypes.c_int, [P]),
+            "lat_plan_info": (ctypes.c_int, [P, P]),
+            "lat_status_reset": (ctypes.c_int, [P, P]),
+            "lat_dofmap": (ctypes.c_int, [P, P, P, P, P, P]),
+            "lat_residual_tangent": (ctypes.c_int, [P, P, P, P, ctypes.c_int, P, P, P, P, P, P]),
+            "lat_principal_ops": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P]),
+            "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P]),
+            "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, I32, P]),
+            "lat_apply_plain": (ctypes.c_int, [P, P, P, P, I32, P]),
+            "lat_apply_combo_adjoint": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, I32, P, P, P, P, P]),
+            "lat_alpha_adjoint": (ctypes.c_int, [P, P, P, P, P, P, I32, P, P, P, P, P, P, P]),
+            "lat_residual_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P]),
+            "lat_assemble": (ctypes.c_int, [P, P, I32, P, P]),
+            "lat_gather": (ctypes.c_int, [P, P, I32, P, P]),
+            "lat_pack": (ctypes.c_int, [P, P, P, I32, P]),
+            "lat_unpack": (ctypes.c_int, [P, P, P, I32, P]),
+            "lat_cil_to_canon": (ctypes.c_int, [P, P, I64, P, P]),
+            "lat_canon_to_cil": (ctypes.c_int, [P, P, I64, P, P]),
+            "lat_plain_ops_to_canon": (ctypes.c_int, [P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    """Names of the C entry points this binding uses (all declared in include/lat.h)."""
+    return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_status_reset",
+            "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_apply_combo",
+            "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
+            "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
+            "lat_plain_ops_to_canon"]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ok(st, where):
+    if st != LAT_OK:
+        raise LatError(st, where)
+
+
+class Plan:
+    """A lattice plan: DOF maps, lane grouping, packed layouts and workspace on one GPU."""
+
+    def __init__(self, dim, ncell, nel, keep, cap=64, device="cuda"):
+        self.device = torch.device(device)
+        keep = np.ascontiguousarray(keep, dtype=np.uint8)
+        nc = (ctypes.c_int32 * 3)(*(list(ncell) + [1] * (3 - len(ncell))))
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _ok(_lib().lat_plan_create(dim, nc, nel, keep.ctypes.data_as(ctypes.c_void_p), cap, _stream(),
+                                       ctypes.byref(out)), "plan_create")
+        self._p = out
+        info = (ctypes.c_int64 * len(INFO_KEYS))()
+        _ok(_lib().lat_plan_info(self._p, info), "plan_info")
+        self.info = {k: int(info[i]) for i, k in enumerate(INFO_KEYS)}
+        for k, v in self.info.items():
+            setattr(self, k, v)
+        self.status_word = torch.zeros(2, dtype=torch.int32, device=self.device)
+        self.reset_status()
+
+    def __del__(self):
+        try:
+            if getattr(self, "_p", None):
+                _lib().lat_plan_destroy(self._p)
+                self._p = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ helpers
+    def _f64(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def reset_status(self):
+        _ok(_lib().lat_status_reset(_ptr(self.status_word), _stream()), "status_reset")
+
+    def check_status(self, allow_cap=True):
+        torch.cuda.current_stream().synchronize()
+        code, cell = (int(x) for x in self.status_word.cpu())
+        if code != LAT_OK and not (allow_cap and code == LAT_W_CAP):
+            raise LatError(code, f"device status (first cell {cell})")
+        return code, cell
+
+    # ------------------------------------------------------------------ a1
+    def dofmap(self):
+        l2g = torch.empty(self.ncells, self.nloc, dtype=torch.int32, device=self.device)
+        nact = torch.empty(self.ncells, dtype=torch.int32, device=self.device)
+        g2bg = torch.empty(max(self.nglobal, 1), dtype=torch.int64, device=self.device)
+        perm = torch.empty(self.ld, dtype=torch.int32, device=self.device)
+        _ok(_lib().lat_dofmap(self._p, _ptr(l2g), _ptr(nact), _ptr(g2bg), _ptr(perm), _stream()), "dofmap")
+        return l2g, nact, g2bg[:self.nglobal], perm
+
+    # ------------------------------------------------------------------ a2-a4
+    def residual_tangent(self, u_global, mu, lam, snap_rule=RULE_FULL, f=True, energy=True, snap=True,
+                         plain=False, out=None):
+        out = dict(out or {})
+        if f and "f" not in out:
+            out["f"] = self._f64(self.nloc * self.dim * self.ld)
+        if energy and "energy" not in out:
+            out["energy"] = self._f64(self.ncells)
+        if snap and "snap" not in out:
+            out["snap"] = self._f64(self.nsnap * self.ld)
+        if plain and "plain" not in out:
+            out["plain"] = self._f64(self.npacked * self.E * 64)
+        _ok(_lib().lat_residual_tangent(self._p, _ptr(u_global), _ptr(mu), _ptr(lam), snap_rule, _ptr(out.get("f")),
+                                        _ptr(out.get("energy")), _ptr(out.get("snap")), _ptr(out.get("plain")),
+                                        _ptr(self.status_word), _stream()), "residual_tangent")
+        return out
+
+    def principal_ops(self, u_global, mu, lam, S, n_r, parts=False, out=None):
+        out = dict(out or {})
+        for key in (["K", "K_mu", "K_lam"] if parts else ["K"]):
+            if key not in out:
+                out[key] = self._f64(self.nloc * self.E * self.cap)
+        _ok(_lib().lat_principal_ops(self._p, _ptr(u_global), _ptr(mu), _ptr(lam), _ptr(S), int(n_r), _ptr(out["K"]),
+                                     _ptr(out.get("K_mu")), _ptr(out.get("K_lam")), _ptr(self.status_word),
+                                     _stream()), "principal_ops")
+        return out
+
+    # ------------------------------------------------------------------ a5-a6
+    def select_principal(self, snap, tol, cap=None, keep_Z=True, out=None):
+        cap = self.cap if cap is None else cap
+        out = dict(out or {})
+        dev = self.device
+        if "S" not in out:
+            out.update(S=torch.empty(self.cap, dtype=torch.int32, device=dev),
+                       n_r=torch.empty(1, dtype=torch.int32, device=dev),
+                       alpha=self._f64(self.ncells, self.cap), beta=self._f64(self.ncells, self.cap),
+                       nu=self._f64(self.ncells), R=self._f64(self.cap, self.cap), achieved=self._f64(1))
+            if keep_Z:
+                out["Z"] = self._f64(self.cap, self.nsnap)
+        _ok(_lib().lat_select_principal(self._p, _ptr(snap), float(tol), int(cap), _ptr(out["S"]), _ptr(out["n_r"]),
+                                        _ptr(out["alpha"]), _ptr(out.get("beta")), _ptr(out.get("nu")),
+                                        _ptr(out["R"]), _ptr(out.get("Z")), _ptr(out["achieved"]),
+                                        _ptr(self.status_word), _stream()), "select_principal")
+        return out
+
+    # ------------------------------------------------------------------ a7-a8
+    def packed_size(self, m):
+        return self.npacked * self.dim * m * 64
+
+    def apply_combo(self, K, n_r, alpha, X, m, transpose=False, prec=F64, out=None):
+        Y = self._f64(self.packed_size(m)) if out is None else out
+        _ok(_lib().lat_apply_combo(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(X), _ptr(Y), int(m), prec,
+                                   int(bool(transpose)), _stream()), "apply_combo")
+        return Y
+
+    def apply_plain(self, ops, X, m, out=None):
+        Y = self._f64(self.packed_size(m)) if out is None else out
+        _ok(_lib().lat_apply_plain(self._p, _ptr(ops), _ptr(X), _ptr(Y), int(m), _stream()), "apply_plain")
+        return Y
+
+    # ------------------------------------------------------------------ a9
+    def apply_combo_adjoint(self, K, n_r, alpha, X, Ybar, m, K_mu=None, K_lam=None, S=None, want_xbar=True,
+                            want_alpha_bar=True):
+        Xbar = self._f64(self.packed_size(m)) if want_xbar else None
+        abar = self._f64(self.ncells, self.cap) if want_alpha_bar else None
+        mub = self._f64(self.ncells) if K_mu is not None else None
+        lamb = self._f64(self.ncells) if K_lam is not None else None
+        _ok(_lib().lat_apply_combo_adjoint(self._p, _ptr(K), _ptr(K_mu), _ptr(K_lam), _ptr(S), int(n_r), _ptr(alpha),
+                                           _ptr(X), _ptr(Ybar), int(m), _ptr(Xbar), _ptr(abar), _ptr(mub), _ptr(lamb),
+                                           _stream()), "apply_combo_adjoint")
+        return {"Xbar": Xbar, "alpha_bar": abar, "mu_bar": mub, "lam_bar": lamb}
+
+    def alpha_adjoint(self, delta, Z, R, nu, S, n_r, alpha, alpha_bar, snap_mu, snap_lam, mu_bar, lam_bar):
+        _ok(_lib().lat_alpha_adjoint(self._p, _ptr(delta), _ptr(Z), _ptr(R), _ptr(nu), _ptr(S), int(n_r), _ptr(alpha),
+                                     _ptr(alpha_bar), _ptr(snap_mu), _ptr(snap_lam), _ptr(mu_bar), _ptr(lam_bar),
+                                     _stream()), "alpha_adjoint")
+
+    def residual_adjoint(self, u_global, mu, lam, w_cil, local=True, glob=True, lame=True):
+        ub = self._f64(self.nloc * self.dim * self.ld) if (local or glob) else None
+        ug = self._f64(max(self.nglobal, 1) * self.dim) if glob else None
+        mub = self._f64(self.ncells) if lame else None
+        lamb = self._f64(self.ncells) if lame else None
+        _ok(_lib().lat_residual_adjoint(self._p, _ptr(u_global), _ptr(mu), _ptr(lam), _ptr(w_cil), _ptr(ub), _ptr(ug),
+                                        _ptr(mub), _ptr(lamb), _ptr(self.status_word), _stream()), "residual_adjoint")
+        return {"ubar_local": ub, "ubar_global": ug, "mu_bar": mub, "lam_bar": lamb}
+
+    # ------------------------------------------------------------------ layouts
+    def assemble(self, local_cil, k):
+        out = self._f64(max(self.nglobal, 1) * k)
+        _ok(_lib().lat_assemble(self._p, _ptr(local_cil), int(k), _ptr(out), _stream()), "assemble")
+        return out
+
+    def gather(self, glob, k):
+        out = self._f64(self.nloc * k * self.ld)
+        _ok(_lib().lat_gather(self._p, _ptr(glob), int(k), _ptr(out), _stream()), "gather")
+        return out
+
+    def pack(self, canon, m):
+        out = self._f64(self.packed_size(m))
+        _ok(_lib().lat_pack(self._p, _ptr(canon), _ptr(out), int(m), _stream()), "pack")
+        return out
+
+    def unpack(self, packed, m):
+        out = self._f64(self.ncells, self.nloc, self.dim, m)
+        _ok(_lib().lat_unpack(self._p, _ptr(packed), _ptr(out), int(m), _stream()), "unpack")
+        return out
+
+    def cil_to_canon(self, cil, k):
+        out = torch.zeros(self.ncells, self.nloc, k, dtype=torch.float64, device=self.device)
+        _ok(_lib().lat_cil_to_canon(self._p, _ptr(cil), int(k), _ptr(out), _stream()), "cil_to_canon")
+        return out
+
+    def canon_to_cil(self, canon, k):
+        out = self._f64(self.nloc * k * self.ld)
+        _ok(_lib().lat_canon_to_cil(self._p, _ptr(canon), int(k), _ptr(out), _stream()), "canon_to_cil")
+        return out
+
+    def plain_ops_to_canon(self, ops):
+        out = self._f64(self.ncells, self.nsnap)
+        _ok(_lib().lat_plain_ops_to_canon(self._p, _ptr(ops), _ptr(out), _stream()), "plain_ops_to_canon")
+        return out

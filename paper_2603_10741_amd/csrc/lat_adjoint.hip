@@ -1,0 +1,181 @@
+// Reverse mode of the RB coefficients (least-squares formula of Sec. 3.2.2) with the principal
+// set frozen, chained to the per-cell Lame parameters through the snapshots
+// t_s = mu_s t^mu_s + lam_s t^lam_s (the tangent is linear in (mu, lam) at fixed u).
+//
+// With T_S = Z R (the greedy's certified decomposition, Algorithm 1), alpha_i = R^{-1} nu_i beta_i
+// and the least-squares residual rho_i = t_i - T_S alpha_i = nu_i Delta_i:
+//   q_i = R^{-T} abar_i,   v_i = R^{-1} q_i
+//   tbar_i  = T_S v_i = Z q_i                          (cotangent of t_i as data)
+//   TbarS   = sum_i ( nu_i Delta_i v_i^T - Z q_i alpha_i^T )  (cotangent of the basis columns)
+//   mubar_i += <tbar_i, t^mu_i> = q_i . (Z^T t^mu_i)
+//   mubar_{s_k} += sum_i nu_i v_ik <Delta_i, t^mu_{s_k}> - alpha_ik q_i . (Z^T t^mu_{s_k})
+// The contractions over the snapshot rows (Z^T T^mu, Delta^T T^mu_S, ...) stream the per-lane
+// matrix once with a wave-uniform second operand held as [row][cap].
+#include "lat_internal.h"
+
+namespace {
+
+// q_i, v_i per lane (plan order), written to qv[0][p][cap], qv[1][p][cap]
+__global__ void k_aa_solve(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
+                           const double *__restrict__ R, const double *__restrict__ abar,
+                           double *__restrict__ qv)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ld) return;
+    const int c = perm[p];
+    double q[LAT_MAX_CAP], v[LAT_MAX_CAP];
+    for (int k = 0; k < LAT_MAX_CAP; ++k) { q[k] = 0.0; v[k] = 0.0; }
+    if (c >= 0) {
+        for (int k = 0; k < n_r; ++k) {                 // R^T q = abar (forward)
+            double acc = abar[(int64_t)c * cap + k];
+            for (int l = 0; l < k; ++l) acc = fma(-R[l * cap + k], q[l], acc);
+            q[k] = acc / R[k * cap + k];
+        }
+        for (int k = n_r - 1; k >= 0; --k) {            // R v = q (backward)
+            double acc = q[k];
+            for (int l = k + 1; l < n_r; ++l) acc = fma(-R[k * cap + l], v[l], acc);
+            v[k] = acc / R[k * cap + k];
+        }
+    }
+    for (int k = 0; k < cap; ++k) {
+        qv[p * cap + k] = q[k];
+        qv[(ld + p) * cap + k] = v[k];
+    }
+}
+
+// U[j][k] = Z[k][j] (k < n_r), 0 beyond
+__global__ void k_aa_zt(int64_t nsnap, int cap, int n_r, const double *__restrict__ Z, double *__restrict__ U)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nsnap) return;
+    for (int k = 0; k < cap; ++k) U[j * cap + k] = k < n_r ? Z[(int64_t)k * nsnap + j] : 0.0;
+}
+
+// U[j][k] = V[j][lane(S[k])] (k < n_r), 0 beyond
+__global__ void k_aa_cols(int64_t nsnap, int64_t ld, int cap, int n_r, const int32_t *__restrict__ S,
+                          const int32_t *__restrict__ lane, const double *__restrict__ V, double *__restrict__ U)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nsnap) return;
+    for (int k = 0; k < cap; ++k) U[j * cap + k] = k < n_r ? V[j * ld + lane[S[k]]] : 0.0;
+}
+
+// part[chunk][p][k] = sum_{j in chunk} V[j][p] U[j][k]
+template <int NR>
+__global__ __launch_bounds__(256) void k_aa_contract(int64_t nsnap, int64_t ld, int cap, int rows_per_chunk,
+                                                     const double *__restrict__ V, const double *__restrict__ U,
+                                                     double *__restrict__ part)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (p >= ld) return;
+    const int64_t j0 = b * rows_per_chunk, j1 = j0 + rows_per_chunk < nsnap ? j0 + rows_per_chunk : nsnap;
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double x = V[j * ld + p];
+        const double *u = U + j * cap;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = fma(x, u[k], acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (k < cap) part[(b * ld + p) * cap + k] = acc[k];
+    for (int k = NR; k < cap; ++k) part[(b * ld + p) * cap + k] = 0.0;
+}
+
+// per-cell term: bar_c += q_c . A[p_c]   (A = Z^T t^x, plan order [ld][cap])
+__global__ void k_aa_cellterm(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
+                              const double *__restrict__ qv, const double *__restrict__ Am,
+                              const double *__restrict__ Al, double *__restrict__ mbar, double *__restrict__ lbar)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ld) return;
+    const int c = perm[p];
+    if (c < 0) return;
+    double sm = 0.0, sl = 0.0;
+    for (int k = 0; k < n_r; ++k) {
+        sm = fma(qv[p * cap + k], Am[p * cap + k], sm);
+        sl = fma(qv[p * cap + k], Al[p * cap + k], sl);
+    }
+    if (mbar) mbar[c] += sm;
+    if (lbar) lbar[c] += sl;
+}
+
+// principal term for slot k (one thread per slot), ascending canonical order over the cells
+__global__ void k_aa_principal(int64_t ncells, int64_t ld, int cap, int n_r, const int32_t *__restrict__ S,
+                               const int32_t *__restrict__ lane, const double *__restrict__ nu,
+                               const double *__restrict__ alpha, const double *__restrict__ qv,
+                               const double *__restrict__ Am, const double *__restrict__ Al,
+                               const double *__restrict__ Bm, const double *__restrict__ Bl,
+                               double *__restrict__ mbar, double *__restrict__ lbar)
+{
+    const int k = threadIdx.x;
+    if (k >= n_r) return;
+    const int sk = S[k];
+    const int64_t pk = lane[sk];
+    double sm = 0.0, sl = 0.0;
+    for (int64_t i = 0; i < ncells; ++i) {
+        const int64_t pi = lane[i];
+        const double vik = qv[(ld + pi) * cap + k];
+        double qAm = 0.0, qAl = 0.0;
+        for (int l = 0; l < n_r; ++l) {
+            qAm = fma(qv[pi * cap + l], Am[pk * cap + l], qAm);
+            qAl = fma(qv[pi * cap + l], Al[pk * cap + l], qAl);
+        }
+        const double aik = alpha[i * cap + k];
+        sm += nu[i] * vik * Bm[pi * cap + k] - aik * qAm;
+        sl += nu[i] * vik * Bl[pi * cap + k] - aik * qAl;
+    }
+    if (mbar) mbar[sk] += sm;
+    if (lbar) lbar[sk] += sl;
+}
+
+lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
+{
+    const int rows = 4096;
+    dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->aa_nchunk);
+    if (n_r <= 8) hipLaunchKernelGGL(k_aa_contract<8>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+    else if (n_r <= 16) hipLaunchKernelGGL(k_aa_contract<16>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+    else if (n_r <= 32) hipLaunchKernelGGL(k_aa_contract<32>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+    else hipLaunchKernelGGL(k_aa_contract<64>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+    LAT_LAUNCH_CHECK();
+    return lat_tree_reduce(P->aa_part, P->aa_nchunk, P->ld * P->cap, 0, out, P->g_t1, P->g_t2, s);
+}
+
+}  // namespace
+
+extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, const double *Z, const double *R,
+                                        const double *nu, const int32_t *S, int32_t n_r, const double *alpha,
+                                        const double *alpha_bar, const double *snap_mu, const double *snap_lam,
+                                        double *mu_bar, double *lam_bar, hipStream_t stream)
+{
+    if (!P || !delta || !Z || !R || !nu || !S || !alpha || !alpha_bar || !snap_mu || !snap_lam) return LAT_E_ARG;
+    if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
+    if (n_r == 0) return LAT_OK;
+    const int64_t ld = P->ld, cap = P->cap;
+    const dim3 lg((unsigned)lat_cdiv(ld, 256)), sg((unsigned)lat_cdiv(P->nsnap, 256));
+    double *Am = P->aa_A, *Al = P->aa_A + ld * cap, *Bm = P->aa_B, *Bl = P->aa_B + ld * cap;
+    hipLaunchKernelGGL(k_aa_solve, lg, dim3(256), 0, stream, ld, (int)cap, n_r, P->perm, R, alpha_bar, P->aa_q);
+    LAT_LAUNCH_CHECK();
+    lat_status st;
+    // A = Z^T T^mu, Z^T T^lam
+    hipLaunchKernelGGL(k_aa_zt, sg, dim3(256), 0, stream, P->nsnap, (int)cap, n_r, Z, P->aa_gath);
+    LAT_LAUNCH_CHECK();
+    if ((st = contract(P, n_r, snap_mu, P->aa_gath, Am, stream)) != LAT_OK) return st;
+    if ((st = contract(P, n_r, snap_lam, P->aa_gath, Al, stream)) != LAT_OK) return st;
+    // B = Delta^T T^mu_S, Delta^T T^lam_S
+    hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_mu, P->aa_gath);
+    LAT_LAUNCH_CHECK();
+    if ((st = contract(P, n_r, delta, P->aa_gath, Bm, stream)) != LAT_OK) return st;
+    hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_lam, P->aa_gath);
+    LAT_LAUNCH_CHECK();
+    if ((st = contract(P, n_r, delta, P->aa_gath, Bl, stream)) != LAT_OK) return st;
+    hipLaunchKernelGGL(k_aa_cellterm, lg, dim3(256), 0, stream, ld, (int)cap, n_r, P->perm, P->aa_q, Am, Al, mu_bar,
+                       lam_bar);
+    hipLaunchKernelGGL(k_aa_principal, dim3(1), dim3(64), 0, stream, P->ncells, ld, (int)cap, n_r, S, P->lane, nu, alpha,
+                       P->aa_q, Am, Al, Bm, Bl, mu_bar, lam_bar);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}

@@ -1,0 +1,594 @@
+// Cell operators of the compressible neo-Hookean law on voxelised Q1 cells:
+// internal force (eq. internalloadvec), stored energy, tangent (Sec. 3.1.4 and
+// eq. fullquadraturerule) in stencil layout, snapshots (eq. snapshots), principal
+// operators (eq. reducedbasis) and the reverse mode of the residual.
+//
+// Work decomposition: one thread per (cell lane, local node a[, tangent row i in 3D]).
+// Lanes are cells (cell-interleaved layouts), so every wave works on the same node of 64
+// cells: element masks, displacements and outputs are read/written with unit stride.
+// The thread visits the (up to) 2^d elements around its node and, at each Gauss point,
+// builds F, J, ln J and p_c = F^{-T} g_c for the element's corners; the tangent row of
+// node a then follows from the identity (material form of the paper's D tensor)
+//   K[(a,i),(c,j)] += w [ mu d_ij (g_a . g_c) + (mu - lam ln J) (p_a)_j (p_c)_i + lam (p_a)_i (p_c)_j ].
+// Every output entry is written by exactly one thread: no atomics, bitwise reproducible.
+#include "lat_internal.h"
+
+namespace {
+
+template <int DIM>
+struct Geo {
+    static constexpr int NC = 1 << DIM;          // element corners
+    static constexpr int NO = DIM == 2 ? 9 : 27; // stencil offsets
+    static constexpr int E = NO * DIM * DIM;     // stencil entries per node
+};
+
+// Quadrature point coordinates on the element reference square/cube [0,1]^d.
+template <int RULE>
+__device__ __forceinline__ double gauss_x(int k)
+{
+    if (RULE == LAT_RULE_REDUCED) return 0.5;
+    return k == 0 ? 0.5 - 0.5 / sqrt(3.0) : 0.5 + 0.5 / sqrt(3.0);
+}
+
+// d N_c / d xi_J at quadrature point q (tensor index), times 1/h.
+template <int DIM, int RULE>
+__device__ __forceinline__ double shape_grad(int q, int c, int J, double invh)
+{
+    constexpr int NP = RULE == LAT_RULE_REDUCED ? 1 : 2;
+    double v = invh;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        int kq = (ax == 0 ? q : (ax == 1 ? q / NP : q / (NP * NP))) % NP;
+        double x = gauss_x<RULE>(kq);
+        int bit = (c >> ax) & 1;
+        if (ax == J) v *= bit ? 1.0 : -1.0;
+        else v *= bit ? x : 1.0 - x;
+    }
+    return v;
+}
+
+struct CellArgs {
+    int nel, nloc;
+    int64_t ld;
+    const double *u_cil;        // [nloc][d][ld]
+    const uint8_t *keep_il;     // [nelem][ld]
+    const int32_t *perm;        // [ld]
+    const int32_t *lane;        // [N_s]
+    const double *mu, *lam;     // [N_s] canonical (material mode 0)
+    int matmode;                // 0: arrays, 1: (1,0), 2: (0,1)
+    // all-cells outputs
+    double *f;                  // CIL(d)
+    double *epart;              // [nloc][ld]
+    double *T;                  // CIL(E)
+    double *ops;                // packed plain ops
+    const int32_t *uidx, *goff;
+    // principal mode
+    const int32_t *S;
+    int n_r, cap;
+    double *Kst;                // [(a*E+e)*cap + k]
+    int32_t *st;
+};
+
+template <int DIM, int RULE, bool PRINCIPAL>
+__global__ __launch_bounds__(256) void k_cell(CellArgs A)
+{
+    using G = Geo<DIM>;
+    constexpr int NQ = RULE == LAT_RULE_REDUCED ? 1 : (1 << DIM);
+    constexpr int NROW = DIM == 2 ? 2 : 1;       // tangent rows per thread
+    const int nel = A.nel, nn = nel + 1;
+    const int64_t ld = A.ld;
+    const int a = blockIdx.y;
+    const int row0 = DIM == 2 ? 0 : (int)blockIdx.z;
+    int64_t p;
+    int cell, slot = 0;
+    if (PRINCIPAL) {
+        slot = threadIdx.x;
+        if (slot >= A.cap) return;
+        cell = slot < A.n_r ? A.S[slot] : -1;
+        p = cell >= 0 ? A.lane[cell] : 0;
+    } else {
+        p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (p >= ld) return;
+        cell = A.perm[p];
+    }
+    const double h = 1.0 / nel, invh = (double)nel;
+    double hd = h;
+#pragma unroll
+    for (int ax = 1; ax < DIM; ++ax) hd *= h;
+    const double wq = (RULE == LAT_RULE_REDUCED ? 1.0 : (DIM == 2 ? 0.25 : 0.125)) * hd;
+    double mu = 0.0, lam = 0.0;
+    if (cell >= 0) {
+        mu = A.matmode == 0 ? A.mu[cell] : (A.matmode == 1 ? 1.0 : 0.0);
+        lam = A.matmode == 0 ? A.lam[cell] : (A.matmode == 2 ? 1.0 : 0.0);
+    }
+    const int ia[3] = {a % nn, (a / nn) % nn, DIM == 3 ? a / (nn * nn) : 0};
+
+    double acc[G::NO][NROW][DIM];
+    double facc[NROW];
+    double en = 0.0;
+#pragma unroll
+    for (int o = 0; o < G::NO; ++o)
+#pragma unroll
+        for (int r = 0; r < NROW; ++r)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) acc[o][r][j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NROW; ++r) facc[r] = 0.0;
+
+    if (cell >= 0) {
+#pragma unroll
+        for (int k = 0; k < G::NC; ++k) {          // node a is corner k of this element
+            int ie[3] = {0, 0, 0};
+            bool ok = true;
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                ie[ax] = ia[ax] - ((k >> ax) & 1);
+                ok = ok && ie[ax] >= 0 && ie[ax] < nel;
+            }
+            if (!ok) continue;
+            const int e = ie[0] + nel * (ie[1] + nel * ie[2]);
+            if (!A.keep_il[(int64_t)e * ld + p]) continue;
+            double ue[G::NC][DIM];
+#pragma unroll
+            for (int c = 0; c < G::NC; ++c) {
+                int b = (ie[0] + (c & 1)) + nn * ((ie[1] + ((c >> 1) & 1)) + nn * (DIM == 3 ? ie[2] + ((c >> 2) & 1) : 0));
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) ue[c][i] = A.u_cil[((int64_t)b * DIM + i) * ld + p];
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double F[DIM][DIM];
+#pragma unroll
+                for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) F[i][J] = (i == J) ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = 0; c < G::NC; ++c)
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) {
+                        const double g = shape_grad<DIM, RULE>(q, c, J, invh);
+#pragma unroll
+                        for (int i = 0; i < DIM; ++i) F[i][J] += ue[c][i] * g;
+                    }
+                double Jd, H[DIM][DIM];                // H = F^{-T}
+                if (DIM == 2) {
+                    Jd = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                    const double r = 1.0 / Jd;
+                    H[0][0] = F[1][1] * r; H[0][1] = -F[1][0] * r;
+                    H[1][0] = -F[0][1] * r; H[1][1] = F[0][0] * r;
+                } else {
+                    double C[3][3];                     // cofactors
+                    C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+                    C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+                    C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+                    C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+                    C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+                    C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+                    C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+                    C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+                    C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                    Jd = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
+                    const double r = 1.0 / Jd;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int J = 0; J < 3; ++J) H[i][J] = C[i][J] * r;
+                }
+                double lnJ = 0.0;
+                if (Jd > 0.0 && isfinite(Jd)) {
+                    lnJ = log(Jd);
+                } else {
+                    lat_flag(A.st, isfinite(Jd) ? LAT_E_INVERTED : LAT_E_NONFINITE, cell);
+                }
+                double gk[DIM], pk[DIM];
+#pragma unroll
+                for (int J = 0; J < DIM; ++J) gk[J] = shape_grad<DIM, RULE>(q, k, J, invh);
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) s += H[i][J] * gk[J];
+                    pk[i] = s;
+                }
+                // internal force row(s): P g_a = mu (F g_a - p_a) + lam ln J p_a
+#pragma unroll
+                for (int r = 0; r < NROW; ++r) {
+                    const int i = DIM == 2 ? r : row0;
+                    double Fg = 0.0;
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) Fg += F[i][J] * gk[J];
+                    facc[r] += wq * (mu * (Fg - pk[i]) + lam * lnJ * pk[i]);
+                }
+                if (k == 0) {                           // element energy, owned by its corner 0
+                    double I1 = DIM == 2 ? 1.0 : 0.0;
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                        for (int J = 0; J < DIM; ++J) I1 += F[i][J] * F[i][J];
+                    en += wq * (0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+                }
+                const double c2 = mu - lam * lnJ;
+#pragma unroll
+                for (int c = 0; c < G::NC; ++c) {
+                    int oi = 0, sc = 1;
+#pragma unroll
+                    for (int ax = 0; ax < DIM; ++ax) { oi += (((c >> ax) & 1) - ((k >> ax) & 1) + 1) * sc; sc *= 3; }
+                    double gc[DIM], pc[DIM], gkgc = 0.0;
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) { gc[J] = shape_grad<DIM, RULE>(q, c, J, invh); gkgc += gk[J] * gc[J]; }
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int J = 0; J < DIM; ++J) s += H[i][J] * gc[J];
+                        pc[i] = s;
+                    }
+#pragma unroll
+                    for (int r = 0; r < NROW; ++r) {
+                        const int i = DIM == 2 ? r : row0;
+#pragma unroll
+                        for (int j = 0; j < DIM; ++j) {
+                            double v = c2 * pk[j] * pc[i] + lam * pk[i] * pc[j];
+                            if (i == j) v += mu * gkgc;
+                            acc[oi][r][j] += wq * v;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // ---- outputs
+    constexpr int E = G::E;
+    if (PRINCIPAL) {
+#pragma unroll
+        for (int o = 0; o < G::NO; ++o)
+#pragma unroll
+            for (int r = 0; r < NROW; ++r)
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) {
+                    const int i = DIM == 2 ? r : row0;
+                    const int ent = (o * DIM + i) * DIM + j;
+                    A.Kst[((int64_t)a * E + ent) * A.cap + slot] = acc[o][r][j];
+                }
+        return;
+    }
+    if (A.f) {
+#pragma unroll
+        for (int r = 0; r < NROW; ++r) {
+            const int i = DIM == 2 ? r : row0;
+            A.f[((int64_t)a * DIM + i) * ld + p] = facc[r];
+        }
+    }
+    if (A.epart && row0 == 0) A.epart[(int64_t)a * ld + p] = en;
+    if (A.T) {
+#pragma unroll
+        for (int o = 0; o < G::NO; ++o)
+#pragma unroll
+            for (int r = 0; r < NROW; ++r)
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) {
+                    const int i = DIM == 2 ? r : row0;
+                    const int ent = (o * DIM + i) * DIM + j;
+                    A.T[((int64_t)a * E + ent) * ld + p] = acc[o][r][j];
+                }
+    }
+    if (A.ops) {
+        const int g = (int)(p / LAT_WAVE), l = (int)(p % LAT_WAVE);
+        const int qi = A.uidx[(int64_t)g * A.nloc + a];
+        if (qi >= 0) {
+            const int64_t q = A.goff[g] + qi;
+#pragma unroll
+            for (int o = 0; o < G::NO; ++o)
+#pragma unroll
+                for (int r = 0; r < NROW; ++r)
+#pragma unroll
+                    for (int j = 0; j < DIM; ++j) {
+                        const int i = DIM == 2 ? r : row0;
+                        const int ent = (o * DIM + i) * DIM + j;
+                        A.ops[(q * E + ent) * LAT_WAVE + l] = acc[o][r][j];
+                    }
+        }
+    }
+}
+
+// u^s = A^{sT} u gathered into the cell-interleaved layout (zero at nodes a cell does not own).
+__global__ void k_gather_u(int dim, int nloc, int64_t ld, const int32_t *__restrict__ l2g_il,
+                           const int32_t *__restrict__ perm, const double *__restrict__ ug,
+                           double *__restrict__ u_cil, int32_t *st)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int a = blockIdx.y;
+    if (p >= ld) return;
+    int g = l2g_il[(int64_t)a * ld + p];
+    for (int i = 0; i < dim; ++i) {
+        double v = g >= 0 ? ug[(int64_t)g * dim + i] : 0.0;
+        if (!isfinite(v)) { lat_flag(st, LAT_E_NONFINITE, perm[p]); v = 0.0; }
+        u_cil[((int64_t)a * dim + i) * ld + p] = v;
+    }
+}
+
+__global__ void k_scatter_lanes(int64_t ld, const int32_t *__restrict__ perm, const double *__restrict__ v,
+                                double *__restrict__ out)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ld) return;
+    int c = perm[p];
+    if (c >= 0) out[c] = v[p];
+}
+
+// Reverse mode of the residual at one node: (K^T w)_a = sum_e sum_q w_q dP(Gw) g_a with
+// dP(G) = mu G + (mu - lam ln J) H G^T H + lam tr(G F^{-1}) H  (A's major symmetry), and the
+// Lame-parameter parts <w_a, f^mu_a>, <w_a, f^lam_a>.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_residual_adjoint(int nel, int64_t ld, const double *__restrict__ u_cil,
+                                                          const double *__restrict__ w_cil,
+                                                          const uint8_t *__restrict__ keep_il,
+                                                          const int32_t *__restrict__ perm,
+                                                          const double *__restrict__ mu_a,
+                                                          const double *__restrict__ lam_a,
+                                                          double *__restrict__ ubar, double *__restrict__ pmu,
+                                                          double *__restrict__ plam, int32_t *st)
+{
+    using G = Geo<DIM>;
+    constexpr int NQ = 1 << DIM;
+    const int nn = nel + 1;
+    const int a = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ld) return;
+    const int cell = perm[p];
+    const double h = 1.0 / nel, invh = (double)nel;
+    double hd = h;
+#pragma unroll
+    for (int ax = 1; ax < DIM; ++ax) hd *= h;
+    const double wq = (DIM == 2 ? 0.25 : 0.125) * hd;
+    const int ia[3] = {a % nn, (a / nn) % nn, DIM == 3 ? a / (nn * nn) : 0};
+    double ub[DIM], fm[DIM], fl[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) { ub[i] = 0.0; fm[i] = 0.0; fl[i] = 0.0; }
+    double mu = 0.0, lam = 0.0;
+    if (cell >= 0) { mu = mu_a[cell]; lam = lam_a[cell]; }
+    if (cell >= 0) {
+#pragma unroll
+        for (int k = 0; k < G::NC; ++k) {
+            int ie[3] = {0, 0, 0};
+            bool ok = true;
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                ie[ax] = ia[ax] - ((k >> ax) & 1);
+                ok = ok && ie[ax] >= 0 && ie[ax] < nel;
+            }
+            if (!ok) continue;
+            const int e = ie[0] + nel * (ie[1] + nel * ie[2]);
+            if (!keep_il[(int64_t)e * ld + p]) continue;
+            double ue[G::NC][DIM], we[G::NC][DIM];
+#pragma unroll
+            for (int c = 0; c < G::NC; ++c) {
+                int b = (ie[0] + (c & 1)) + nn * ((ie[1] + ((c >> 1) & 1)) + nn * (DIM == 3 ? ie[2] + ((c >> 2) & 1) : 0));
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    ue[c][i] = u_cil[((int64_t)b * DIM + i) * ld + p];
+                    we[c][i] = w_cil[((int64_t)b * DIM + i) * ld + p];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double F[DIM][DIM], Gw[DIM][DIM];
+#pragma unroll
+                for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) { F[i][J] = (i == J) ? 1.0 : 0.0; Gw[i][J] = 0.0; }
+#pragma unroll
+                for (int c = 0; c < G::NC; ++c)
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) {
+                        const double g = shape_grad<DIM, LAT_RULE_FULL>(q, c, J, invh);
+#pragma unroll
+                        for (int i = 0; i < DIM; ++i) { F[i][J] += ue[c][i] * g; Gw[i][J] += we[c][i] * g; }
+                    }
+                double Jd, H[DIM][DIM];
+                if (DIM == 2) {
+                    Jd = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                    const double r = 1.0 / Jd;
+                    H[0][0] = F[1][1] * r; H[0][1] = -F[1][0] * r;
+                    H[1][0] = -F[0][1] * r; H[1][1] = F[0][0] * r;
+                } else {
+                    double C[3][3];
+                    C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+                    C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+                    C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+                    C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+                    C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+                    C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+                    C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+                    C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+                    C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                    Jd = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
+                    const double r = 1.0 / Jd;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int J = 0; J < 3; ++J) H[i][J] = C[i][J] * r;
+                }
+                double lnJ = 0.0;
+                if (Jd > 0.0 && isfinite(Jd)) lnJ = log(Jd);
+                else lat_flag(st, isfinite(Jd) ? LAT_E_INVERTED : LAT_E_NONFINITE, cell);
+                // tr(Gw F^{-1}) = sum_iJ Gw_iJ Finv_Ji = sum_iJ Gw_iJ H_iJ
+                double tr = 0.0;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) tr += Gw[i][J] * H[i][J];
+                // M = H Gw^T H
+                double M[DIM][DIM];
+#pragma unroll
+                for (int j = 0; j < DIM; ++j)
+#pragma unroll
+                    for (int L = 0; L < DIM; ++L) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int x = 0; x < DIM; ++x)
+#pragma unroll
+                            for (int y = 0; y < DIM; ++y) s += H[j][x] * Gw[y][x] * H[y][L];
+                        M[j][L] = s;
+                    }
+                double gk[DIM];
+#pragma unroll
+                for (int J = 0; J < DIM; ++J) gk[J] = shape_grad<DIM, LAT_RULE_FULL>(q, k, J, invh);
+                const double c2 = mu - lam * lnJ;
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) {
+                    double s = 0.0, sfm = 0.0, sfl = 0.0;
+#pragma unroll
+                    for (int L = 0; L < DIM; ++L) {
+                        s += (mu * Gw[j][L] + c2 * M[j][L] + lam * tr * H[j][L]) * gk[L];
+                        sfm += (F[j][L] - H[j][L]) * gk[L];
+                        sfl += lnJ * H[j][L] * gk[L];
+                    }
+                    ub[j] += wq * s;
+                    fm[j] += wq * sfm;
+                    fl[j] += wq * sfl;
+                }
+            }
+        }
+    }
+    double dm = 0.0, dl = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const double wa = cell >= 0 ? w_cil[((int64_t)a * DIM + i) * ld + p] : 0.0;
+        dm += wa * fm[i];
+        dl += wa * fl[i];
+        if (ubar) ubar[((int64_t)a * DIM + i) * ld + p] = ub[i];
+    }
+    pmu[(int64_t)a * ld + p] = dm;
+    plam[(int64_t)a * ld + p] = dl;
+}
+
+template <int DIM, int RULE, bool PRINCIPAL>
+lat_status launch_cell(const lat_plan *P, CellArgs &A, hipStream_t s)
+{
+    if (PRINCIPAL) {
+        dim3 grid(1, (unsigned)P->nloc, DIM == 3 ? 3 : 1);
+        hipLaunchKernelGGL((k_cell<DIM, RULE, true>), grid, dim3(64), 0, s, A);
+    } else {
+        dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc, DIM == 3 ? 3 : 1);
+        hipLaunchKernelGGL((k_cell<DIM, RULE, false>), grid, dim3(256), 0, s, A);
+    }
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
+template <bool PRINCIPAL>
+lat_status dispatch_cell(const lat_plan *P, int rule, CellArgs &A, hipStream_t s)
+{
+    if (P->dim == 2)
+        return rule == LAT_RULE_FULL ? launch_cell<2, LAT_RULE_FULL, PRINCIPAL>(P, A, s)
+                                     : launch_cell<2, LAT_RULE_REDUCED, PRINCIPAL>(P, A, s);
+    return rule == LAT_RULE_FULL ? launch_cell<3, LAT_RULE_FULL, PRINCIPAL>(P, A, s)
+                                 : launch_cell<3, LAT_RULE_REDUCED, PRINCIPAL>(P, A, s);
+}
+
+CellArgs base_args(const lat_plan *P)
+{
+    CellArgs A{};
+    A.nel = P->nel; A.nloc = P->nloc; A.ld = P->ld;
+    A.u_cil = P->u_cil; A.keep_il = P->keep_il; A.perm = P->perm; A.lane = P->lane;
+    A.uidx = P->uidx; A.goff = P->goff; A.cap = P->cap;
+    return A;
+}
+
+lat_status gather_u(const lat_plan *P, const double *u_global, int32_t *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_u, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc), dim3(256), 0, s, P->dim,
+                       P->nloc, P->ld, P->l2g_il, P->perm, u_global, P->u_cil, st);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
+                                lat_rule snap_rule, double *f_int, double *energy, double *snap, double *plain_ops,
+                                int32_t *dev_status, hipStream_t stream)
+{
+    if (!P || !u_global || !mu || !lam) return LAT_E_ARG;
+    if (snap_rule != LAT_RULE_FULL && snap_rule != LAT_RULE_REDUCED) return LAT_E_ARG;
+    lat_status st = gather_u(P, u_global, dev_status, stream);
+    if (st != LAT_OK) return st;
+    CellArgs A = base_args(P);
+    A.mu = mu; A.lam = lam; A.matmode = 0; A.st = dev_status;
+    const bool full_snap = snap && snap_rule == LAT_RULE_FULL;
+    if (f_int || energy || plain_ops || full_snap) {
+        A.f = f_int;
+        A.epart = energy ? P->w_part : nullptr;
+        A.T = full_snap ? snap : nullptr;
+        A.ops = plain_ops;
+        if ((st = dispatch_cell<false>(P, LAT_RULE_FULL, A, stream)) != LAT_OK) return st;
+    }
+    if (snap && snap_rule == LAT_RULE_REDUCED) {
+        CellArgs B = base_args(P);
+        B.mu = mu; B.lam = lam; B.matmode = 0; B.st = dev_status; B.T = snap;
+        if ((st = dispatch_cell<false>(P, LAT_RULE_REDUCED, B, stream)) != LAT_OK) return st;
+    }
+    if (energy) {
+        if ((st = lat_tree_reduce(P->w_part, P->nloc, P->ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        hipLaunchKernelGGL(k_scatter_lanes, dim3((unsigned)lat_cdiv(P->ld, 256)), dim3(256), 0, stream, P->ld, P->perm,
+                           P->v_sq, energy);
+        LAT_LAUNCH_CHECK();
+    }
+    return LAT_OK;
+}
+
+lat_status lat_principal_ops(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
+                             const int32_t *S, int32_t n_r, double *K, double *K_mu, double *K_lam,
+                             int32_t *dev_status, hipStream_t stream)
+{
+    if (!P || !u_global || !mu || !lam || !S || !K) return LAT_E_ARG;
+    if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
+    lat_status st = gather_u(P, u_global, dev_status, stream);
+    if (st != LAT_OK) return st;
+    double *outs[3] = {K, K_mu, K_lam};
+    for (int mode = 0; mode < 3; ++mode) {
+        if (!outs[mode]) continue;
+        CellArgs A = base_args(P);
+        A.mu = mu; A.lam = lam; A.matmode = mode; A.st = dev_status;
+        A.S = S; A.n_r = n_r; A.Kst = outs[mode];
+        if ((st = dispatch_cell<true>(P, LAT_RULE_FULL, A, stream)) != LAT_OK) return st;
+    }
+    return LAT_OK;
+}
+
+lat_status lat_residual_adjoint(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
+                                const double *w, double *ubar_local, double *ubar_global, double *mu_bar,
+                                double *lam_bar, int32_t *dev_status, hipStream_t stream)
+{
+    if (!P || !u_global || !mu || !lam || !w) return LAT_E_ARG;
+    if (ubar_global && !ubar_local) return LAT_E_ARG;     // assembly reads the local result
+    lat_status st = gather_u(P, u_global, dev_status, stream);
+    if (st != LAT_OK) return st;
+    dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc);
+    if (P->dim == 2)
+        hipLaunchKernelGGL(k_residual_adjoint<2>, grid, dim3(256), 0, stream, P->nel, P->ld, P->u_cil, w, P->keep_il,
+                           P->perm, mu, lam, ubar_local, P->w_part, P->w_part2, dev_status);
+    else
+        hipLaunchKernelGGL(k_residual_adjoint<3>, grid, dim3(256), 0, stream, P->nel, P->ld, P->u_cil, w, P->keep_il,
+                           P->perm, mu, lam, ubar_local, P->w_part, P->w_part2, dev_status);
+    LAT_LAUNCH_CHECK();
+    if (mu_bar) {
+        if ((st = lat_tree_reduce(P->w_part, P->nloc, P->ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        hipLaunchKernelGGL(k_scatter_lanes, dim3((unsigned)lat_cdiv(P->ld, 256)), dim3(256), 0, stream, P->ld, P->perm,
+                           P->v_sq, mu_bar);
+        LAT_LAUNCH_CHECK();
+    }
+    if (lam_bar) {
+        if ((st = lat_tree_reduce(P->w_part2, P->nloc, P->ld, 0, P->v_inf, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        hipLaunchKernelGGL(k_scatter_lanes, dim3((unsigned)lat_cdiv(P->ld, 256)), dim3(256), 0, stream, P->ld, P->perm,
+                           P->v_inf, lam_bar);
+        LAT_LAUNCH_CHECK();
+    }
+    if (ubar_global) return lat_assemble(P, ubar_local, P->dim, ubar_global, stream);
+    return LAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,363 @@
+// Greedy selection of principal cells (Algorithm 1, Sec. 3.2.2), RB coefficients (the
+// least-squares formula of Sec. 3.2.2, solved through the greedy's certified decomposition),
+// and the reverse mode of those coefficients.
+//
+// The snapshot matrix T is cell-interleaved: row = snapshot entry, column = cell lane, so a
+// wave streams 64 cells' entries with unit stride.  All decisions use FP64 in a fixed order:
+//   - dot products / squared norms: chunks of 256 consecutive rows, each thread accumulating
+//     its lane by s = fma(x, y, s) from 0; chunk sums combined by a pairwise tree (neighbours
+//     (2k, 2k+1) per level, odd last element carried), done 256 rows per launch in LDS;
+//   - inf-norms: max of |x| (exact, order-free);
+//   - arg-max: largest inf-norm, ties to the lowest canonical cell id.
+// The loop is device-driven: every iteration's kernels read a device 'done' flag and return
+// at once when it is set, so the host enqueues `cap` iterations without synchronising.
+#include "lat_internal.h"
+
+namespace {
+
+enum { C_DONE = 0, C_SEL = 1, C_NR = 2, C_CELL = 3 };
+enum { D_RHO = 0, D_ACH = 1 };
+
+// ---------------------------------------------------------------------------- tree reduction
+// in [nrows][ld] -> out [ceil(nrows/256)][ld]; blockDim = 256 = 16 lanes x 16 row slots.
+__global__ __launch_bounds__(256) void k_tree(const double *__restrict__ in, int64_t nrows, int64_t ld, int op,
+                                              double *__restrict__ out)
+{
+    __shared__ double sh[LAT_TREE][17];
+    const int lx = threadIdx.x & 15, ry = threadIdx.x >> 4;
+    const int64_t p = (int64_t)blockIdx.x * 16 + lx;
+    const int64_t r0 = (int64_t)blockIdx.y * LAT_TREE;
+    const int n0 = (int)((nrows - r0) < LAT_TREE ? (nrows - r0) : LAT_TREE);
+    for (int t = ry; t < LAT_TREE; t += 16) {
+        double v = 0.0;
+        if (t < n0 && p < ld) v = in[(r0 + t) * ld + p];
+        sh[t][lx] = v;
+    }
+    __syncthreads();
+    int n = n0;
+    while (n > 1) {
+        const int half = n >> 1;
+        double vals[LAT_TREE / 32];               // half <= 128: at most 8 pairs per thread
+#pragma unroll
+        for (int t = 0; t < LAT_TREE / 32; ++t) {
+            const int k = ry + 16 * t;
+            if (k < half) {
+                const double x = sh[2 * k][lx], y = sh[2 * k + 1][lx];
+                vals[t] = op == 0 ? x + y : fmax(x, y);
+            }
+        }
+        const double tail = (n & 1) ? sh[n - 1][lx] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < LAT_TREE / 32; ++t) {
+            const int k = ry + 16 * t;
+            if (k < half) sh[k][lx] = vals[t];
+        }
+        if ((n & 1) && ry == 0) sh[half][lx] = tail;
+        __syncthreads();
+        n = half + (n & 1);
+    }
+    if (ry == 0 && p < ld) out[(int64_t)blockIdx.y * ld + p] = sh[0][lx];
+}
+
+// ---------------------------------------------------------------------------- greedy passes
+// grid: x = lane blocks of 256, y = chunk (z for chunks beyond 65535)
+__device__ __forceinline__ int64_t chunk_id() { return (int64_t)blockIdx.y + (int64_t)blockIdx.z * 65535; }
+
+// squared norms of the raw snapshots
+__global__ __launch_bounds__(256) void k_sq(const double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
+                                            double *__restrict__ psq)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = chunk_id();
+    if (p >= ld || b >= nchunk) return;
+    const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
+    double s = 0.0;
+    #pragma unroll 16
+    for (int64_t j = j0; j < j1; ++j) { const double x = T[j * ld + p]; s = fma(x, x, s); }
+    psq[b * ld + p] = s;
+}
+
+// Delta_0 = t / ||t||_2 (IEEE division; zero snapshot -> 0) with sq / inf partials of Delta_0
+__global__ __launch_bounds__(256) void k_normalize(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
+                                                   const double *__restrict__ nu, double *__restrict__ psq,
+                                                   double *__restrict__ pinf)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = chunk_id();
+    if (p >= ld || b >= nchunk) return;
+    const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
+    const double n = nu[p];
+    double s = 0.0, m = 0.0;
+#pragma unroll 16
+    for (int64_t j = j0; j < j1; ++j) {
+        const double x = n > 0.0 ? T[j * ld + p] / n : 0.0;
+        T[j * ld + p] = x;
+        s = fma(x, x, s);
+        m = fmax(m, fabs(x));
+    }
+    psq[b * ld + p] = s;
+    pinf[b * ld + p] = m;
+}
+
+__global__ void k_sqrt(int64_t ld, const double *__restrict__ sq, double *__restrict__ nu)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < ld) nu[p] = sqrt(sq[p]);
+}
+
+// beta partials: Delta . zeta
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
+                                             const double *__restrict__ zeta, const int32_t *__restrict__ ictl,
+                                             double *__restrict__ pdot)
+{
+    if (ictl[C_DONE]) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = chunk_id();
+    if (p >= ld || b >= nchunk) return;
+    const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
+    double s = 0.0;
+    #pragma unroll 16
+    for (int64_t j = j0; j < j1; ++j) s = fma(T[j * ld + p], zeta[j], s);
+    pdot[b * ld + p] = s;
+}
+
+// Delta <- Delta - beta zeta, with sq / inf partials of the updated Delta
+__global__ __launch_bounds__(256) void k_update(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
+                                                const double *__restrict__ zeta, const double *__restrict__ beta,
+                                                const int32_t *__restrict__ ictl, double *__restrict__ psq,
+                                                double *__restrict__ pinf)
+{
+    if (ictl[C_DONE]) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = chunk_id();
+    if (p >= ld || b >= nchunk) return;
+    const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
+    const double nb = -beta[p];
+    double s = 0.0, m = 0.0;
+#pragma unroll 16
+    for (int64_t j = j0; j < j1; ++j) {
+        const double x = fma(nb, zeta[j], T[j * ld + p]);
+        T[j * ld + p] = x;
+        s = fma(x, x, s);
+        m = fmax(m, fabs(x));
+    }
+    psq[b * ld + p] = s;
+    pinf[b * ld + p] = m;
+}
+
+// Arg-max of the inf-norms over the lanes (ties -> lowest canonical cell), stop test, and the
+// bookkeeping of iteration `it`.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_select(int64_t ld, const int32_t *__restrict__ perm,
+                                                 const double *__restrict__ inf, const double *__restrict__ sq,
+                                                 double tol, int it, int cap, int32_t *__restrict__ ictl,
+                                                 double *__restrict__ dctl, int32_t *__restrict__ S,
+                                                 int32_t *__restrict__ n_r, int32_t *st)
+{
+    __shared__ double bv[1024];
+    __shared__ int bc[1024];
+    __shared__ int bl[1024];
+    if (ictl[C_DONE]) return;
+    double v = -1.0;
+    int c = 0x7fffffff, l = -1;
+    for (int64_t p = threadIdx.x; p < ld; p += 1024) {
+        const int cell = perm[p];
+        if (cell < 0) continue;
+        const double x = inf[p];
+        if (x > v || (x == v && cell < c)) { v = x; c = cell; l = (int)p; }
+    }
+    bv[threadIdx.x] = v; bc[threadIdx.x] = c; bl[threadIdx.x] = l;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double x = bv[threadIdx.x + w];
+            const int cc = bc[threadIdx.x + w];
+            if (x > bv[threadIdx.x] || (x == bv[threadIdx.x] && cc < bc[threadIdx.x])) {
+                bv[threadIdx.x] = x; bc[threadIdx.x] = cc; bl[threadIdx.x] = bl[threadIdx.x + w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double top = bv[0];
+        dctl[D_ACH] = top > 0.0 ? top : 0.0;
+        if (!(top > tol)) {                 // converged
+            ictl[C_DONE] = 1;
+            *n_r = it;
+            ictl[C_NR] = it;
+        } else if (it >= cap) {             // cap reached above the tolerance
+            ictl[C_DONE] = 1;
+            *n_r = it;
+            ictl[C_NR] = it;
+            if (st) { atomicMax(&st[0], LAT_W_CAP); }
+        } else {
+            ictl[C_SEL] = bl[0];
+            ictl[C_CELL] = bc[0];
+            S[it] = bc[0];
+            dctl[D_RHO] = sqrt(sq[bl[0]]);
+            *n_r = it + 1;
+            ictl[C_NR] = it + 1;
+        }
+    }
+}
+
+// zeta_i = Delta^{s_i} / ||Delta^{s_i}||_2  (and the basis row Z[i])
+__global__ void k_zeta(const double *__restrict__ T, int64_t nsnap, int64_t ld, const int32_t *__restrict__ ictl,
+                       const double *__restrict__ dctl, double *__restrict__ zeta, double *__restrict__ Zrow)
+{
+    if (ictl[C_DONE]) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nsnap) return;
+    const double z = T[j * ld + ictl[C_SEL]] / dctl[D_RHO];
+    zeta[j] = z;
+    if (Zrow) Zrow[j] = z;
+}
+
+__global__ void k_store_beta(int64_t ld, int it, int cap, const int32_t *__restrict__ ictl,
+                             const double *__restrict__ beta, double *__restrict__ beta_pl)
+{
+    if (ictl[C_DONE]) return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < ld) beta_pl[p * cap + it] = beta[p];
+}
+
+__global__ void k_init_ctl(int32_t *ictl, double *dctl, int32_t *S, int cap, int32_t *n_r)
+{
+    const int t = threadIdx.x;
+    if (t < 16) ictl[t] = 0;
+    if (t < 16) dctl[t] = 0.0;
+    if (t < cap) S[t] = -1;
+    if (t == 0) *n_r = 0;
+}
+
+__global__ void k_zero(int64_t n, double *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+// R[j][k] = nu_{s_k} beta_j^{s_k}, j <= k < n_r   (R has stride cap, beta_pl stride pcap)
+__global__ void k_build_R(int cap, int pcap, const int32_t *__restrict__ ictl, const int32_t *__restrict__ S,
+                          const int32_t *__restrict__ lane, const double *__restrict__ nu_pl,
+                          const double *__restrict__ beta_pl, double *__restrict__ R)
+{
+    const int j = threadIdx.x, k = blockIdx.x;
+    if (j >= cap || k >= cap) return;
+    const int nr = ictl[C_NR];
+    double v = 0.0;
+    if (k < nr && j <= k) {
+        const int pk = lane[S[k]];
+        v = nu_pl[pk] * beta_pl[(int64_t)pk * pcap + j];
+    }
+    R[j * cap + k] = v;
+}
+
+// alpha^s: R alpha = nu_s beta^s by back-substitution from the last row (fma order
+// acc = fma(-R[k][l], alpha_l, acc) for l = k+1 .. n_r-1); outputs in canonical order.
+__global__ void k_alpha(int64_t ld, int cap, int pcap, const int32_t *__restrict__ ictl,
+                        const int32_t *__restrict__ perm, const double *__restrict__ R,
+                        const double *__restrict__ nu_pl, const double *__restrict__ beta_pl,
+                        double *__restrict__ alpha, double *__restrict__ beta, double *__restrict__ nu)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ld) return;
+    const int c = perm[p];
+    if (c < 0) return;
+    const int nr = ictl[C_NR];
+    const double n = nu_pl[p];
+    double a[LAT_MAX_CAP];
+    for (int k = 0; k < LAT_MAX_CAP; ++k) a[k] = 0.0;
+    for (int k = nr - 1; k >= 0; --k) {
+        double acc = n * beta_pl[p * pcap + k];
+        for (int l = k + 1; l < nr; ++l) acc = fma(-R[k * cap + l], a[l], acc);
+        a[k] = acc / R[k * cap + k];
+    }
+    for (int k = 0; k < cap; ++k) {
+        alpha[(int64_t)c * cap + k] = a[k];
+        if (beta) beta[(int64_t)c * cap + k] = k < nr ? beta_pl[p * pcap + k] : 0.0;
+    }
+    if (nu) nu[c] = n;
+}
+
+__global__ void k_achieved(const double *__restrict__ dctl, double *__restrict__ achieved)
+{
+    if (threadIdx.x == 0) *achieved = dctl[D_ACH];
+}
+
+dim3 chunk_grid(int64_t ld, int64_t nchunk)
+{
+    return dim3((unsigned)lat_cdiv(ld, 256), (unsigned)(nchunk < 65535 ? nchunk : 65535), (unsigned)lat_cdiv(nchunk, 65535));
+}
+
+}  // namespace
+
+lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1, double *t2,
+                           hipStream_t s)
+{
+    const double *src = in;
+    int64_t n = nrows;
+    double *bufs[2] = {t1, t2};
+    int which = 0;
+    while (true) {
+        const int64_t nb = lat_cdiv(n, LAT_TREE);
+        double *dst = nb == 1 ? out : bufs[which];
+        hipLaunchKernelGGL(k_tree, dim3((unsigned)lat_cdiv(ld, 16), (unsigned)nb), dim3(256), 0, s, src, n, ld, op, dst);
+        LAT_LAUNCH_CHECK();
+        if (nb == 1) break;
+        src = dst;
+        n = nb;
+        which ^= 1;
+    }
+    return LAT_OK;
+}
+
+extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, double tol, int32_t cap, int32_t *S,
+                                           int32_t *n_r, double *alpha, double *beta, double *nu, double *R, double *Z,
+                                           double *achieved, int32_t *dev_status, hipStream_t stream)
+{
+    if (!P || !snap || !S || !n_r || !alpha || !R || !achieved) return LAT_E_ARG;
+    if (!(tol > 0.0) || cap < 1 || cap > P->cap) return LAT_E_ARG;
+    const int64_t ld = P->ld, ns = P->nsnap, nc = P->nchunk;
+    const dim3 cg = chunk_grid(ld, nc);
+    const dim3 lg((unsigned)lat_cdiv(ld, 256));
+    lat_status st;
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, stream, P->ictl, P->dctl, S, P->cap, n_r);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)lat_cdiv(ld * P->cap, 256)), dim3(256), 0, stream, ld * P->cap, P->beta_pl);
+    if (Z) hipLaunchKernelGGL(k_zero, dim3((unsigned)lat_cdiv((int64_t)P->cap * ns, 256)), dim3(256), 0, stream,
+                              (int64_t)P->cap * ns, Z);
+    LAT_LAUNCH_CHECK();
+    // nu_s = ||t^s||_2 and the normalisation Delta_0 = t / nu
+    hipLaunchKernelGGL(k_sq, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->g_sq);
+    LAT_LAUNCH_CHECK();
+    if ((st = lat_tree_reduce(P->g_sq, nc, ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+    hipLaunchKernelGGL(k_sqrt, lg, dim3(256), 0, stream, ld, P->v_sq, P->v_nu);
+    hipLaunchKernelGGL(k_normalize, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->v_nu, P->g_sq, P->g_inf);
+    LAT_LAUNCH_CHECK();
+    if ((st = lat_tree_reduce(P->g_sq, nc, ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+    if ((st = lat_tree_reduce(P->g_inf, nc, ld, 1, P->v_inf, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+    for (int it = 0; it <= cap; ++it) {
+        hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, stream, ld, P->perm, P->v_inf, P->v_sq, tol, it, cap,
+                           P->ictl, P->dctl, S, n_r, dev_status);
+        LAT_LAUNCH_CHECK();
+        if (it == cap) break;
+        hipLaunchKernelGGL(k_zeta, dim3((unsigned)lat_cdiv(ns, 256)), dim3(256), 0, stream, snap, ns, ld, P->ictl,
+                           P->dctl, P->zeta, Z ? Z + (int64_t)it * ns : nullptr);
+        hipLaunchKernelGGL(k_dot, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->ictl, P->g_dot);
+        LAT_LAUNCH_CHECK();
+        if ((st = lat_tree_reduce(P->g_dot, nc, ld, 0, P->v_beta, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        hipLaunchKernelGGL(k_store_beta, lg, dim3(256), 0, stream, ld, it, P->cap, P->ictl, P->v_beta, P->beta_pl);
+        hipLaunchKernelGGL(k_update, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->v_beta, P->ictl,
+                           P->g_sq, P->g_inf);
+        LAT_LAUNCH_CHECK();
+        if ((st = lat_tree_reduce(P->g_sq, nc, ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        if ((st = lat_tree_reduce(P->g_inf, nc, ld, 1, P->v_inf, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+    }
+    // R, alpha (canonical order), beta, nu, achieved
+    hipLaunchKernelGGL(k_build_R, dim3((unsigned)P->cap), dim3(64), 0, stream, P->cap, P->cap, P->ictl, S, P->lane,
+                       P->v_nu, P->beta_pl, R);
+    hipLaunchKernelGGL(k_alpha, lg, dim3(256), 0, stream, ld, P->cap, P->cap, P->ictl, P->perm, R, P->v_nu, P->beta_pl,
+                       alpha, beta, nu);
+    hipLaunchKernelGGL(k_achieved, dim3(1), dim3(64), 0, stream, P->dctl, achieved);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}

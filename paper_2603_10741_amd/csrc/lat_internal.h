@@ -1,0 +1,96 @@
+// Internal definitions shared by the liblat HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "lat.h"
+
+#define LAT_WAVE 64
+#define LAT_CHUNK 256          // rows per fixed-order dot-product chunk
+#define LAT_TREE 256           // rows reduced per tree-kernel launch
+#define LAT_MAX_CAP 64
+
+struct lat_plan {
+    int dim, nel, nn, nloc, nelem, no, E, nc;
+    int ncell[3];
+    int64_t ncells, nglobal, nsnap, ld, npacked, nbg;
+    int ngroups, cap, device;
+    int64_t nchunk;            // greedy dot-product chunks over the snapshot rows
+    int maxunion;              // largest union of active nodes in a group
+    int napc;                  // node chunks per group for the adjoint forms
+    // device tables (immutable after creation)
+    uint8_t *keep = nullptr;       // [N_s][nelem] canonical
+    uint8_t *keep_il = nullptr;    // [nelem][ld]
+    int32_t *perm = nullptr;       // [ld] lane -> canonical cell / -1
+    int32_t *lane = nullptr;       // [N_s] canonical cell -> lane
+    int32_t *l2g = nullptr;        // [N_s][nloc]
+    int32_t *l2g_il = nullptr;     // [nloc][ld]
+    int32_t *nact = nullptr;       // [N_s]
+    int64_t *g2bg = nullptr;       // [nglobal]
+    uint8_t *dm_act = nullptr;     // DOF-map scratch: [N_s][nloc] active flags
+    int32_t *dm_flag = nullptr;    // [nbg] background flags
+    int32_t *dm_gid = nullptr;     // [nbg] scan output
+    int32_t *dm_bsum = nullptr;    // [nbg/1024 + 1] block sums + total
+    int32_t *goff = nullptr;       // [ngroups+1] packed-node offsets of the groups
+    int32_t *unode = nullptr;      // [npacked] local node of each packed node
+    int32_t *unbr = nullptr;       // [npacked][no] packed neighbour (a+o) or -1
+    uint64_t *umask = nullptr;     // [npacked] lanes owning the node
+    int32_t *uidx = nullptr;       // [ngroups][nloc] packed index within the group or -1
+    // workspace (device)
+    double *u_cil = nullptr;       // [nloc][dim][ld]
+    double *w_part = nullptr;      // [nloc][ld] per-node partials (energy, adjoint dots)
+    double *w_part2 = nullptr;     // [nloc][ld]
+    double *g_sq = nullptr;        // [nchunk][ld]
+    double *g_inf = nullptr;       // [nchunk][ld]
+    double *g_dot = nullptr;       // [nchunk][ld]
+    double *g_t1 = nullptr;        // [ceil(max(nchunk,nloc)/256)][ld] tree scratch
+    double *g_t2 = nullptr;
+    double *v_sq = nullptr, *v_inf = nullptr, *v_beta = nullptr, *v_nu = nullptr;   // [ld]
+    double *beta_pl = nullptr;     // [ld][cap] plan-order coordinates
+    double *zeta = nullptr;        // [nsnap]
+    int32_t *ictl = nullptr;       // small control block: done, sel lane, n_r, ...
+    double *dctl = nullptr;        // rho, achieved, ...
+    double *form_part = nullptr;   // [napc][ld][cap] adjoint form partials
+    double *form_out = nullptr;    // [ld][cap]
+    double *alpha_il = nullptr;    // [cap][ld] interleaved RB coefficients
+    double *aa_A = nullptr;        // [cap][ld] alpha-adjoint products
+    double *aa_B = nullptr;        // [ld][cap]
+    double *aa_q = nullptr;        // [2][ld][cap] q = R^{-T} alpha_bar, v = R^{-1} q
+    double *aa_gath = nullptr;     // [nsnap][cap] uniform operand (Z^T or principal columns)
+    double *aa_part = nullptr;     // partials for the alpha adjoint
+    int64_t aa_nchunk = 0;
+};
+
+#define LAT_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) {                                              \
+            std::fprintf(stderr, "liblat: %s failed: %s (%s:%d)\n", #call,   \
+                         hipGetErrorString(e_), __FILE__, __LINE__);         \
+            return LAT_E_DEVICE;                                             \
+        }                                                                    \
+    } while (0)
+
+#define LAT_LAUNCH_CHECK() LAT_HIP(hipGetLastError())
+
+static inline int lat_ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
+static inline int64_t lat_cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device status word helpers.
+__device__ inline void lat_flag(int32_t *st, int code, int cell)
+{
+    if (st) {
+        atomicMax(&st[0], code);
+        atomicMin(&st[1], cell);
+    }
+}
+
+// Shared internal launches (defined in lat_greedy.hip).
+// Pairwise-tree reduction over rows of in [nrows][ld] (row-major, lanes fastest), applying
+// sum (op 0) or max (op 1); result [ld] in out.  Uses t1/t2 as scratch ([ceil(nrows/256)][ld]).
+lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1,
+                           double *t2, hipStream_t s);
