@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the principal-cell lattice hot path on one MI355X.
+
+One step = one pass of every hot-path stage over the workload (inputs already in HBM):
+  DOF maps -> residual + energy + snapshots + plain operators -> greedy selection + RB
+  coefficients -> principal operators -> ROM apply (the measured kernel) -> plain per-cell apply
+  -> reverse mode (ROM apply adjoint, coefficient adjoint, residual adjoint).
+`value` is the ROM apply's throughput, GDOF/s = (active local DOFs x right-hand sides) / (apply
+kernel time), with the kernel timed by HIP events on the stream it runs on.
+
+Workload: 32 x 32 cells of 32^2 Q1 quads with hole radius graded 0.20 -> 0.35 along x,
+neo-Hookean mu = 1, lam = 10, 10% compression + seeded perturbation, 16 right-hand sides,
+at most 32 principal cells (tolerance 1e-8).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD_INDEX = 1
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=12.0):
+    """The FP64 oracle's ROM apply on the host cores, repeated for about `budget_s` seconds."""
+    import numpy as np
+    import oracle as O
+    O.build(force=False)
+    l2g, nact, g2bg = O.dofmap(cfg.dim, cfg.ncell, cfg.nel, keep)
+    uloc = O.gather_local(u_bg[g2bg], l2g)
+    T = O.cells_eval(cfg.dim, cfg.nel, keep, uloc, mu, lam, want_f=False, want_energy=False)["T"]
+    g = O.greedy(T, cfg.tol, cfg.cap, keep_Z=False)
+    Kp = np.ascontiguousarray(T[g["S"][:g["n_r"]]])
+    del T
+    dofs = int(nact.sum()) * cfg.dim * X.shape[-1]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.combo_apply(cfg.dim, cfg.nel, Kp, g["alpha"], l2g, X)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": dofs * reps / el / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"full workload ({cfg.n_cells} cells, m={X.shape[-1]}), oracle ROM apply repeated "
+                      f"{reps}x in {el:.1f} s"}, {"S": g["S"], "n_r": g["n_r"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lattice as L
+    from paper_2603_10741_amd import binding as B
+    from paper_2603_10741_amd.autograd import build_rom_state  # noqa: F401  (same pipeline, not timed here)
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = L.config(WORKLOAD_INDEX)
+    m = cfg.m
+    log("workload", cfg.name)
+    keep = L.make_keep(cfg)
+    mu, lam = L.make_material(cfg)
+    u_bg = L.make_displacement(cfg)
+    X = L.make_rhs(cfg)
+    Yb = L.make_rhs(cfg, stream=1)
+
+    P = B.Plan(cfg.dim, cfg.ncell, cfg.nel, keep, cap=cfg.cap)
+    l2g, nact, g2bg, perm = P.dofmap()
+    active_dofs = int(nact.sum().item()) * cfg.dim
+    ug = torch.from_numpy(u_bg).to(dev)[g2bg].contiguous()
+    mu_t, lam_t = torch.from_numpy(mu).to(dev), torch.from_numpy(lam).to(dev)
+    ones, zeros = torch.ones_like(mu_t), torch.zeros_like(mu_t)
+    Xp = P.pack(torch.from_numpy(X).to(dev), m)
+    Ybp = P.pack(torch.from_numpy(Yb).to(dev), m)
+    rbar = torch.randn(P.nglobal, cfg.dim, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(5))
+    w_cil = P.gather(rbar, cfg.dim)
+
+    # persistent outputs (no allocation inside the timed steps)
+    bufs = {
+        "res": {"f": P._f64(P.nloc * P.dim * P.ld), "energy": P._f64(P.ncells), "snap": P._f64(P.nsnap * P.ld),
+                "plain": P._f64(P.npacked * P.E * 64)},
+        "snap_mu": {"snap": P._f64(P.nsnap * P.ld)},
+        "snap_lam": {"snap": P._f64(P.nsnap * P.ld)},
+        "ops": {k: P._f64(P.nloc * P.E * P.cap) for k in ("K", "K_mu", "K_lam")},
+        "Y": P._f64(P.packed_size(m)), "Yp": P._f64(P.packed_size(m)),
+    }
+    greedy_out = {}
+    stages = ["dofmap", "residual_tangent", "select_principal", "principal_ops", "rom_apply", "plain_apply",
+              "adjoint"]
+    ev = {s: [] for s in stages}
+    state = {}
+
+    def step(record):
+        s = torch.cuda.current_stream()
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+        marks[0].record(s)
+        P.dofmap()
+        marks[1].record(s)
+        P.residual_tangent(ug, mu_t, lam_t, f=True, energy=True, snap=True, plain=True, out=bufs["res"])
+        P.residual_tangent(ug, ones, zeros, f=False, energy=False, snap=True, out=bufs["snap_mu"])
+        P.residual_tangent(ug, zeros, ones, f=False, energy=False, snap=True, out=bufs["snap_lam"])
+        marks[2].record(s)
+        g = P.select_principal(bufs["res"]["snap"], cfg.tol, keep_Z=True, out=greedy_out or None)
+        greedy_out.update(g)
+        marks[3].record(s)
+        if "n_r" not in state:
+            state["n_r"] = int(g["n_r"].item())        # host copy of the count, read once
+        n_r = state["n_r"]
+        ops = P.principal_ops(ug, mu_t, lam_t, g["S"], n_r, parts=True, out=bufs["ops"])
+        marks[4].record(s)
+        P.apply_combo(ops["K"], n_r, g["alpha"], Xp, m, out=bufs["Y"])
+        marks[5].record(s)
+        P.apply_plain(bufs["res"]["plain"], Xp, m, out=bufs["Yp"])
+        marks[6].record(s)
+        ad = P.apply_combo_adjoint(ops["K"], n_r, g["alpha"], Xp, Ybp, m, K_mu=ops["K_mu"], K_lam=ops["K_lam"],
+                                   S=g["S"])
+        P.alpha_adjoint(bufs["res"]["snap"], g["Z"], g["R"], g["nu"], g["S"], n_r, g["alpha"], ad["alpha_bar"],
+                        bufs["snap_mu"]["snap"], bufs["snap_lam"]["snap"], ad["mu_bar"], ad["lam_bar"])
+        P.residual_adjoint(ug, mu_t, lam_t, w_cil)
+        marks[7].record(s)
+        if record:
+            for i, st in enumerate(stages):
+                ev[st].append((marks[i], marks[i + 1]))
+
+    P.reset_status()
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log("warmup done; n_r =", state.get("n_r"))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    code, cell = P.check_status(allow_cap=True)
+    ms_stage = {st: float(np.mean([a.elapsed_time(b) for a, b in ev[st]])) for st in stages}
+    t_apply = ms_stage["rom_apply"] * 1e-3
+    t_plain = ms_stage["plain_apply"] * 1e-3
+    n_r = state["n_r"]
+    dofs_rhs = active_dofs * m
+    value = dofs_rhs / t_apply / 1e9
+    alg_bytes = 16.0 * dofs_rhs + 8.0 * P.ncells * n_r + 8.0 * P.nloc * P.E * n_r
+    achieved = alg_bytes / t_apply / 1e9
+
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+
+    # accuracy of the ROM apply against the FP64 oracle, on a sample of cells, same S and alpha
+    import oracle as O
+    O.build(force=False)
+    Y = P.unpack(bufs["Y"], m).cpu().numpy()
+    Yp = P.unpack(bufs["Yp"], m).cpu().numpy()
+    S = greedy_out["S"].cpu().numpy()[:n_r]
+    alpha = greedy_out["alpha"].cpu().numpy()
+    l2g_o, _, g2bg_o = O.dofmap(cfg.dim, cfg.ncell, cfg.nel, keep)
+    uloc = O.gather_local(u_bg[g2bg_o], l2g_o)
+    sample = np.unique(np.concatenate([np.arange(0, P.ncells, max(1, P.ncells // 24)), S]))
+    Kp = np.stack([O.cell_eval(cfg.dim, cfg.nel, keep[s], uloc[s], mu[s], lam[s])["stencil"] for s in S])
+    Yo = O.combo_apply(cfg.dim, cfg.nel, Kp, alpha[sample], l2g_o[sample], X[sample])
+    err_rom = float(np.linalg.norm(Y[sample] - Yo) / np.linalg.norm(Yo))
+    Kself = np.stack([O.cell_eval(cfg.dim, cfg.nel, keep[s], uloc[s], mu[s], lam[s])["stencil"] for s in sample])
+    Ypo = O.plain_apply(cfg.dim, cfg.nel, Kself, l2g_o[sample], X[sample])
+    err_plain = float(np.linalg.norm(Yp[sample] - Ypo) / np.linalg.norm(Ypo))
+    rom_vs_plain = float(np.linalg.norm(Y - Yp) / np.linalg.norm(Yp))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu, _ = cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=args.cpu_budget)
+
+    out = {
+        "metric": "GDOF/s of principal-combo apply vs plain per-cell apply at ≤1e-5 rel err",
+        "value": round(value, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "cells": P.ncells, "elements_per_cell": f"{cfg.nel}^2",
+                   "right_hand_sides": m, "principal_cap": cfg.cap, "tol": cfg.tol, "n_r": n_r,
+                   "active_local_dofs": active_dofs, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_apply (ROM apply)", "algorithmic_bytes_per_launch": int(alg_bytes)},
+        "cpu_baseline": cpu,
+        "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
+        "rom_over_plain_speedup": round(t_plain / t_apply, 3),
+        "rel_err_rom_apply_vs_fp64_oracle": err_rom,
+        "rel_err_plain_apply_vs_fp64_oracle": err_plain,
+        "rom_vs_plain_operator_rel_diff": rom_vs_plain,
+        "stage_ms": {k: round(v, 4) for k, v in ms_stage.items()},
+        "device_status": {"code": code, "first_cell": cell},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -148,13 +148,28 @@ lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, 
                                 double *achieved, int32_t *dev_status, hipStream_t stream);
 
 /* ROM apply (eq. romstiffnessmatrix): Y_i = M_i (sum_k alpha_ik K_k) M_i X_i for every cell at
- * once, M_i the active-DOF mask of cell i.  K: principal stack (cap slots), n_r HOST value,
- * alpha [N_s][cap] (canonical), X, Y packed with m right-hand sides.
- * prec = LAT_F64 only in this version (others return LAT_E_ARG).  transpose != 0 applies the
- * transposed operator (used by the adjoint). */
+ * once, M_i the active-DOF mask of cell i.  K: a stack of n_r stencils in the principal stack
+ * layout (cap slots) -- the principal tangents from lat_principal_ops with alpha the RB
+ * coefficients, or the greedy's orthonormal basis with its coefficients (lat_basis_stack), which
+ * is the same operator when the snapshots use the full rule.  n_r is a HOST value, alpha
+ * [N_s][cap] canonical, X and Y packed with m right-hand sides.
+ * prec = LAT_F64: FP64 throughout (transpose != 0 applies the transposed operator).
+ * prec = LAT_F32: stack and coefficients rounded to FP32, FP32 combination and apply.
+ * prec = LAT_BF16: the combination runs on the bf16 matrix cores with FP32 accumulation on
+ *   operands split into bf16 slices; the slice products are grouped in levels of 2^-8 relative
+ *   size, 1 to 3 levels as refine_tol requires (>= 2^-8: 1, >= 2^-16: 2, else 3), each level summed
+ *   in FP64; the apply runs in FP32.  Requires m in {1, 2, 4, 8, 16}.
+ * X and Y stay FP64 for every prec; transpose is LAT_F64 only. */
 lat_status lat_apply_combo(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
-                           const double *X, double *Y, int32_t m, lat_prec prec, int32_t transpose,
-                           hipStream_t stream);
+                           const double *X, double *Y, int32_t m, lat_prec prec, double refine_tol,
+                           int32_t transpose, hipStream_t stream);
+
+/* The greedy's orthonormal basis as a ROM stack: stack[(a E + e) cap + k] = Z[k][(a, e)] and
+ * coefficients coef[s][k] = nu_s beta_k^s (the certified decomposition of Algorithm 1), k < n_r
+ * (HOST value), zero beyond.  Z [cap][n_snap], nu [N_s], beta [N_s][cap] from
+ * lat_select_principal; stack [(n+1)^d][E][cap], coef [N_s][cap]. */
+lat_status lat_basis_stack(const lat_plan *plan, const double *Z, const double *nu, const double *beta,
+                           int32_t n_r, double *stack, double *coef, hipStream_t stream);
 
 /* Plain per-cell apply Y_i = M_i K_i M_i X_i with every cell's own full-rule tangent
  * (plain_ops from lat_residual_tangent).  X, Y packed. */

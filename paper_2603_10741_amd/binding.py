@@ -48,7 +48,8 @@ def _lib():
             "lat_residual_tangent": (ctypes.c_int, [P, P, P, P, ctypes.c_int, P, P, P, P, P, P]),
             "lat_principal_ops": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P]),
             "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P]),
-            "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, I32, P]),
+            "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, F, I32, P]),
+            "lat_basis_stack": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
             "lat_apply_plain": (ctypes.c_int, [P, P, P, P, I32, P]),
             "lat_apply_combo_adjoint": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, I32, P, P, P, P, P]),
             "lat_alpha_adjoint": (ctypes.c_int, [P, P, P, P, P, P, I32, P, P, P, P, P, P, P]),
@@ -72,7 +73,7 @@ def _lib():
 def exported_symbols():
     """Names of the C entry points this binding uses (all declared in include/lat.h)."""
     return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_status_reset",
-            "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_apply_combo",
+            "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_apply_combo", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
             "lat_plain_ops_to_canon"]
@@ -194,11 +195,20 @@ class Plan:
     def packed_size(self, m):
         return self.npacked * self.dim * m * 64
 
-    def apply_combo(self, K, n_r, alpha, X, m, transpose=False, prec=F64, out=None):
+    def apply_combo(self, K, n_r, alpha, X, m, transpose=False, prec=F64, refine_tol=1e-6, out=None):
         Y = self._f64(self.packed_size(m)) if out is None else out
         _ok(_lib().lat_apply_combo(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(X), _ptr(Y), int(m), prec,
-                                   int(bool(transpose)), _stream()), "apply_combo")
+                                   float(refine_tol), int(bool(transpose)), _stream()), "apply_combo")
         return Y
+
+    def basis_stack(self, Z, nu, beta, n_r, out=None):
+        out = dict(out or {})
+        if "stack" not in out:
+            out["stack"] = self._f64(self.nloc * self.E * self.cap)
+            out["coef"] = self._f64(self.ncells, self.cap)
+        _ok(_lib().lat_basis_stack(self._p, _ptr(Z), _ptr(nu), _ptr(beta), int(n_r), _ptr(out["stack"]),
+                                   _ptr(out["coef"]), _stream()), "basis_stack")
+        return out
 
     def apply_plain(self, ops, X, m, out=None):
         Y = self._f64(self.packed_size(m)) if out is None else out

@@ -103,20 +103,22 @@ __global__ void k_aa_cellterm(int64_t ld, int cap, int n_r, const int32_t *__res
     if (lbar) lbar[c] += sl;
 }
 
-// principal term for slot k (one thread per slot), ascending canonical order over the cells
-__global__ void k_aa_principal(int64_t ncells, int64_t ld, int cap, int n_r, const int32_t *__restrict__ S,
-                               const int32_t *__restrict__ lane, const double *__restrict__ nu,
-                               const double *__restrict__ alpha, const double *__restrict__ qv,
-                               const double *__restrict__ Am, const double *__restrict__ Al,
-                               const double *__restrict__ Bm, const double *__restrict__ Bl,
-                               double *__restrict__ mbar, double *__restrict__ lbar)
+// principal term for slot k: one workgroup per slot, strided over the cells (canonical order),
+// fixed-shape tree in LDS (deterministic)
+__global__ __launch_bounds__(256) void k_aa_principal(int64_t ncells, int64_t ld, int cap, int n_r,
+                                                      const int32_t *__restrict__ S,
+                                                      const int32_t *__restrict__ lane, const double *__restrict__ nu,
+                                                      const double *__restrict__ alpha, const double *__restrict__ qv,
+                                                      const double *__restrict__ Am, const double *__restrict__ Al,
+                                                      const double *__restrict__ Bm, const double *__restrict__ Bl,
+                                                      double *__restrict__ mbar, double *__restrict__ lbar)
 {
-    const int k = threadIdx.x;
-    if (k >= n_r) return;
+    __shared__ double shm[256], shl[256];
+    const int k = blockIdx.x;
     const int sk = S[k];
     const int64_t pk = lane[sk];
     double sm = 0.0, sl = 0.0;
-    for (int64_t i = 0; i < ncells; ++i) {
+    for (int64_t i = threadIdx.x; i < ncells; i += 256) {
         const int64_t pi = lane[i];
         const double vik = qv[(ld + pi) * cap + k];
         double qAm = 0.0, qAl = 0.0;
@@ -128,13 +130,21 @@ __global__ void k_aa_principal(int64_t ncells, int64_t ld, int cap, int n_r, con
         sm += nu[i] * vik * Bm[pi * cap + k] - aik * qAm;
         sl += nu[i] * vik * Bl[pi * cap + k] - aik * qAl;
     }
-    if (mbar) mbar[sk] += sm;
-    if (lbar) lbar[sk] += sl;
+    shm[threadIdx.x] = sm; shl[threadIdx.x] = sl;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) { shm[threadIdx.x] += shm[threadIdx.x + w]; shl[threadIdx.x] += shl[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mbar) mbar[sk] += shm[0];
+        if (lbar) lbar[sk] += shl[0];
+    }
 }
 
 lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
 {
-    const int rows = 4096;
+    const int rows = P->aa_rows;
     dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->aa_nchunk);
     if (n_r <= 8) hipLaunchKernelGGL(k_aa_contract<8>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
     else if (n_r <= 16) hipLaunchKernelGGL(k_aa_contract<16>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
@@ -174,8 +184,8 @@ extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, 
     if ((st = contract(P, n_r, delta, P->aa_gath, Bl, stream)) != LAT_OK) return st;
     hipLaunchKernelGGL(k_aa_cellterm, lg, dim3(256), 0, stream, ld, (int)cap, n_r, P->perm, P->aa_q, Am, Al, mu_bar,
                        lam_bar);
-    hipLaunchKernelGGL(k_aa_principal, dim3(1), dim3(64), 0, stream, P->ncells, ld, (int)cap, n_r, S, P->lane, nu, alpha,
-                       P->aa_q, Am, Al, Bm, Bl, mu_bar, lam_bar);
+    hipLaunchKernelGGL(k_aa_principal, dim3((unsigned)n_r), dim3(256), 0, stream, P->ncells, ld, (int)cap, n_r, S, P->lane,
+                       nu, alpha, P->aa_q, Am, Al, Bm, Bl, mu_bar, lam_bar);
     LAT_LAUNCH_CHECK();
     return LAT_OK;
 }

@@ -21,7 +21,7 @@ struct Geo {
 };
 
 struct ApplyArgs {
-    int nn, m, cap, n_r, nch, chunks_per_group;
+    int nn, m, cap, n_r, nch, chunks_per_group, nseg;
     int64_t ld;
     const int32_t *goff, *unode, *unbr;
     const uint64_t *umask;
@@ -39,29 +39,41 @@ __device__ __forceinline__ int offset_node(int a, int o, int nn, int dim)
     return ix + nn * (iy + nn * iz);
 }
 
-// MODE 0: ROM apply, 1: ROM apply transposed, 2: plain apply
+// MODE 0: ROM apply, 1: ROM apply transposed, 2: plain apply.
+// Pointers are separate __restrict__ arguments: read-only, non-aliased memory lets wave-uniform
+// reads (node tables, principal stack) go through the scalar cache.
 template <int DIM, int MC, int NR, int MODE>
-__global__ __launch_bounds__(256) void k_apply(ApplyArgs A)
+__global__ __launch_bounds__(256) void k_apply(ApplyArgs A, const int32_t *__restrict__ goff,
+                                               const int32_t *__restrict__ unode, const int32_t *__restrict__ unbr,
+                                               const uint64_t *__restrict__ umask, const double *__restrict__ K,
+                                               const double *__restrict__ alpha_il, const double *__restrict__ X,
+                                               double *__restrict__ Y)
 {
     using G = Geo<DIM>;
     constexpr int E = G::E;
-    const int wave = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    // the wave index is uniform across the wave; say so, so that everything derived from it
+    // (node ids, principal-stack addresses) is read with scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(lat_xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63;
     const int g = wave / A.chunks_per_group, ch = wave % A.chunks_per_group;
     if (g >= (int)(A.ld / LAT_WAVE)) return;
-    const int q0 = A.goff[g] + ch * A.nch;
-    const int q1 = min(A.goff[g + 1], q0 + A.nch);
+    // wave ch of the group takes nodes ch, ch + cpg, ch + 2 cpg, ...: at any moment the waves of
+    // a group work on one compact band of nodes, whose stencil neighbourhoods overlap in L2
+    const int cpg = A.chunks_per_group;
+    const int q0 = goff[g] + ch;
+    const int q1 = goff[g + 1];
     if (q0 >= q1) return;
     const int64_t p = (int64_t)g * LAT_WAVE + l;
     const int m = A.m;
+    const int cap = A.cap;
     double alpha[MODE == 2 ? 1 : NR];
     if (MODE != 2) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) alpha[k] = k < A.n_r ? A.alpha_il[(int64_t)k * A.ld + p] : 0.0;
+        for (int k = 0; k < NR; ++k) alpha[k] = alpha_il[(int64_t)k * A.ld + p];   // zero beyond n_r
     }
-    for (int q = q0; q < q1; ++q) {
-        const int a = A.unode[q];
-        const uint64_t msk = A.umask[q];
+    for (int q = q0; q < q1; q += cpg) {
+        const int a = unode[q];
+        const uint64_t msk = umask[q];
         for (int c0 = 0; c0 < m; c0 += MC) {
             double acc[DIM][MC];
 #pragma unroll
@@ -69,16 +81,16 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A)
 #pragma unroll
                 for (int c = 0; c < MC; ++c) acc[i][c] = 0.0;
             for (int o = 0; o < G::NO; ++o) {
-                const int nb = A.unbr[(int64_t)q * G::NO + o];
+                const int nb = unbr[(int64_t)q * G::NO + o];
                 if (nb < 0) continue;
-                const bool nb_own = (A.umask[nb] >> l) & 1;    // inputs at DOFs a cell does not own are ignored
+                const bool nb_own = (umask[nb] >> l) & 1;    // inputs at DOFs a cell does not own are ignored
                 double kt[DIM][DIM];
                 if (MODE == 2) {
 #pragma unroll
                     for (int i = 0; i < DIM; ++i)
 #pragma unroll
                         for (int j = 0; j < DIM; ++j)
-                            kt[i][j] = A.K[((int64_t)q * E + (o * DIM + i) * DIM + j) * LAT_WAVE + l];
+                            kt[i][j] = K[((int64_t)q * E + (o * DIM + i) * DIM + j) * LAT_WAVE + l];
                 } else {
                     const int arow = MODE == 0 ? a : offset_node(a, o, A.nn, DIM);
                     const int orow = MODE == 0 ? o : G::NO - 1 - o;
@@ -88,11 +100,10 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A)
                         for (int j = 0; j < DIM; ++j) {
                             // MODE 1 reads the transposed block K[(a+o, j), (a, i)]
                             const int ent = MODE == 0 ? (orow * DIM + i) * DIM + j : (orow * DIM + j) * DIM + i;
-                            const double *kp = A.K + ((int64_t)arow * E + ent) * A.cap;
+                            const double *kp = K + ((int64_t)arow * E + ent) * cap;
                             double s = 0.0;
 #pragma unroll
-                            for (int k = 0; k < NR; ++k)
-                                if (k < A.n_r) s = fma(alpha[k], kp[k], s);
+                            for (int k = 0; k < NR; ++k) s = fma(alpha[k], kp[k], s);
                             kt[i][j] = s;
                         }
                 }
@@ -100,7 +111,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A)
                 for (int j = 0; j < DIM; ++j)
 #pragma unroll
                     for (int c = 0; c < MC; ++c) {
-                        const double x = nb_own ? A.X[(((int64_t)nb * DIM + j) * m + c0 + c) * LAT_WAVE + l] : 0.0;
+                        const double x = nb_own ? X[(((int64_t)nb * DIM + j) * m + c0 + c) * LAT_WAVE + l] : 0.0;
 #pragma unroll
                         for (int i = 0; i < DIM; ++i) acc[i][c] = fma(kt[i][j], x, acc[i][c]);
                     }
@@ -110,54 +121,253 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A)
             for (int i = 0; i < DIM; ++i)
 #pragma unroll
                 for (int c = 0; c < MC; ++c)
-                    A.Y[(((int64_t)q * DIM + i) * m + c0 + c) * LAT_WAVE + l] = own ? acc[i][c] : 0.0;
+                    Y[(((int64_t)q * DIM + i) * m + c0 + c) * LAT_WAVE + l] = own ? acc[i][c] : 0.0;
         }
     }
 }
 
+// 2D row walk, software pipelined.  One workgroup = one group of 64 cells (lanes) and one node
+// row y; its NW = 8 waves split the right-hand sides (wave w owns MW = m / 8 of them) and walk
+// x = 0..n in step.  Per step (node x):
+//   - each wave combines its share of the node's 36 stencil entries (Ktilde = sum_k alpha_k K_k,
+//     the principal block read as a broadcast from LDS, where it was staged one step earlier) or,
+//     for the plain apply, copies its share of the cell's own stencil, into LDS;
+//   - it stages the next node's principal block and issues the loads of X column x+2 into a
+//     4-slot register window (columns x-1 .. x+2 of rows y-1, y, y+1);
+//   - one barrier; then each wave applies the node's 2x2 blocks to its right-hand sides.
+// Every X entry is fetched once per row walk and all loads are issued a step ahead of use.
+template <int MW, int NR, int MODE>
+__global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *__restrict__ goff,
+                                                    const int32_t *__restrict__ uidx,
+                                                    const uint64_t *__restrict__ umask, const double *__restrict__ K,
+                                                    const double *__restrict__ alpha_il, const double *__restrict__ X,
+                                                    double *__restrict__ Y)
+{
+    constexpr int E = 36, NW = 8;
+    constexpr int KB = MODE == 2 ? 1 : E * NR;          // principal block of one node (doubles)
+    constexpr int KPT = (KB + NW * 64 - 1) / (NW * 64);  // staged per thread
+    __shared__ double kt_s[2][E][64];
+    __shared__ double kb_s[2][MODE == 2 ? 1 : KB];
+    const int nn = A.nn, nloc = nn * nn, m = A.m, cap = A.cap;
+    const int lb = lat_xcd_block(blockIdx.x, gridDim.x);
+    const int nseg = A.nseg;                             // each row is walked in nseg x-segments
+    const int g = lb / (nn * nseg), y = (lb / nseg) % nn, seg = lb % nseg;
+    const int xs0 = (seg * nn) / nseg, xs1 = ((seg + 1) * nn) / nseg;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63, tid = threadIdx.x;
+    const int64_t p = (int64_t)g * LAT_WAVE + l;
+    const int r0 = w * MW;
+    const int e0 = (w * E) / NW, e1 = ((w + 1) * E) / NW;   // this wave's share of the entries
+    const int32_t *ui = uidx + (int64_t)g * nloc;
+    const int gq = goff[g];
+    double alpha[MODE == 2 ? 1 : NR];
+    if (MODE != 2) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) alpha[k] = alpha_il[(int64_t)k * A.ld + p];
+    }
+    // principal-block staging (ROM modes): block[e * NR + k] = K_k[row(e)][ent(e)]
+    double kpre[KPT];
+    auto fetch_block = [&](int x) {
+        if (MODE == 2) return;
+        const bool inx = x < nn;
+#pragma unroll
+        for (int t = 0; t < KPT; ++t) {
+            const int idx = tid + t * NW * 64;
+            double v = 0.0;
+            if (inx && idx < KB) {
+                const int e = idx / NR, k = idx % NR;
+                const int o = e >> 2, i = (e >> 1) & 1, j = e & 1;
+                int arow = x + nn * y, ent = e;
+                bool valid = true;
+                if (MODE == 1) {       // transposed block K[(a+o, j), (a, i)]
+                    const int xb = x + (o % 3) - 1, yb = y + (o / 3) - 1;
+                    valid = xb >= 0 && xb < nn && yb >= 0 && yb < nn;
+                    arow = valid ? xb + nn * yb : 0;
+                    ent = ((8 - o) * 2 + j) * 2 + i;
+                }
+                if (valid) v = K[((int64_t)arow * E + ent) * cap + k];
+            }
+            kpre[t] = v;
+        }
+    };
+    auto store_block = [&](int buf) {
+        if (MODE == 2) return;
+#pragma unroll
+        for (int t = 0; t < KPT; ++t) {
+            const int idx = tid + t * NW * 64;
+            if (idx < KB) kb_s[buf][idx] = kpre[t];
+        }
+    };
+    // plain mode: this wave's share of the cell's own stencil, one step ahead
+    double ppre[(E + NW - 1) / NW];
+    auto fetch_plain = [&](int x) {
+        if (MODE != 2) return;
+        int qi = -1;
+        if (x < nn) qi = ui[x + nn * y];
+        const int64_t q = qi >= 0 ? gq + qi : 0;
+#pragma unroll
+        for (int t = 0; t < (E + NW - 1) / NW; ++t) {
+            const int e = e0 + t;
+            const double v = (e < e1) ? K[(q * E + (e < E ? e : 0)) * LAT_WAVE + l] : 0.0;
+            ppre[t] = qi >= 0 ? v : 0.0;
+        }
+    };
+    double xw[4][3][2][MW];            // [slot][row y-1..y+1][dof][rhs]; column c lives in slot (c+1) % 4
+    auto load_col = [&](double (&col)[3][2][MW], int xc) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int yy = y + dy - 1;
+            int qi = -1;
+            if (xc >= 0 && xc < nn && yy >= 0 && yy < nn) qi = ui[xc + nn * yy];
+            const int64_t q = qi >= 0 ? gq + qi : 0;        // always a valid packed node index
+            const bool own = qi >= 0 && ((umask[q] >> l) & 1);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int c = 0; c < MW; ++c) {
+                    const double v = X[((q * 2 + j) * m + r0 + c) * LAT_WAVE + l];
+                    col[dy][j][c] = own ? v : 0.0;
+                }
+        }
+    };
+    auto step = [&](int x, int sp, int sc, int sn, int sf) {
+        const int a = x + nn * y;
+        const int qi = ui[a];
+        const int buf = x & 1;
+        // (1) this wave's entries of the node's blocks -> LDS
+        if (qi >= 0) {
+            if (MODE == 2) {
+#pragma unroll
+                for (int t = 0; t < (E + NW - 1) / NW; ++t)
+                    if (e0 + t < e1) kt_s[buf][e0 + t][l] = ppre[t];
+            } else {
+                for (int e = e0; e < e1; ++e) {
+                    const double *kb = &kb_s[buf][e * NR];
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) sacc = fma(alpha[k], kb[k], sacc);
+                    kt_s[buf][e][l] = sacc;
+                }
+            }
+        }
+        // (2) stage the next node's block, prefetch the one after, and the next X column
+        store_block(buf ^ 1);
+        fetch_block(x + 2);
+        fetch_plain(x + 1);
+        load_col(xw[sf], x + 2);
+        __syncthreads();
+        // (3) apply
+        if (qi >= 0) {
+            double acc[2][MW];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int c = 0; c < MW; ++c) acc[i][c] = 0.0;
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+                const int dx = o % 3, dy = o / 3;
+                const double (&col)[3][2][MW] = dx == 0 ? xw[sp] : (dx == 1 ? xw[sc] : xw[sn]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const double kt = kt_s[buf][(o * 2 + i) * 2 + j][l];
+#pragma unroll
+                        for (int c = 0; c < MW; ++c) acc[i][c] = fma(kt, col[dy][j][c], acc[i][c]);
+                    }
+            }
+            const int64_t q = gq + qi;
+            const bool own = (umask[q] >> l) & 1;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int c = 0; c < MW; ++c) Y[((q * 2 + i) * m + r0 + c) * LAT_WAVE + l] = own ? acc[i][c] : 0.0;
+        }
+    };
+    // prologue: window columns x0-1, x0, x0+1; block of node x0 staged, x0+1 in flight; plain entries of x0
+    // (slot of column c is (c - x0 + 1) % 4 within the segment; the LDS parity follows x)
+    load_col(xw[0], xs0 - 1);
+    load_col(xw[1], xs0);
+    load_col(xw[2], xs0 + 1);
+    fetch_block(xs0);
+    store_block(xs0 & 1);
+    fetch_block(xs0 + 1);
+    fetch_plain(xs0);
+    __syncthreads();
+    int x = xs0;
+    for (; x + 3 < xs1; x += 4) {
+        step(x, 0, 1, 2, 3);
+        step(x + 1, 1, 2, 3, 0);
+        step(x + 2, 2, 3, 0, 1);
+        step(x + 3, 3, 0, 1, 2);
+    }
+    if (x < xs1) step(x, 0, 1, 2, 3);
+    if (x + 1 < xs1) step(x + 1, 1, 2, 3, 0);
+    if (x + 2 < xs1) step(x + 2, 2, 3, 0, 1);
+}
+
 // Adjoint forms: partial sums over a run of nodes of G_ik = sum_{a,o,i,j} K_k[a,o,i,j] W_i[a,o,i,j],
 // W_i[a,o,i,j] = sum_r Ybar_i[a,i,r] X_i[a+o,j,r].  Output [chunk][lane][cap].
+constexpr int FORM_MC = 8;
+
 template <int DIM, int NR>
-__global__ __launch_bounds__(256) void k_forms(ApplyArgs A)
+__global__ __launch_bounds__(256) void k_forms(ApplyArgs A, const int32_t *__restrict__ goff,
+                                               const int32_t *__restrict__ unode, const int32_t *__restrict__ unbr,
+                                               const uint64_t *__restrict__ umask, const double *__restrict__ K,
+                                               const double *__restrict__ X, const double *__restrict__ Ybar,
+                                               double *__restrict__ part)
 {
     using G = Geo<DIM>;
     constexpr int E = G::E;
-    const int wave = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(lat_xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63;
     const int g = wave / A.chunks_per_group, ch = wave % A.chunks_per_group;
     if (g >= (int)(A.ld / LAT_WAVE)) return;
-    const int q0 = A.goff[g] + ch * A.nch;
-    const int q1 = min(A.goff[g + 1], q0 + A.nch);
+    const int q0 = goff[g] + ch * A.nch;
+    const int q1 = min(goff[g + 1], q0 + A.nch);
     const int64_t p = (int64_t)g * LAT_WAVE + l;
     const int m = A.m;
+    const int cap = A.cap;
     double gk[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) gk[k] = 0.0;
     for (int q = q0; q < q1; ++q) {
-        const int a = A.unode[q];
-        if (!((A.umask[q] >> l) & 1)) continue;          // Ybar only counts at owned DOFs
-        for (int o = 0; o < G::NO; ++o) {
-            const int nb = A.unbr[(int64_t)q * G::NO + o];
-            if (nb < 0 || !((A.umask[nb] >> l) & 1)) continue;
+        const int a = unode[q];
+        if (!((umask[q] >> l) & 1)) continue;          // Ybar only counts at owned DOFs
+        for (int r0 = 0; r0 < m; r0 += FORM_MC) {
+            const int mc = min(FORM_MC, m - r0);
+            double yb[DIM][FORM_MC];
 #pragma unroll
             for (int i = 0; i < DIM; ++i)
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) {
-                    double w = 0.0;
-                    for (int r = 0; r < m; ++r)
-                        w = fma(A.Ybar[(((int64_t)q * DIM + i) * m + r) * LAT_WAVE + l],
-                                A.X[(((int64_t)nb * DIM + j) * m + r) * LAT_WAVE + l], w);
-                    const double *kp = A.K + ((int64_t)a * E + (o * DIM + i) * DIM + j) * A.cap;
+                for (int r = 0; r < FORM_MC; ++r)
+                    yb[i][r] = r < mc ? Ybar[(((int64_t)q * DIM + i) * m + r0 + r) * LAT_WAVE + l] : 0.0;
+            for (int o = 0; o < G::NO; ++o) {
+                const int nb = unbr[(int64_t)q * G::NO + o];
+                if (nb < 0 || !((umask[nb] >> l) & 1)) continue;
+                double xv[DIM][FORM_MC];
 #pragma unroll
-                    for (int k = 0; k < NR; ++k)
-                        if (k < A.n_r) gk[k] = fma(w, kp[k], gk[k]);
-                }
+                for (int j = 0; j < DIM; ++j)
+#pragma unroll
+                    for (int r = 0; r < FORM_MC; ++r)
+                        xv[j][r] = r < mc ? X[(((int64_t)nb * DIM + j) * m + r0 + r) * LAT_WAVE + l] : 0.0;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                    for (int j = 0; j < DIM; ++j) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int r = 0; r < FORM_MC; ++r) w = fma(yb[i][r], xv[j][r], w);
+                        const double *kp = K + ((int64_t)a * E + (o * DIM + i) * DIM + j) * cap;
+#pragma unroll
+                        for (int k = 0; k < NR; ++k) gk[k] = fma(w, kp[k], gk[k]);
+                    }
+            }
         }
     }
 #pragma unroll
-    for (int k = 0; k < NR; ++k)
-        if (k < A.cap) A.Y[((int64_t)ch * A.ld + p) * A.cap + k] = gk[k];
-    for (int k = NR; k < A.cap; ++k) A.Y[((int64_t)ch * A.ld + p) * A.cap + k] = 0.0;
+    for (int k = 0; k < NR; ++k) part[((int64_t)ch * A.ld + p) * cap + k] = gk[k];
+    for (int k = NR; k < cap; ++k) part[((int64_t)ch * A.ld + p) * cap + k] = 0.0;
 }
 
 __global__ void k_alpha_il(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
@@ -181,21 +391,31 @@ __global__ void k_forms_scatter(int64_t ld, int cap, const int32_t *__restrict__
     for (int k = 0; k < cap; ++k) out[(int64_t)c * cap + k] = f[p * cap + k];
 }
 
-// direct Lame part: bar_{s_k} = sum_i alpha_ik G_ik (ascending canonical i), zero elsewhere
-__global__ void k_direct_lame(int64_t ncells, int cap, int n_r, const int32_t *__restrict__ S,
-                              const int32_t *__restrict__ lane, const double *__restrict__ alpha,
-                              const double *__restrict__ f, double *__restrict__ bar)
+// direct Lame part: bar_{s_k} = sum_i alpha_ik G_ik, zero for non-principal cells.
+__global__ void k_zero_vec(int64_t n, double *__restrict__ x)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
-    double v = 0.0;
-    for (int k = 0; k < n_r; ++k) {
-        if (S[k] != c) continue;
-        double s = 0.0;
-        for (int64_t i = 0; i < ncells; ++i) s = fma(alpha[i * cap + k], f[(int64_t)lane[i] * cap + k], s);
-        v += s;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+// one workgroup per slot k: strided partial sums over the cells (canonical order), then a
+// fixed-shape tree in LDS (deterministic)
+__global__ __launch_bounds__(256) void k_direct_lame(int64_t ncells, int cap, const int32_t *__restrict__ S,
+                                                     const int32_t *__restrict__ lane,
+                                                     const double *__restrict__ alpha,
+                                                     const double *__restrict__ f, double *__restrict__ bar)
+{
+    __shared__ double sh[256];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < ncells; i += 256) s = fma(alpha[i * cap + k], f[(int64_t)lane[i] * cap + k], s);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
     }
-    bar[c] = v;
+    if (threadIdx.x == 0) bar[S[k]] = sh[0];
 }
 
 template <int DIM, int MC, int MODE>
@@ -203,10 +423,13 @@ lat_status launch_apply_nr(const ApplyArgs &A, int nwaves, hipStream_t s)
 {
     dim3 grid((unsigned)lat_cdiv(nwaves, 4)), block(256);
     const int nr = A.n_r;
-    if (MODE == 2 || nr <= 8) hipLaunchKernelGGL((k_apply<DIM, MC, 8, MODE>), grid, block, 0, s, A);
-    else if (nr <= 16) hipLaunchKernelGGL((k_apply<DIM, MC, 16, MODE>), grid, block, 0, s, A);
-    else if (nr <= 32) hipLaunchKernelGGL((k_apply<DIM, MC, 32, MODE>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_apply<DIM, MC, 64, MODE>), grid, block, 0, s, A);
+#define APPLY(NRV) hipLaunchKernelGGL((k_apply<DIM, MC, NRV, MODE>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
+                                      A.umask, A.K, A.alpha_il, A.X, A.Y)
+    if (MODE == 2 || nr <= 8) APPLY(8);
+    else if (nr <= 16) APPLY(16);
+    else if (nr <= 32) APPLY(32);
+    else APPLY(64);
+#undef APPLY
     LAT_LAUNCH_CHECK();
     return LAT_OK;
 }
@@ -222,6 +445,38 @@ lat_status launch_apply(const ApplyArgs &A, int nwaves, hipStream_t s)
     return launch_apply_nr<DIM, 1, MODE>(A, nwaves, s);
 }
 
+template <int MW, int MODE>
+lat_status launch_rowwalk_nr(const lat_plan *P, const ApplyArgs &A, hipStream_t s)
+{
+    ApplyArgs B = A;
+    // enough walks to fill the chip in whole waves of workgroups: split rows into x-segments
+    B.nseg = P->ngroups * P->nn >= 1024 ? 1 : (P->nn >= 16 ? 2 : 1);
+    dim3 grid((unsigned)(P->ngroups * P->nn * B.nseg)), block(512);
+#define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE>), grid, block, 0, s, B, P->goff, P->uidx, P->umask, A.K, \
+                                   A.alpha_il, A.X, A.Y)
+    if (MODE == 2 || A.n_r <= 8) RW(8);
+    else if (A.n_r <= 16) RW(16);
+    else if (A.n_r <= 32) RW(32);
+    else RW(64);
+#undef RW
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
+template <int MW>
+lat_status launch_rowwalk_mode(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
+{
+    if (mode == 0) return launch_rowwalk_nr<MW, 0>(P, A, s);
+    if (mode == 1) return launch_rowwalk_nr<MW, 1>(P, A, s);
+    return launch_rowwalk_nr<MW, 2>(P, A, s);
+}
+
+lat_status launch_rowwalk(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
+{
+    if (A.m == 16) return launch_rowwalk_mode<2>(P, A, mode, s);
+    return launch_rowwalk_mode<1>(P, A, mode, s);
+}
+
 ApplyArgs base_args(const lat_plan *P, int m, int nch)
 {
     ApplyArgs A{};
@@ -232,11 +487,12 @@ ApplyArgs base_args(const lat_plan *P, int m, int nch)
 }
 
 constexpr int APPLY_NODES_PER_WAVE = 4;
-constexpr int FORM_NODES_PER_WAVE = 64;
+constexpr int FORM_NODES_PER_WAVE = 8;
 
 lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, const double *alpha, const double *X,
                      double *Y, int m, hipStream_t s)
 {
+    if (P->npacked == 0) return LAT_OK;              // no owned DOF anywhere: nothing to write
     ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
     A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
     if (mode != 2) {
@@ -246,6 +502,7 @@ lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, cons
         A.alpha_il = P->alpha_il;
     }
     const int nwaves = P->ngroups * A.chunks_per_group;
+    if (P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3) return launch_rowwalk(P, A, mode, s);
     if (P->dim == 2) {
         if (mode == 0) return launch_apply<2, 0>(A, nwaves, s);
         if (mode == 1) return launch_apply<2, 1>(A, nwaves, s);
@@ -265,16 +522,19 @@ lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *
     if (A.chunks_per_group > P->napc) return LAT_E_SHAPE;
     const int nwaves = P->ngroups * A.chunks_per_group;
     dim3 grid((unsigned)lat_cdiv(nwaves, 4)), block(256);
+#define FORMS1(D, NRV) hipLaunchKernelGGL((k_forms<D, NRV>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, A.umask, \
+                                           A.K, A.X, A.Ybar, A.Y)
 #define FORMS(D)                                                                                   \
     do {                                                                                           \
-        if (n_r <= 8) hipLaunchKernelGGL((k_forms<D, 8>), grid, block, 0, s, A);                   \
-        else if (n_r <= 16) hipLaunchKernelGGL((k_forms<D, 16>), grid, block, 0, s, A);            \
-        else if (n_r <= 32) hipLaunchKernelGGL((k_forms<D, 32>), grid, block, 0, s, A);            \
-        else hipLaunchKernelGGL((k_forms<D, 64>), grid, block, 0, s, A);                           \
+        if (n_r <= 8) FORMS1(D, 8);                                                                \
+        else if (n_r <= 16) FORMS1(D, 16);                                                         \
+        else if (n_r <= 32) FORMS1(D, 32);                                                         \
+        else FORMS1(D, 64);                                                                        \
     } while (0)
     if (P->dim == 2) FORMS(2);
     else FORMS(3);
 #undef FORMS
+#undef FORMS1
     LAT_LAUNCH_CHECK();
     return lat_tree_reduce(P->form_part, A.chunks_per_group, P->ld * P->cap, 0, out_pl, P->g_t1, P->g_t2, s);
 }
@@ -284,12 +544,14 @@ lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *
 extern "C" {
 
 lat_status lat_apply_combo(const lat_plan *P, const double *K, int32_t n_r, const double *alpha, const double *X,
-                           double *Y, int32_t m, lat_prec prec, int32_t transpose, hipStream_t stream)
+                           double *Y, int32_t m, lat_prec prec, double refine_tol, int32_t transpose,
+                           hipStream_t stream)
 {
     if (!P || !K || !alpha || !X || !Y || m < 1) return LAT_E_ARG;
     if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
-    if (prec != LAT_F64) return LAT_E_ARG;
-    return run_apply(P, transpose ? 1 : 0, K, n_r, alpha, X, Y, m, stream);
+    if (prec == LAT_F64) return run_apply(P, transpose ? 1 : 0, K, n_r, alpha, X, Y, m, stream);
+    if ((prec != LAT_F32 && prec != LAT_BF16) || transpose) return LAT_E_ARG;
+    return lat_apply_lowp(P, K, n_r, alpha, X, Y, m, prec, refine_tol, stream);
 }
 
 lat_status lat_apply_plain(const lat_plan *P, const double *plain_ops, const double *X, double *Y, int32_t m,
@@ -320,8 +582,11 @@ lat_status lat_apply_combo_adjoint(const lat_plan *P, const double *K, const dou
     for (int t = 0; t < 2; ++t) {
         if (!bars[t]) continue;
         if ((st = run_forms(P, parts[t], n_r, X, Ybar, m, P->form_out, stream)) != LAT_OK) return st;
-        hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)lat_cdiv(P->ncells, 256)), dim3(256), 0, stream, P->ncells,
-                           P->cap, n_r, S, P->lane, alpha, P->form_out, bars[t]);
+        hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)lat_cdiv(P->ncells, 256)), dim3(256), 0, stream, P->ncells,
+                           bars[t]);
+        if (n_r > 0)
+            hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)n_r), dim3(256), 0, stream, P->ncells, P->cap, S, P->lane,
+                               alpha, P->form_out, bars[t]);
         LAT_LAUNCH_CHECK();
     }
     return LAT_OK;

@@ -63,6 +63,13 @@ struct lat_plan {
     double *aa_gath = nullptr;     // [nsnap][cap] uniform operand (Z^T or principal columns)
     double *aa_part = nullptr;     // partials for the alpha adjoint
     int64_t aa_nchunk = 0;
+    int aa_rows = 4096;            // snapshot rows per alpha-adjoint chunk
+    // reduced-precision ROM apply
+    int EP;                        // stencil entries padded to a multiple of 16
+    uint16_t *lp_kslice = nullptr; // [3][nloc][EP][64] bf16 slices of a principal stack
+    uint16_t *lp_cslice = nullptr; // [3][ld][64] bf16 slices of the coefficients (plan order)
+    float *lp_kf32 = nullptr;      // [nloc][E][cap] FP32 principal stack
+    float *lp_cf32 = nullptr;      // [cap][ld] FP32 coefficients
 };
 
 #define LAT_HIP(call)                                                        \
@@ -80,6 +87,16 @@ struct lat_plan {
 static inline int lat_ipow(int b, int e) { int r = 1; while (e-- > 0) r *= b; return r; }
 static inline int64_t lat_cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  This maps the
+// hardware block index to a logical one so that every XCD receives a contiguous range of logical
+// blocks: neighbouring node chunks, whose stencils read the same vector entries, share an L2.
+// A bijection on [0, n).
+__device__ __forceinline__ int lat_xcd_block(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7, s = b >> 3;
+    return x * q + (x < r ? x : r) + s;
+}
+
 // Device status word helpers.
 __device__ inline void lat_flag(int32_t *st, int code, int cell)
 {
@@ -94,3 +111,7 @@ __device__ inline void lat_flag(int32_t *st, int code, int cell)
 // sum (op 0) or max (op 1); result [ld] in out.  Uses t1/t2 as scratch ([ceil(nrows/256)][ld]).
 lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1,
                            double *t2, hipStream_t s);
+
+// Reduced-precision ROM apply (defined in lat_lowp.hip).
+lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X, double *Y,
+                          int m, int prec, double refine_tol, hipStream_t s);

@@ -355,7 +355,8 @@ void free_plan(lat_plan *P)
                     P->dm_gid, P->dm_bsum, P->goff,
                     P->unode, P->unbr, P->umask, P->uidx, P->u_cil, P->w_part, P->w_part2, P->g_sq, P->g_inf,
                     P->g_dot, P->g_t1, P->g_t2, P->v_sq, P->v_inf, P->v_beta, P->v_nu, P->beta_pl, P->zeta,
-                    P->ictl, P->dctl, P->form_part, P->form_out, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part};
+                    P->ictl, P->dctl, P->form_part, P->form_out, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part,
+                    P->lp_kslice, P->lp_cslice, P->lp_kf32, P->lp_cf32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P;
@@ -409,7 +410,9 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     }
     if (P->nbg >= (int64_t)INT32_MAX || P->ncells >= (int64_t)INT32_MAX / 64) { delete P; return LAT_E_ARG; }
     P->nsnap = (int64_t)P->nloc * P->E;
-    P->cap = cap;
+    P->cap = 8;                                     // stride of every [..][cap] array: a power of two >= cap
+    while (P->cap < cap) P->cap *= 2;
+    cap = P->cap;
     LAT_HIP(hipGetDevice(&P->device));
     lat_status st;
 #define ALLOC(ptr, n) do { if ((st = dalloc(&(ptr), (size_t)(n))) != LAT_OK) { free_plan(P); return st; } } while (0)
@@ -541,9 +544,12 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     HCHK(hipGetLastError());
     // ---- workspace
     P->nchunk = lat_cdiv(P->nsnap, LAT_CHUNK);
-    P->napc = (int)lat_cdiv(std::max(P->maxunion, 1), 64);          // 64 packed nodes per adjoint chunk
+    P->napc = (int)lat_cdiv(std::max(P->maxunion, 1), 8);           // 8 packed nodes per adjoint chunk
     int64_t tree_rows = std::max<int64_t>(lat_cdiv(std::max<int64_t>(P->nchunk, nloc), LAT_TREE), 1);
-    P->aa_nchunk = lat_cdiv(P->nsnap, 4096);
+    // rows per chunk of the alpha-adjoint contractions: enough workgroups to fill the chip
+    P->aa_rows = 128;
+    while (P->aa_rows < 4096 && lat_cdiv(P->nsnap, P->aa_rows * 2) * lat_cdiv(ld, 256) >= 4096) P->aa_rows *= 2;
+    P->aa_nchunk = lat_cdiv(P->nsnap, P->aa_rows);
     int64_t tree_elems = std::max<int64_t>(tree_rows * ld, lat_cdiv(P->napc, LAT_TREE) * ld * cap);
     tree_elems = std::max<int64_t>(tree_elems, lat_cdiv(P->aa_nchunk, LAT_TREE) * ld * cap);
     ALLOC(P->u_cil, nloc * dim * ld);
@@ -567,6 +573,11 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     ALLOC(P->aa_q, (int64_t)cap * ld * 2);          // q, v                  [2][ld][cap]
     ALLOC(P->aa_gath, P->nsnap * cap);              // uniform operand       [nsnap][cap]
     ALLOC(P->aa_part, P->aa_nchunk * ld * cap);
+    P->EP = dim == 2 ? 48 : 3 * 96;                 // stencil planes padded to 16-row matrix tiles
+    ALLOC(P->lp_kslice, 3 * nloc * P->EP * 64);
+    ALLOC(P->lp_cslice, 3 * ld * 64);
+    ALLOC(P->lp_kf32, nloc * P->E * cap);
+    ALLOC(P->lp_cf32, (int64_t)cap * ld);
     HCHK(hipStreamSynchronize(stream));
 #undef ALLOC
 #undef HCHK

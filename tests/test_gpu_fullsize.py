@@ -1,0 +1,116 @@
+"""GPU parity at the workloads' full sizes, on sampled cells the oracle computes one by one,
+plus properties that hold at any size (orthonormal basis, certified decomposition, alpha as
+least squares).  Launch configuration as in the benchmark."""
+import numpy as np
+import pytest
+import torch
+
+import lattice as L
+import oracle as O
+from gpu_common import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_full(cfg, m, sample_n=12, seed=0):
+    from paper_2603_10741_amd import binding as B
+    dev = torch.device("cuda:0")
+    print(f"[fullsize] {cfg.name} cells={cfg.n_cells} m={m}", flush=True)
+    keep = L.make_keep(cfg)
+    mu, lam = L.make_material(cfg)
+    u_bg = L.make_displacement(cfg)
+    P = B.Plan(cfg.dim, cfg.ncell, cfg.nel, keep, cap=cfg.cap)
+    l2g_g, nact_g, g2bg_g, perm = P.dofmap()
+    l2g, nact, g2bg = O.dofmap(cfg.dim, cfg.ncell, cfg.nel, keep)
+    assert np.array_equal(l2g_g.cpu().numpy(), l2g)
+    assert np.array_equal(g2bg_g.cpu().numpy(), g2bg)
+    ug = torch.from_numpy(u_bg).to(dev)[g2bg_g].contiguous()
+    mu_t, lam_t = torch.from_numpy(mu).to(dev), torch.from_numpy(lam).to(dev)
+    P.reset_status()
+    r = P.residual_tangent(ug, mu_t, lam_t, f=True, energy=True, snap=True, plain=True)
+    T0 = r["snap"].clone()
+    g = P.select_principal(r["snap"], cfg.tol, keep_Z=True)
+    code, _ = P.check_status()
+    n_r = int(g["n_r"].item())
+    ops = P.principal_ops(ug, mu_t, lam_t, g["S"], n_r)
+    rng = np.random.default_rng(seed)
+    S = g["S"].cpu().numpy()[:n_r]
+    sample = np.unique(np.concatenate([rng.choice(cfg.n_cells, sample_n, replace=False), S[:4]]))
+    uloc = O.gather_local(u_bg[g2bg], l2g[sample])
+    return dict(P=P, cfg=cfg, keep=keep, mu=mu, lam=lam, ug=ug, mu_t=mu_t, lam_t=lam_t, r=r, T0=T0, g=g, n_r=n_r,
+                ops=ops, S=S, sample=sample, l2g=l2g, g2bg=g2bg, u_bg=u_bg, uloc_s=uloc, code=code, dev=dev)
+
+
+def _check(d, m):
+    P, cfg = d["P"], d["cfg"]
+    dim, nel = cfg.dim, cfg.nel
+    sample, S, n_r = d["sample"], d["S"], d["n_r"]
+    # snapshots and forces of sampled cells against the oracle, cell by cell
+    lanes = P.dofmap()[3].cpu().numpy()
+    lane_of = np.empty(cfg.n_cells, np.int64); lane_of[lanes[lanes >= 0]] = np.nonzero(lanes >= 0)[0]
+    T0 = d["T0"].view(P.nsnap, P.ld)
+    f = d["r"]["f"].view(P.nloc * dim, P.ld)
+    for t, c in enumerate(sample):
+        oc = O.cell_eval(dim, nel, d["keep"][c], d["uloc_s"][t], d["mu"][c], d["lam"][c])
+        Tc = T0[:, int(lane_of[c])].cpu().numpy()
+        assert np.abs(Tc - oc["stencil"]).max() <= 1e-12 * np.abs(oc["stencil"]).max()
+        fc = f[:, int(lane_of[c])].cpu().numpy().reshape(-1, dim)
+        assert np.abs(fc - oc["f"]).max() <= 1e-12 * max(np.abs(oc["f"]).max(), 1e-300)
+        assert abs(d["r"]["energy"][c].item() - oc["energy"]) <= 1e-12 * abs(oc["energy"])
+    # greedy properties at full size
+    g = d["g"]
+    Z = g["Z"][:n_r]
+    G = Z @ Z.T
+    # modified Gram-Schmidt keeps orthogonality to about u * cond(T_S); cond <= 1/tol = 1e8 here
+    assert torch.max(torch.abs(G - torch.eye(n_r, dtype=G.dtype, device=G.device))).item() <= 1e-8
+    beta = g["beta"][:, :n_r]
+    nu = g["nu"]
+    idx = torch.from_numpy(sample).to(d["dev"]).long()
+    cols = torch.from_numpy(lane_of[sample]).to(d["dev"]).long()
+    Ts = T0[:, cols].T                                              # sampled snapshots [n_sample][n_snap]
+    rec = nu[idx, None] * (beta[idx] @ Z)
+    err = torch.max(torch.abs(Ts - rec), dim=1).values
+    ach = g["achieved"].item()
+    assert torch.all(err <= ach * nu[idx] * (1 + 1e-6) + 1e-14 * nu[idx]).item()
+    if d["code"] != 7:
+        assert ach <= cfg.tol
+    else:
+        assert n_r == cfg.cap
+    # alpha equals the least-squares coordinates in the principal snapshots (sampled cells)
+    TS = T0[:, torch.from_numpy(lane_of[S]).to(d["dev"]).long()]   # [n_snap][n_r]
+    ls = torch.linalg.lstsq(TS, Ts.T).solution.T
+    assert rel(g["alpha"][idx, :n_r].cpu().numpy(), ls.cpu().numpy()) <= 1e-7
+    del Ts, TS, rec
+    # ROM and plain applies on sampled cells against the oracle (same S and alpha)
+    X = L.make_rhs(cfg, m=m)
+    Xp = P.pack(torch.from_numpy(X).to(d["dev"]), m)
+    Y = P.unpack(P.apply_combo(d["ops"]["K"], n_r, g["alpha"], Xp, m), m)[idx].cpu().numpy()
+    Yp = P.unpack(P.apply_plain(d["r"]["plain"], Xp, m), m)[idx].cpu().numpy()
+    uloc_S = O.gather_local(d["u_bg"][d["g2bg"]], d["l2g"][S])
+    Kp = np.stack([O.cell_eval(dim, nel, d["keep"][s], uloc_S[t], d["mu"][s], d["lam"][s])["stencil"]
+                   for t, s in enumerate(S)])
+    alpha = g["alpha"].cpu().numpy()
+    Yo = O.combo_apply(dim, nel, Kp, alpha[sample], d["l2g"][sample], X[sample])
+    assert rel(Y, Yo) <= 1e-10
+    Ks = np.stack([O.cell_eval(dim, nel, d["keep"][c], d["uloc_s"][t], d["mu"][c], d["lam"][c])["stencil"]
+                   for t, c in enumerate(sample)])
+    Ypo = O.plain_apply(dim, nel, Ks, d["l2g"][sample], X[sample])
+    assert rel(Yp, Ypo) <= 1e-10
+
+
+def test_bcc_10x10x10_full():
+    cfg = L.config(2)
+    d = _run_full(cfg, cfg.m)
+    _check(d, cfg.m)
+
+
+def test_hole_32x32_full():
+    cfg = L.config(1)
+    d = _run_full(cfg, cfg.m)
+    _check(d, cfg.m)
+
+
+def test_mixed_20x20x20_full():
+    cfg = L.config(4)
+    d = _run_full(cfg, 4, sample_n=8)
+    _check(d, 4)
