@@ -20,17 +20,22 @@ enum { D_RHO = 0, D_ACH = 1 };
 
 // ---------------------------------------------------------------------------- tree reduction
 // in [nrows][ld] -> out [ceil(nrows/256)][ld]; blockDim = 256 = 16 lanes x 16 row slots.
-__global__ __launch_bounds__(256) void k_tree(const double *__restrict__ in, int64_t nrows, int64_t ld, int op,
-                                              double *__restrict__ out)
+// A second array (in2 -> out2, operation op2) may be reduced in the same launch.  When the
+// launch produces the final value (one block of rows) it is written at out[p * ostride + ooff].
+struct TreeIO {
+    const double *in;
+    double *out;
+    int op;
+};
+
+__device__ __forceinline__ void tree_block(double (*sh)[17], const TreeIO &io, int64_t nrows, int64_t ld, int64_t p,
+                                           int lx, int ry, int64_t ostride, int64_t ooff, bool final_level)
 {
-    __shared__ double sh[LAT_TREE][17];
-    const int lx = threadIdx.x & 15, ry = threadIdx.x >> 4;
-    const int64_t p = (int64_t)blockIdx.x * 16 + lx;
     const int64_t r0 = (int64_t)blockIdx.y * LAT_TREE;
     const int n0 = (int)((nrows - r0) < LAT_TREE ? (nrows - r0) : LAT_TREE);
     for (int t = ry; t < LAT_TREE; t += 16) {
         double v = 0.0;
-        if (t < n0 && p < ld) v = in[(r0 + t) * ld + p];
+        if (t < n0 && p < ld) v = io.in[(r0 + t) * ld + p];
         sh[t][lx] = v;
     }
     __syncthreads();
@@ -43,7 +48,7 @@ __global__ __launch_bounds__(256) void k_tree(const double *__restrict__ in, int
             const int k = ry + 16 * t;
             if (k < half) {
                 const double x = sh[2 * k][lx], y = sh[2 * k + 1][lx];
-                vals[t] = op == 0 ? x + y : fmax(x, y);
+                vals[t] = io.op == 0 ? x + y : fmax(x, y);
             }
         }
         const double tail = (n & 1) ? sh[n - 1][lx] : 0.0;
@@ -57,7 +62,22 @@ __global__ __launch_bounds__(256) void k_tree(const double *__restrict__ in, int
         __syncthreads();
         n = half + (n & 1);
     }
-    if (ry == 0 && p < ld) out[(int64_t)blockIdx.y * ld + p] = sh[0][lx];
+    if (ry == 0 && p < ld) {
+        if (final_level) io.out[p * ostride + ooff] = sh[0][lx];
+        else io.out[(int64_t)blockIdx.y * ld + p] = sh[0][lx];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_tree(TreeIO a, TreeIO b, int two, int64_t nrows, int64_t ld, int64_t ostride,
+                                              int64_t ooff, int final_level, const int32_t *__restrict__ skip)
+{
+    __shared__ double sh[LAT_TREE][17];
+    if (skip && skip[0]) return;
+    const int lx = threadIdx.x & 15, ry = threadIdx.x >> 4;
+    const int64_t p = (int64_t)blockIdx.x * 16 + lx;
+    tree_block(sh, a, nrows, ld, p, lx, ry, ostride, ooff, final_level);
+    if (two) tree_block(sh, b, nrows, ld, p, lx, ry, 1, 0, final_level);
 }
 
 // ---------------------------------------------------------------------------- greedy passes
@@ -78,7 +98,10 @@ __global__ __launch_bounds__(256) void k_sq(const double *__restrict__ T, int64_
     psq[b * ld + p] = s;
 }
 
-// Delta_0 = t / ||t||_2 (IEEE division; zero snapshot -> 0) with sq / inf partials of Delta_0
+// Delta_0 = t / ||t||_2 (IEEE division; zero snapshot -> 0) with sq / inf partials of Delta_0.
+// The chunk is read in register batches before it is written back (the same column is both
+// read and written, so batching is what lets the loads run ahead of the stores).
+constexpr int GB = 16;
 __global__ __launch_bounds__(256) void k_normalize(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
                                                    const double *__restrict__ nu, double *__restrict__ psq,
                                                    double *__restrict__ pinf)
@@ -89,12 +112,19 @@ __global__ __launch_bounds__(256) void k_normalize(double *__restrict__ T, int64
     const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
     const double n = nu[p];
     double s = 0.0, m = 0.0;
-#pragma unroll 16
-    for (int64_t j = j0; j < j1; ++j) {
-        const double x = n > 0.0 ? T[j * ld + p] / n : 0.0;
-        T[j * ld + p] = x;
-        s = fma(x, x, s);
-        m = fmax(m, fabs(x));
+    for (int64_t jb = j0; jb < j1; jb += GB) {
+        double v[GB];
+#pragma unroll
+        for (int t = 0; t < GB; ++t) v[t] = jb + t < j1 ? T[(jb + t) * ld + p] : 0.0;
+#pragma unroll
+        for (int t = 0; t < GB; ++t) {
+            if (jb + t < j1) {
+                const double x = n > 0.0 ? v[t] / n : 0.0;
+                T[(jb + t) * ld + p] = x;
+                s = fma(x, x, s);
+                m = fmax(m, fabs(x));
+            }
+        }
     }
     psq[b * ld + p] = s;
     pinf[b * ld + p] = m;
@@ -122,25 +152,32 @@ __global__ __launch_bounds__(256) void k_dot(const double *__restrict__ T, int64
     pdot[b * ld + p] = s;
 }
 
-// Delta <- Delta - beta zeta, with sq / inf partials of the updated Delta
+// Delta <- Delta - beta zeta, with sq / inf partials of the updated Delta (batched like k_normalize)
 __global__ __launch_bounds__(256) void k_update(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
                                                 const double *__restrict__ zeta, const double *__restrict__ beta,
-                                                const int32_t *__restrict__ ictl, double *__restrict__ psq,
-                                                double *__restrict__ pinf)
+                                                int64_t bstride, const int32_t *__restrict__ ictl,
+                                                double *__restrict__ psq, double *__restrict__ pinf)
 {
     if (ictl[C_DONE]) return;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t b = chunk_id();
     if (p >= ld || b >= nchunk) return;
     const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
-    const double nb = -beta[p];
+    const double nb = -beta[p * bstride];
     double s = 0.0, m = 0.0;
-#pragma unroll 16
-    for (int64_t j = j0; j < j1; ++j) {
-        const double x = fma(nb, zeta[j], T[j * ld + p]);
-        T[j * ld + p] = x;
-        s = fma(x, x, s);
-        m = fmax(m, fabs(x));
+    for (int64_t jb = j0; jb < j1; jb += GB) {
+        double v[GB];
+#pragma unroll
+        for (int t = 0; t < GB; ++t) v[t] = jb + t < j1 ? T[(jb + t) * ld + p] : 0.0;
+#pragma unroll
+        for (int t = 0; t < GB; ++t) {
+            if (jb + t < j1) {
+                const double x = fma(nb, zeta[jb + t], v[t]);
+                T[(jb + t) * ld + p] = x;
+                s = fma(x, x, s);
+                m = fmax(m, fabs(x));
+            }
+        }
     }
     psq[b * ld + p] = s;
     pinf[b * ld + p] = m;
@@ -291,24 +328,37 @@ dim3 chunk_grid(int64_t ld, int64_t nchunk)
 
 }  // namespace
 
-lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1, double *t2,
-                           hipStream_t s)
+// Pairwise-tree reduction of one or two [nrows][ld] arrays; final values to out[p * ostride + ooff]
+// (second array: out2[p]).  `skip` (device flag, may be NULL) makes every launch return at once.
+static lat_status tree2(const double *in, int op, double *out, int64_t ostride, int64_t ooff, const double *in2, int op2,
+                        double *out2, int64_t nrows, int64_t ld, double *t1, double *t2, double *t3, double *t4,
+                        const int32_t *skip, hipStream_t s)
 {
-    const double *src = in;
+    const double *src = in, *src2 = in2;
     int64_t n = nrows;
-    double *bufs[2] = {t1, t2};
+    double *bufs[2] = {t1, t2}, *bufs2[2] = {t3, t4};
     int which = 0;
     while (true) {
         const int64_t nb = lat_cdiv(n, LAT_TREE);
-        double *dst = nb == 1 ? out : bufs[which];
-        hipLaunchKernelGGL(k_tree, dim3((unsigned)lat_cdiv(ld, 16), (unsigned)nb), dim3(256), 0, s, src, n, ld, op, dst);
+        const bool fin = nb == 1;
+        TreeIO a{src, fin ? out : bufs[which], op};
+        TreeIO b{src2, fin ? out2 : bufs2[which], op2};
+        hipLaunchKernelGGL(k_tree, dim3((unsigned)lat_cdiv(ld, 16), (unsigned)nb), dim3(256), 0, s, a, b, in2 ? 1 : 0, n,
+                           ld, fin ? ostride : (int64_t)1, fin ? ooff : (int64_t)0, fin ? 1 : 0, skip);
         LAT_LAUNCH_CHECK();
-        if (nb == 1) break;
-        src = dst;
+        if (fin) break;
+        src = bufs[which];
+        src2 = bufs2[which];
         n = nb;
         which ^= 1;
     }
     return LAT_OK;
+}
+
+lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1, double *t2,
+                           hipStream_t s)
+{
+    return tree2(in, op, out, 1, 0, nullptr, 0, nullptr, nrows, ld, t1, t2, nullptr, nullptr, nullptr, s);
 }
 
 extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, double tol, int32_t cap, int32_t *S,
@@ -333,8 +383,8 @@ extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, doub
     hipLaunchKernelGGL(k_sqrt, lg, dim3(256), 0, stream, ld, P->v_sq, P->v_nu);
     hipLaunchKernelGGL(k_normalize, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->v_nu, P->g_sq, P->g_inf);
     LAT_LAUNCH_CHECK();
-    if ((st = lat_tree_reduce(P->g_sq, nc, ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
-    if ((st = lat_tree_reduce(P->g_inf, nc, ld, 1, P->v_inf, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+    if ((st = tree2(P->g_sq, 0, P->v_sq, 1, 0, P->g_inf, 1, P->v_inf, nc, ld, P->g_t1, P->g_t2, P->g_t3, P->g_t4,
+                    nullptr, stream)) != LAT_OK) return st;
     for (int it = 0; it <= cap; ++it) {
         hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, stream, ld, P->perm, P->v_inf, P->v_sq, tol, it, cap,
                            P->ictl, P->dctl, S, n_r, dev_status);
@@ -344,13 +394,14 @@ extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, doub
                            P->dctl, P->zeta, Z ? Z + (int64_t)it * ns : nullptr);
         hipLaunchKernelGGL(k_dot, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->ictl, P->g_dot);
         LAT_LAUNCH_CHECK();
-        if ((st = lat_tree_reduce(P->g_dot, nc, ld, 0, P->v_beta, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
-        hipLaunchKernelGGL(k_store_beta, lg, dim3(256), 0, stream, ld, it, P->cap, P->ictl, P->v_beta, P->beta_pl);
-        hipLaunchKernelGGL(k_update, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->v_beta, P->ictl,
-                           P->g_sq, P->g_inf);
+        // beta_i lands directly in its column of the plan-order coordinate matrix
+        if ((st = tree2(P->g_dot, 0, P->beta_pl, P->cap, it, nullptr, 0, nullptr, nc, ld, P->g_t1, P->g_t2, nullptr,
+                        nullptr, P->ictl + C_DONE, stream)) != LAT_OK) return st;
+        hipLaunchKernelGGL(k_update, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->beta_pl + it, P->cap,
+                           P->ictl, P->g_sq, P->g_inf);
         LAT_LAUNCH_CHECK();
-        if ((st = lat_tree_reduce(P->g_sq, nc, ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
-        if ((st = lat_tree_reduce(P->g_inf, nc, ld, 1, P->v_inf, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        if ((st = tree2(P->g_sq, 0, P->v_sq, 1, 0, P->g_inf, 1, P->v_inf, nc, ld, P->g_t1, P->g_t2, P->g_t3, P->g_t4,
+                        P->ictl + C_DONE, stream)) != LAT_OK) return st;
     }
     // R, alpha (canonical order), beta, nu, achieved
     hipLaunchKernelGGL(k_build_R, dim3((unsigned)P->cap), dim3(64), 0, stream, P->cap, P->cap, P->ictl, S, P->lane,

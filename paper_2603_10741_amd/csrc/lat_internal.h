@@ -49,6 +49,7 @@ struct lat_plan {
     double *g_dot = nullptr;       // [nchunk][ld]
     double *g_t1 = nullptr;        // [ceil(max(nchunk,nloc)/256)][ld] tree scratch
     double *g_t2 = nullptr;
+    double *g_t3 = nullptr, *g_t4 = nullptr;   // second-array tree scratch
     double *v_sq = nullptr, *v_inf = nullptr, *v_beta = nullptr, *v_nu = nullptr;   // [ld]
     double *beta_pl = nullptr;     // [ld][cap] plan-order coordinates
     double *zeta = nullptr;        // [nsnap]

@@ -354,7 +354,7 @@ void free_plan(lat_plan *P)
     void *ptrs[] = {P->keep, P->keep_il, P->perm, P->lane, P->l2g, P->l2g_il, P->nact, P->g2bg, P->dm_act, P->dm_flag,
                     P->dm_gid, P->dm_bsum, P->goff,
                     P->unode, P->unbr, P->umask, P->uidx, P->u_cil, P->w_part, P->w_part2, P->g_sq, P->g_inf,
-                    P->g_dot, P->g_t1, P->g_t2, P->v_sq, P->v_inf, P->v_beta, P->v_nu, P->beta_pl, P->zeta,
+                    P->g_dot, P->g_t1, P->g_t2, P->g_t3, P->g_t4, P->v_sq, P->v_inf, P->v_beta, P->v_nu, P->beta_pl, P->zeta,
                     P->ictl, P->dctl, P->form_part, P->form_out, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part,
                     P->lp_kslice, P->lp_cslice, P->lp_kf32, P->lp_cf32};
     for (void *p : ptrs)
@@ -560,6 +560,8 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     ALLOC(P->g_dot, P->nchunk * ld);
     ALLOC(P->g_t1, tree_elems);
     ALLOC(P->g_t2, tree_elems);
+    ALLOC(P->g_t3, tree_elems);
+    ALLOC(P->g_t4, tree_elems);
     ALLOC(P->v_sq, ld); ALLOC(P->v_inf, ld); ALLOC(P->v_beta, ld); ALLOC(P->v_nu, ld);
     ALLOC(P->beta_pl, ld * cap);
     ALLOC(P->zeta, P->nsnap);
