@@ -15,8 +15,10 @@ at most 32 principal cells (tolerance 1e-8).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +31,23 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_apply2d_rw_hole2d_32x32_hbm_traffic.md")
+
+
+def measured_traffic(workload):
+    """HBM bytes per ROM-apply launch from the committed counter summary, or None when that
+    summary was taken on another workload or on a different apply source than the one built."""
+    if workload != "hole2d_32x32_n32_graded" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    sha = re.search(r"lat_apply\.hip\): ([0-9a-f]{64})", text)
+    val = re.search(r"rom_apply traffic bytes per launch: (\d+)", text)
+    src = os.path.join(ROOT, "paper_2603_10741_amd", "csrc", "lat_apply.hip")
+    if not sha or not val or hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+        return None
+    return int(val.group(1))
 
 
 def cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=12.0):
@@ -166,6 +185,7 @@ def main():
     value = dofs_rhs / t_apply / 1e9
     alg_bytes = 16.0 * dofs_rhs + 8.0 * P.ncells * n_r + 8.0 * P.nloc * P.E * n_r
     achieved = alg_bytes / t_apply / 1e9
+    traffic = measured_traffic(cfg.name)
 
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 8
@@ -215,8 +235,8 @@ def main():
                    "right_hand_sides": m, "principal_cap": cfg.cap, "tol": cfg.tol, "n_r": n_r,
                    "active_local_dofs": active_dofs, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_apply (ROM apply)", "algorithmic_bytes_per_launch": int(alg_bytes)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_apply2d_rw<2,32,0> (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(alg_bytes)},
         "cpu_baseline": cpu,
         "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
         "rom_over_plain_speedup": round(t_plain / t_apply, 3),
