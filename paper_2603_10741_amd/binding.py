@@ -13,7 +13,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblat.so")
+# LAT_LIBRARY may name another build of the same ABI (e.g. a tuning variant)
+LIB_PATH = os.environ.get("LAT_LIBRARY") or os.path.join(_HERE, "liblat.so")
 
 LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP = range(8)
 RULE_FULL, RULE_REDUCED = 0, 1

@@ -20,6 +20,8 @@ struct Geo {
     static constexpr int E = NO * DIM * DIM;
 };
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 struct ApplyArgs {
     int nn, m, cap, n_r, nch, chunks_per_group, nseg;
     int64_t ld;
@@ -129,9 +131,12 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A, const int32_t *__res
 // 2D row walk, software pipelined.  One workgroup = one group of 64 cells (lanes) and one node
 // row y; its NW = 8 waves split the right-hand sides (wave w owns MW = m / 8 of them) and walk
 // x = 0..n in step.  Per step (node x):
-//   - each wave combines its share of the node's 36 stencil entries (Ktilde = sum_k alpha_k K_k,
-//     the principal block read as a broadcast from LDS, where it was staged one step earlier) or,
-//     for the plain apply, copies its share of the cell's own stencil, into LDS;
+//   - the node's combined stencil Ktilde[e][cell] = sum_k K_k[e] alpha[k][cell] (36 entries x 64
+//     cells, a dense contraction over the principal cells) is formed on the matrix cores with
+//     v_mfma_f64_16x16x4 from the principal block staged in LDS one step earlier; the 12 tiles of
+//     16 entries x 16 cells go to the 8 waves (cell tile w & 3; entry tiles {0, 2} or {1},
+//     alternating with the node's parity so every wave does 3 tiles per 2 nodes).  For the plain
+//     apply each wave copies its share of the cell's own stencil instead.  Result -> LDS;
 //   - it stages the next node's principal block and issues the loads of X column x+2 into a
 //     4-slot register window (columns x-1 .. x+2 of rows y-1, y, y+1);
 //   - one barrier; then each wave applies the node's 2x2 blocks to its right-hand sides.
@@ -147,7 +152,8 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     constexpr int KB = MODE == 2 ? 1 : E * NR;          // principal block of one node (doubles)
     constexpr int KPT = (KB + NW * 64 - 1) / (NW * 64);  // staged per thread
     __shared__ double kt_s[2][E][64];
-    __shared__ double kb_s[2][MODE == 2 ? 1 : KB];
+    constexpr int KSTR = NR + 1;                        // row stride of a staged block (doubles)
+    __shared__ double kb_s[2][MODE == 2 ? 1 : E * KSTR];
     const int nn = A.nn, nloc = nn * nn, m = A.m, cap = A.cap;
     const int lb = lat_xcd_block(blockIdx.x, gridDim.x);
     const int nseg = A.nseg;                             // each row is walked in nseg x-segments
@@ -160,10 +166,14 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     const int e0 = (w * E) / NW, e1 = ((w + 1) * E) / NW;   // this wave's share of the entries
     const int32_t *ui = uidx + (int64_t)g * nloc;
     const int gq = goff[g];
-    double alpha[MODE == 2 ? 1 : NR];
+    // alpha as the B operand of v_mfma_f64_16x16x4: wave w combines for cells ct*16 .. ct*16+15
+    // (ct = w & 3); lane l holds alpha[k = 4 s + l / 16][cell = ct*16 + l % 16] in aB[s]
+    const int ct = w & 3;
+    double aB[MODE == 2 ? 1 : NR / 4];
     if (MODE != 2) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) alpha[k] = alpha_il[(int64_t)k * A.ld + p];
+        for (int s = 0; s < NR / 4; ++s)
+            aB[s] = alpha_il[(int64_t)(4 * s + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
     }
     // principal-block staging (ROM modes): block[e * NR + k] = K_k[row(e)][ent(e)]
     double kpre[KPT];
@@ -195,7 +205,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 #pragma unroll
         for (int t = 0; t < KPT; ++t) {
             const int idx = tid + t * NW * 64;
-            if (idx < KB) kb_s[buf][idx] = kpre[t];
+            if (idx < KB) kb_s[buf][(idx / NR) * KSTR + idx % NR] = kpre[t];
         }
     };
     // plain mode: this wave's share of the cell's own stencil, one step ahead
@@ -241,12 +251,35 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                 for (int t = 0; t < (E + NW - 1) / NW; ++t)
                     if (e0 + t < e1) kt_s[buf][e0 + t][l] = ppre[t];
             } else {
-                for (int e = e0; e < e1; ++e) {
-                    const double *kb = &kb_s[buf][e * NR];
-                    double sacc = 0.0;
+                // Ktilde[e][cell] = sum_k K[e][k] alpha[k][cell] as 16 x 16 tiles (entries x cells):
+                // 3 entry tiles (the last holds entries 32..35) x 4 cell tiles; wave w takes cell tile
+                // w & 3 and, alternating with the node's parity, entry tiles {0, 2} or {1}
+                const bool heavy = (w < 4) == ((x & 1) == 0);
+                const double *kb = &kb_s[buf][0];
+                const int c16 = ct * 16 + (l & 15);
+                if (heavy) {
+                    v4d c0 = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
+                    const double *r0p = kb + (l & 15) * KSTR + (l >> 4);
+                    const int e2 = 32 + (l & 15) < E ? 32 + (l & 15) : E - 1;
+                    const double *r2p = kb + e2 * KSTR + (l >> 4);
 #pragma unroll
-                    for (int k = 0; k < NR; ++k) sacc = fma(alpha[k], kb[k], sacc);
-                    kt_s[buf][e][l] = sacc;
+                    for (int s2 = 0; s2 < NR / 4; ++s2) {
+                        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(r0p[4 * s2], aB[s2], c0, 0, 0, 0);
+                        c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(r2p[4 * s2], aB[s2], c2, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        kt_s[buf][(l >> 4) + 4 * r][c16] = c0[r];
+                        if ((l >> 4) + 4 * r < E - 32) kt_s[buf][32 + (l >> 4) + 4 * r][c16] = c2[r];
+                    }
+                } else {
+                    v4d c1 = {0.0, 0.0, 0.0, 0.0};
+                    const double *r1p = kb + (16 + (l & 15)) * KSTR + (l >> 4);
+#pragma unroll
+                    for (int s2 = 0; s2 < NR / 4; ++s2)
+                        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(r1p[4 * s2], aB[s2], c1, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) kt_s[buf][16 + (l >> 4) + 4 * r][c16] = c1[r];
                 }
             }
         }
