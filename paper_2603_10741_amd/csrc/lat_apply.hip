@@ -339,6 +339,129 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     if (x + 2 < xs1) step(x + 2, 2, 3, 0, 1);
 }
 
+// 3D ROM apply (and its transpose), formation on the matrix cores.  One workgroup of 4 waves =
+// a run of APPLY3_RUN packed nodes (their group's 64 cells are the lanes).  Per node, in two
+// halves of the 243 stencil entries (APPLY3_EH = 128 entries, 8 tiles of 16):
+//   - formation: Ktilde[e][cell] = sum_k K_k[e] alpha[k][cell], v_mfma_f64_16x16x4 tiles of
+//     16 entries x 16 cells; wave w forms cell tile w for the half's 8 entry tiles (A operand =
+//     the principal block, read per lane from global memory; B operand = alpha, in registers for
+//     the whole run) and writes them to LDS;
+//   - one barrier; apply: wave w takes right-hand sides 4w .. 4w+3 and accumulates
+//     Ktilde[(o,i,j)] X[a+o, j] over the half's entries (X masked to owned neighbour DOFs);
+//   - one barrier (the LDS half is reused).
+// 64 KB of LDS per workgroup: two workgroups per CU, so one's formation overlaps the other's apply.
+constexpr int APPLY3_RUN = 16;
+constexpr int APPLY3_EH = 128;
+
+template <int NR, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply3d_mfma(ApplyArgs A, const int32_t *__restrict__ goff,
+                                                      const int32_t *__restrict__ unode,
+                                                      const int32_t *__restrict__ unbr,
+                                                      const uint64_t *__restrict__ umask,
+                                                      const double *__restrict__ K,
+                                                      const double *__restrict__ alpha_il,
+                                                      const double *__restrict__ X, double *__restrict__ Y,
+                                                      int npacked, const int32_t *__restrict__ qgroup)
+{
+    constexpr int E = 243, NO = 27, LDSR = 65;           // LDS row of 64 cells, padded
+    __shared__ double kt_s[APPLY3_EH * LDSR];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63;
+    const int run = lat_xcd_block(blockIdx.x, gridDim.x);
+    const int q0 = run * APPLY3_RUN;
+    const int q1 = min(npacked, q0 + APPLY3_RUN);
+    const int nn = A.nn, m = A.m, cap = A.cap;
+    const int ct = w;                                    // this wave's cell tile (formation)
+    const int r0 = 4 * w;                                // this wave's right-hand sides (apply)
+    const int nrw = max(0, min(4, m - r0));
+    int gcur = -1;
+    double aB[NR / 4];
+    for (int q = q0; q < q1; ++q) {
+        const int g = qgroup[q];
+        if (g != gcur) {                                 // alpha of this group as the B operand
+            gcur = g;
+#pragma unroll
+            for (int s = 0; s < NR / 4; ++s)
+                aB[s] = alpha_il[(int64_t)(4 * s + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
+        }
+        const int a = unode[q];
+        double acc[3][4];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // ---- formation of entries [128 h, 128 h + 128) for cell tile ct
+            const double *kb[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                int e = (8 * h + t) * 16 + (l & 15);
+                e = e < E ? e : E - 1;
+                int arow = a, ent = e;
+                if (MODE == 1) {         // transposed block K[(a+o, j), (a, i)]
+                    const int o = e / 9, i = (e / 3) % 3, j = e % 3;
+                    const int xn = a % nn + o % 3 - 1, yn = (a / nn) % nn + (o / 3) % 3 - 1, zn = a / (nn * nn) + o / 9 - 1;
+                    const bool in = xn >= 0 && xn < nn && yn >= 0 && yn < nn && zn >= 0 && zn < nn;
+                    arow = in ? xn + nn * (yn + nn * zn) : 0;   // an entry off the grid is never applied
+                    ent = ((NO - 1 - o) * 3 + j) * 3 + i;
+                }
+                kb[t] = K + ((int64_t)arow * E + ent) * cap + (l >> 4);
+            }
+            v4d c[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NR / 4; ++s)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(kb[t][4 * s], aB[s], c[t], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int el = t * 16 + (l >> 4) + 4 * r;          // entry within the half
+                    if (APPLY3_EH * h + el < E) kt_s[el * LDSR + ct * 16 + (l & 15)] = c[t][r];
+                }
+            __syncthreads();
+            // ---- apply the half's entries to this wave's right-hand sides
+            if (nrw > 0) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    if ((o + 1) * 9 <= APPLY3_EH * h || o * 9 >= APPLY3_EH * (h + 1)) continue;
+                    const int nb = unbr[(int64_t)q * NO + o];
+                    if (nb < 0) continue;
+                    const bool nb_own = (umask[nb] >> l) & 1;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        double xv[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = r < nrw ? r0 + r : r0;
+                            const double v = X[(((int64_t)nb * 3 + j) * m + rr) * LAT_WAVE + l];
+                            xv[r] = (nb_own && r < nrw) ? v : 0.0;
+                        }
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            const int e = (o * 3 + i) * 3 + j;
+                            if (e < APPLY3_EH * h || e >= APPLY3_EH * (h + 1)) continue;
+                            const double kt = kt_s[(e - APPLY3_EH * h) * LDSR + l];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) acc[i][r] = fma(kt, xv[r], acc[i][r]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const bool own = (umask[q] >> l) & 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < nrw) Y[(((int64_t)q * 3 + i) * m + r0 + r) * LAT_WAVE + l] = own ? acc[i][r] : 0.0;
+    }
+}
+
 // Adjoint forms: partial sums over a run of nodes of G_ik = sum_{a,o,i,j} K_k[a,o,i,j] W_i[a,o,i,j],
 // W_i[a,o,i,j] = sum_r Ybar_i[a,i,r] X_i[a+o,j,r].  Output [chunk][lane][cap].
 constexpr int FORM_MC = 8;
@@ -510,6 +633,27 @@ lat_status launch_rowwalk(const lat_plan *P, const ApplyArgs &A, int mode, hipSt
     return launch_rowwalk_mode<1>(P, A, mode, s);
 }
 
+lat_status launch_apply3d(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
+{
+    dim3 grid((unsigned)lat_cdiv(P->npacked, APPLY3_RUN)), block(256);
+    const int32_t *qgroup = P->goff + P->ngroups + 1;
+#define A3(NRV, MD) hipLaunchKernelGGL((k_apply3d_mfma<NRV, MD>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
+                                       A.umask, A.K, A.alpha_il, A.X, A.Y, (int)P->npacked, qgroup)
+#define A3M(MD)                          \
+    do {                                 \
+        if (A.n_r <= 8) A3(8, MD);        \
+        else if (A.n_r <= 16) A3(16, MD); \
+        else if (A.n_r <= 32) A3(32, MD); \
+        else A3(64, MD);                  \
+    } while (0)
+    if (mode == 0) A3M(0);
+    else A3M(1);
+#undef A3M
+#undef A3
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
 ApplyArgs base_args(const lat_plan *P, int m, int nch)
 {
     ApplyArgs A{};
@@ -541,6 +685,7 @@ lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, cons
         if (mode == 1) return launch_apply<2, 1>(A, nwaves, s);
         return launch_apply<2, 2>(A, nwaves, s);
     }
+    if (mode != 2 && m <= 16) return launch_apply3d(P, A, mode, s);
     if (mode == 0) return launch_apply<3, 0>(A, nwaves, s);
     if (mode == 1) return launch_apply<3, 1>(A, nwaves, s);
     return launch_apply<3, 2>(A, nwaves, s);
