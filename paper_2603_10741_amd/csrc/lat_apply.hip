@@ -339,126 +339,167 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     if (x + 2 < xs1) step(x + 2, 2, 3, 0, 1);
 }
 
-// 3D ROM apply (and its transpose), formation on the matrix cores.  One workgroup of 4 waves =
-// a run of APPLY3_RUN packed nodes (their group's 64 cells are the lanes).  Per node, in two
-// halves of the 243 stencil entries (APPLY3_EH = 128 entries, 8 tiles of 16):
-//   - formation: Ktilde[e][cell] = sum_k K_k[e] alpha[k][cell], v_mfma_f64_16x16x4 tiles of
-//     16 entries x 16 cells; wave w forms cell tile w for the half's 8 entry tiles (A operand =
-//     the principal block, read per lane from global memory; B operand = alpha, in registers for
-//     the whole run) and writes them to LDS;
-//   - one barrier; apply: wave w takes right-hand sides 4w .. 4w+3 and accumulates
-//     Ktilde[(o,i,j)] X[a+o, j] over the half's entries (X masked to owned neighbour DOFs);
-//   - one barrier (the LDS half is reused).
-// 64 KB of LDS per workgroup: two workgroups per CU, so one's formation overlaps the other's apply.
+// 3D ROM apply (and its transpose), formation on the matrix cores.  One workgroup of 8 waves =
+// a run of APPLY3_RUN packed nodes (their group's 64 cells are the lanes).  A node's 27 stencil
+// offsets are taken in 9 slices of 3 (27 entries, two 16-row tiles); per slice step:
+//   - each wave issues the loads of the X values its right-hand sides need for the slice's three
+//     neighbour nodes (consumed after the barrier, so they overlap the formation);
+//   - formation: Ktilde[e][cell] = sum_k K_k[e] alpha[k][cell] with v_mfma_f64_16x16x4 (A operand =
+//     the principal block slice, staged in LDS; B operand = alpha, in registers); wave w forms
+//     entry tile w / 4 of cell tile w % 4 and writes it to LDS;
+//   - the next slice's principal block (fetched with coalesced loads one step earlier) goes to
+//     LDS and the one after is fetched;
+//   - one barrier; apply: wave w accumulates Ktilde[(o,i,j)] X[a+o, j] for right-hand sides
+//     2w, 2w+1 (X masked to owned neighbour DOFs).
+// Both LDS buffers are double-buffered (33 KB each for 64 principal cells), so one barrier per
+// step suffices and two workgroups fit on a CU.
 constexpr int APPLY3_RUN = 16;
-constexpr int APPLY3_EH = 128;
 
 template <int NR, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_apply3d_mfma(ApplyArgs A, const int32_t *__restrict__ goff,
-                                                      const int32_t *__restrict__ unode,
-                                                      const int32_t *__restrict__ unbr,
-                                                      const uint64_t *__restrict__ umask,
-                                                      const double *__restrict__ K,
-                                                      const double *__restrict__ alpha_il,
-                                                      const double *__restrict__ X, double *__restrict__ Y,
-                                                      int npacked, const int32_t *__restrict__ qgroup)
+__global__ __launch_bounds__(512) void k_apply3d_mfma(
+    ApplyArgs A, const int32_t *__restrict__ goff, const int32_t *__restrict__ unode,
+    const int32_t *__restrict__ unbr, const uint64_t *__restrict__ umask, const double *__restrict__ K,
+    const double *__restrict__ alpha_il, const double *__restrict__ X, double *__restrict__ Y, int npacked,
+    const int32_t *__restrict__ qgroup)
 {
-    constexpr int E = 243, NO = 27, LDSR = 65;           // LDS row of 64 cells, padded
-    __shared__ double kt_s[APPLY3_EH * LDSR];
+    constexpr int E = 243, NO = 27, ES = 27, ER = 32, KR = NR + 1, TR = 65, NSL = 9;
+    constexpr int SPT = (ER * NR + 511) / 512;           // staged values per thread and slice
+    __shared__ double kb_s[2][ER * KR];
+    __shared__ double kt_s[2][ER * TR];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int l = threadIdx.x & 63;
+    const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int run = lat_xcd_block(blockIdx.x, gridDim.x);
     const int q0 = run * APPLY3_RUN;
     const int q1 = min(npacked, q0 + APPLY3_RUN);
+    if (q0 >= q1) return;
     const int nn = A.nn, m = A.m, cap = A.cap;
-    const int ct = w;                                    // this wave's cell tile (formation)
-    const int r0 = 4 * w;                                // this wave's right-hand sides (apply)
-    const int nrw = max(0, min(4, m - r0));
+    const int ct = w & 3, et = w >> 2;                   // formation tile of this wave
+    const int r0 = 2 * w;                                // this wave's right-hand sides (apply)
+    const int nrw = max(0, min(2, m - r0));
+    const int nsl = (q1 - q0) * NSL;
+    // ---- principal block slice sl (node q0 + sl / 9, offsets 3 (sl % 9) ..): coalesced fetch
+    double kpre[SPT];
+    bool kval[SPT];
+    auto fetch = [&](int sl) __attribute__((always_inline)) {
+        const bool live = sl < nsl;
+        const int a = live ? unode[q0 + sl / NSL] : 0;
+        const int h = sl % NSL;
+#pragma unroll
+        for (int t = 0; t < SPT; ++t) {
+            const int idx = tid + 512 * t < ER * NR ? tid + 512 * t : 0;
+            const int el = idx / NR, k = idx % NR;
+            const int e = ES * h + (el < ES ? el : ES - 1);
+            bool valid = live && el < ES;
+            int arow = a, ent = e;
+            if (MODE == 1) {             // transposed block K[(a+o, j), (a, i)]
+                const int o = e / 9, i = (e / 3) % 3, j = e % 3;
+                const int xn = a % nn + o % 3 - 1, yn = (a / nn) % nn + (o / 3) % 3 - 1, zn = a / (nn * nn) + o / 9 - 1;
+                const bool in = xn >= 0 && xn < nn && yn >= 0 && yn < nn && zn >= 0 && zn < nn;
+                valid = valid && in;
+                arow = in ? xn + nn * (yn + nn * zn) : 0;
+                ent = ((NO - 1 - o) * 3 + j) * 3 + i;
+            }
+            kpre[t] = K[((int64_t)arow * E + ent) * cap + k];
+            kval[t] = valid;
+        }
+    };
+    auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int t = 0; t < SPT; ++t) {
+            const int idx = tid + 512 * t;
+            if (idx < ER * NR) kb_s[buf][(idx / NR) * KR + idx % NR] = kval[t] ? kpre[t] : 0.0;
+        }
+    };
+    // neighbour table of node q, one offset per lane: packed index and owner mask
+    auto nbr_load = [&](int q, int &nbv, uint32_t &mlo, uint32_t &mhi) __attribute__((always_inline)) {
+        nbv = (q < q1 && l < NO) ? unbr[(int64_t)q * NO + l] : -1;
+        const uint64_t mk = nbv >= 0 ? umask[nbv] : 0ull;
+        mlo = (uint32_t)mk;
+        mhi = (uint32_t)(mk >> 32);
+    };
     int gcur = -1;
     double aB[NR / 4];
+    int nbv, nbv_n;
+    uint32_t mlo, mhi, mlo_n, mhi_n;
+    nbr_load(q0, nbv, mlo, mhi);
+    fetch(0);
+    store(0);
+    fetch(1);
+    __syncthreads();
     for (int q = q0; q < q1; ++q) {
         const int g = qgroup[q];
         if (g != gcur) {                                 // alpha of this group as the B operand
             gcur = g;
 #pragma unroll
-            for (int s = 0; s < NR / 4; ++s)
-                aB[s] = alpha_il[(int64_t)(4 * s + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
+            for (int s2 = 0; s2 < NR / 4; ++s2)
+                aB[s2] = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
         }
-        const int a = unode[q];
-        double acc[3][4];
+        nbr_load(q + 1, nbv_n, mlo_n, mhi_n);            // next node's table, used one node later
+        double acc[3][2];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
+            for (int r = 0; r < 2; ++r) acc[i][r] = 0.0;
+        const int sl0 = (q - q0) * NSL;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // ---- formation of entries [128 h, 128 h + 128) for cell tile ct
-            const double *kb[8];
+        for (int h = 0; h < NSL; ++h) {
+            const int buf = (sl0 + h) & 1;
+            // (0) X of the slice's neighbour nodes for this wave's right-hand sides (raw)
+            double xv[3][3][2];
+            int nbs[3];
+            bool ownb[3];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                int e = (8 * h + t) * 16 + (l & 15);
-                e = e < E ? e : E - 1;
-                int arow = a, ent = e;
-                if (MODE == 1) {         // transposed block K[(a+o, j), (a, i)]
-                    const int o = e / 9, i = (e / 3) % 3, j = e % 3;
-                    const int xn = a % nn + o % 3 - 1, yn = (a / nn) % nn + (o / 3) % 3 - 1, zn = a / (nn * nn) + o / 9 - 1;
-                    const bool in = xn >= 0 && xn < nn && yn >= 0 && yn < nn && zn >= 0 && zn < nn;
-                    arow = in ? xn + nn * (yn + nn * zn) : 0;   // an entry off the grid is never applied
-                    ent = ((NO - 1 - o) * 3 + j) * 3 + i;
-                }
-                kb[t] = K + ((int64_t)arow * E + ent) * cap + (l >> 4);
+            for (int u = 0; u < 3; ++u) {
+                const int o = 3 * h + u;
+                const int nb = __builtin_amdgcn_readlane(nbv, o);
+                const uint32_t lo = __builtin_amdgcn_readlane(mlo, o), hi = __builtin_amdgcn_readlane(mhi, o);
+                nbs[u] = nb;
+                ownb[u] = ((l < 32 ? lo >> l : hi >> (l - 32)) & 1u) != 0;
+                const int64_t nq = nb >= 0 ? nb : 0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+                        const int rr = r < nrw ? r0 + r : 0;
+                        xv[u][j][r] = X[((nq * 3 + j) * m + rr) * LAT_WAVE + l];
+                    }
             }
-            v4d c[8];
+            // (1) formation of entry tile et of this slice for cell tile ct -> kt_s[buf]
+            {
+                v4d c = {0.0, 0.0, 0.0, 0.0};
+                const double *pa = &kb_s[buf][(16 * et + (l & 15)) * KR + (l >> 4)];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) c[t] = v4d{0.0, 0.0, 0.0, 0.0};
+                for (int s2 = 0; s2 < NR / 4; ++s2) c = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s2], aB[s2], c, 0, 0, 0);
 #pragma unroll
-            for (int s = 0; s < NR / 4; ++s)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(kb[t][4 * s], aB[s], c[t], 0, 0, 0);
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int el = t * 16 + (l >> 4) + 4 * r;          // entry within the half
-                    if (APPLY3_EH * h + el < E) kt_s[el * LDSR + ct * 16 + (l & 15)] = c[t][r];
-                }
+                for (int r = 0; r < 4; ++r) kt_s[buf][(16 * et + (l >> 4) + 4 * r) * TR + ct * 16 + (l & 15)] = c[r];
+            }
+            // (2) stage the next slice, fetch the one after
+            store(buf ^ 1);
+            fetch(sl0 + h + 2);
             __syncthreads();
-            // ---- apply the half's entries to this wave's right-hand sides
+            // (3) apply the slice's 27 entries
             if (nrw > 0) {
 #pragma unroll
-                for (int o = 0; o < NO; ++o) {
-                    if ((o + 1) * 9 <= APPLY3_EH * h || o * 9 >= APPLY3_EH * (h + 1)) continue;
-                    const int nb = unbr[(int64_t)q * NO + o];
-                    if (nb < 0) continue;
-                    const bool nb_own = (umask[nb] >> l) & 1;
+                for (int u = 0; u < 3; ++u) {
+                    if (nbs[u] < 0) continue;
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        double xv[4];
+                    for (int i = 0; i < 3; ++i)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int rr = r < nrw ? r0 + r : r0;
-                            const double v = X[(((int64_t)nb * 3 + j) * m + rr) * LAT_WAVE + l];
-                            xv[r] = (nb_own && r < nrw) ? v : 0.0;
+                        for (int j = 0; j < 3; ++j) {
+                            const double kt = kt_s[buf][((u * 3 + i) * 3 + j) * TR + l];
+#pragma unroll
+                            for (int r = 0; r < 2; ++r) acc[i][r] = fma(kt, ownb[u] ? xv[u][j][r] : 0.0, acc[i][r]);
                         }
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            const int e = (o * 3 + i) * 3 + j;
-                            if (e < APPLY3_EH * h || e >= APPLY3_EH * (h + 1)) continue;
-                            const double kt = kt_s[(e - APPLY3_EH * h) * LDSR + l];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) acc[i][r] = fma(kt, xv[r], acc[i][r]);
-                        }
-                    }
                 }
             }
-            __syncthreads();
         }
         const bool own = (umask[q] >> l) & 1;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 2; ++r)
                 if (r < nrw) Y[(((int64_t)q * 3 + i) * m + r0 + r) * LAT_WAVE + l] = own ? acc[i][r] : 0.0;
+        nbv = nbv_n; mlo = mlo_n; mhi = mhi_n;
     }
 }
 
@@ -635,7 +676,7 @@ lat_status launch_rowwalk(const lat_plan *P, const ApplyArgs &A, int mode, hipSt
 
 lat_status launch_apply3d(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
 {
-    dim3 grid((unsigned)lat_cdiv(P->npacked, APPLY3_RUN)), block(256);
+    dim3 grid((unsigned)lat_cdiv(P->npacked, APPLY3_RUN)), block(512);
     const int32_t *qgroup = P->goff + P->ngroups + 1;
 #define A3(NRV, MD) hipLaunchKernelGGL((k_apply3d_mfma<NRV, MD>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
                                        A.umask, A.K, A.alpha_il, A.X, A.Y, (int)P->npacked, qgroup)
