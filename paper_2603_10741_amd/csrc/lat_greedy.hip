@@ -19,21 +19,24 @@ enum { C_DONE = 0, C_SEL = 1, C_NR = 2, C_CELL = 3 };
 enum { D_RHO = 0, D_ACH = 1 };
 
 // ---------------------------------------------------------------------------- tree reduction
-// in [nrows][ld] -> out [ceil(nrows/256)][ld]; blockDim = 256 = 16 lanes x 16 row slots.
+// in [nrows][ld] -> out [ceil(nrows/256)][ld]; blockDim = 256 = TLX lanes x TRY row slots (few
+// lanes per block: the greedy reduces ~150 rows of only ~1000 lanes, which needs many blocks).
 // A second array (in2 -> out2, operation op2) may be reduced in the same launch.  When the
 // launch produces the final value (one block of rows) it is written at out[p * ostride + ooff].
+constexpr int TLX = 4, TRY = 256 / TLX;
+
 struct TreeIO {
     const double *in;
     double *out;
     int op;
 };
 
-__device__ __forceinline__ void tree_block(double (*sh)[17], const TreeIO &io, int64_t nrows, int64_t ld, int64_t p,
+__device__ __forceinline__ void tree_block(double (*sh)[TLX + 1], const TreeIO &io, int64_t nrows, int64_t ld, int64_t p,
                                            int lx, int ry, int64_t ostride, int64_t ooff, bool final_level)
 {
     const int64_t r0 = (int64_t)blockIdx.y * LAT_TREE;
     const int n0 = (int)((nrows - r0) < LAT_TREE ? (nrows - r0) : LAT_TREE);
-    for (int t = ry; t < LAT_TREE; t += 16) {
+    for (int t = ry; t < LAT_TREE; t += TRY) {
         double v = 0.0;
         if (t < n0 && p < ld) v = io.in[(r0 + t) * ld + p];
         sh[t][lx] = v;
@@ -42,10 +45,11 @@ __device__ __forceinline__ void tree_block(double (*sh)[17], const TreeIO &io, i
     int n = n0;
     while (n > 1) {
         const int half = n >> 1;
-        double vals[LAT_TREE / 32];               // half <= 128: at most 8 pairs per thread
+        constexpr int PPT = (LAT_TREE / 2 + TRY - 1) / TRY;   // pairs per thread and level
+        double vals[PPT];
 #pragma unroll
-        for (int t = 0; t < LAT_TREE / 32; ++t) {
-            const int k = ry + 16 * t;
+        for (int t = 0; t < PPT; ++t) {
+            const int k = ry + TRY * t;
             if (k < half) {
                 const double x = sh[2 * k][lx], y = sh[2 * k + 1][lx];
                 vals[t] = io.op == 0 ? x + y : fmax(x, y);
@@ -54,8 +58,8 @@ __device__ __forceinline__ void tree_block(double (*sh)[17], const TreeIO &io, i
         const double tail = (n & 1) ? sh[n - 1][lx] : 0.0;
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < LAT_TREE / 32; ++t) {
-            const int k = ry + 16 * t;
+        for (int t = 0; t < PPT; ++t) {
+            const int k = ry + TRY * t;
             if (k < half) sh[k][lx] = vals[t];
         }
         if ((n & 1) && ry == 0) sh[half][lx] = tail;
@@ -72,10 +76,10 @@ __device__ __forceinline__ void tree_block(double (*sh)[17], const TreeIO &io, i
 __global__ __launch_bounds__(256) void k_tree(TreeIO a, TreeIO b, int two, int64_t nrows, int64_t ld, int64_t ostride,
                                               int64_t ooff, int final_level, const int32_t *__restrict__ skip)
 {
-    __shared__ double sh[LAT_TREE][17];
+    __shared__ double sh[LAT_TREE][TLX + 1];
     if (skip && skip[0]) return;
-    const int lx = threadIdx.x & 15, ry = threadIdx.x >> 4;
-    const int64_t p = (int64_t)blockIdx.x * 16 + lx;
+    const int lx = threadIdx.x % TLX, ry = threadIdx.x / TLX;
+    const int64_t p = (int64_t)blockIdx.x * TLX + lx;
     tree_block(sh, a, nrows, ld, p, lx, ry, ostride, ooff, final_level);
     if (two) tree_block(sh, b, nrows, ld, p, lx, ry, 1, 0, final_level);
 }
@@ -343,7 +347,7 @@ static lat_status tree2(const double *in, int op, double *out, int64_t ostride, 
         const bool fin = nb == 1;
         TreeIO a{src, fin ? out : bufs[which], op};
         TreeIO b{src2, fin ? out2 : bufs2[which], op2};
-        hipLaunchKernelGGL(k_tree, dim3((unsigned)lat_cdiv(ld, 16), (unsigned)nb), dim3(256), 0, s, a, b, in2 ? 1 : 0, n,
+        hipLaunchKernelGGL(k_tree, dim3((unsigned)lat_cdiv(ld, TLX), (unsigned)nb), dim3(256), 0, s, a, b, in2 ? 1 : 0, n,
                            ld, fin ? ostride : (int64_t)1, fin ? ooff : (int64_t)0, fin ? 1 : 0, skip);
         LAT_LAUNCH_CHECK();
         if (fin) break;
