@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A, const int32_t *__res
 //     4-slot register window (columns x-1 .. x+2 of rows y-1, y, y+1);
 //   - one barrier; then each wave applies the node's 2x2 blocks to its right-hand sides.
 // Every X entry is fetched once per row walk and all loads are issued a step ahead of use.
-template <int MW, int NR, int MODE>
+template <int MW, int NR, int MODE, int LP>
 __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *__restrict__ goff,
                                                     const int32_t *__restrict__ uidx,
                                                     const uint64_t *__restrict__ umask, const double *__restrict__ K,
@@ -169,11 +169,32 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     // alpha as the B operand of v_mfma_f64_16x16x4: wave w combines for cells ct*16 .. ct*16+15
     // (ct = w & 3); lane l holds alpha[k = 4 s + l / 16][cell = ct*16 + l % 16] in aB[s]
     const int ct = w & 3;
-    double aB[MODE == 2 ? 1 : NR / 4];
-    if (MODE != 2) {
+    double aB[MODE == 2 || LP > 0 ? 1 : NR / 4];
+    if (MODE != 2 && LP == 0) {
 #pragma unroll
         for (int s = 0; s < NR / 4; ++s)
             aB[s] = alpha_il[(int64_t)(4 * s + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
+    }
+    // LP > 0: the coefficients as bf16 slices, B operand of v_mfma_f32_16x16x32_bf16: lane l holds
+    // c[k = 32 kb + 8 (l / 16) .. + 7][cell = ct*16 + l % 16] in cB[slice][kb]
+    constexpr int NKB = NR <= 32 ? 1 : NR / 32;
+    lat_bf16x8 cB[LP > 0 ? LP : 1][NKB];
+    if (LP > 0) {
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            lat_s16x8 sl[LP > 0 ? LP : 1];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = 32 * kb + 8 * (l >> 4) + t;
+                const double c = k < NR ? alpha_il[(int64_t)k * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)] : 0.0;
+                uint16_t b3[3];
+                lat_slice3(c, b3);
+#pragma unroll
+                for (int v = 0; v < (LP > 0 ? LP : 1); ++v) sl[v][t] = (short)b3[v];
+            }
+#pragma unroll
+            for (int v = 0; v < (LP > 0 ? LP : 1); ++v) cB[v][kb] = __builtin_bit_cast(lat_bf16x8, sl[v]);
+        }
     }
     // principal-block staging (ROM modes): block[e * NR + k] = K_k[row(e)][ent(e)]
     double kpre[KPT];
@@ -257,7 +278,52 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                 const bool heavy = (w < 4) == ((x & 1) == 0);
                 const double *kb = &kb_s[buf][0];
                 const int c16 = ct * 16 + (l & 15);
-                if (heavy) {
+                if (LP > 0) {
+                    // bf16 slices: A operand lane l = entry 16 et + l % 16, k = 32 kb + 8 (l / 16) .. + 7;
+                    // slice products grouped by level p + q, FP32 accumulation per level, levels
+                    // summed in FP64; output rows 4 (l / 16) + r, column = cell
+                    auto tile = [&](int et) __attribute__((always_inline)) {
+                        lat_f32x4 acc[LP > 0 ? LP : 1];
+#pragma unroll
+                        for (int v = 0; v < (LP > 0 ? LP : 1); ++v) acc[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
+                        const int er = 16 * et + (l & 15) < E ? 16 * et + (l & 15) : E - 1;
+#pragma unroll
+                        for (int kbi = 0; kbi < NKB; ++kbi) {
+                            lat_s16x8 sl[LP > 0 ? LP : 1];
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                const int k = 32 * kbi + 8 * (l >> 4) + t;
+                                const double kv = k < NR ? kb[er * KSTR + k] : 0.0;
+                                uint16_t b3[3];
+                                lat_slice3(kv, b3);
+#pragma unroll
+                                for (int v = 0; v < (LP > 0 ? LP : 1); ++v) sl[v][t] = (short)b3[v];
+                            }
+                            lat_bf16x8 ap[LP > 0 ? LP : 1];
+#pragma unroll
+                            for (int v = 0; v < (LP > 0 ? LP : 1); ++v) ap[v] = __builtin_bit_cast(lat_bf16x8, sl[v]);
+#pragma unroll
+                            for (int lev = 0; lev < (LP > 0 ? LP : 1); ++lev)
+#pragma unroll
+                                for (int pc = 0; pc <= lev; ++pc)
+                                    acc[lev] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[lev - pc], cB[pc][kbi], acc[lev], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int e = 16 * et + 4 * (l >> 4) + r;
+                            double v = 0.0;
+#pragma unroll
+                            for (int lev = (LP > 0 ? LP : 1) - 1; lev >= 0; --lev) v += (double)acc[lev][r];
+                            if (e < E) kt_s[buf][e][c16] = v;
+                        }
+                    };
+                    if (heavy) {
+                        tile(0);
+                        tile(2);
+                    } else {
+                        tile(1);
+                    }
+                } else if (heavy) {
                     v4d c0 = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
                     const double *r0p = kb + (l & 15) * KSTR + (l >> 4);
                     const int e2 = 32 + (l & 15) < E ? 32 + (l & 15) : E - 1;
@@ -642,14 +708,14 @@ lat_status launch_apply(const ApplyArgs &A, int nwaves, hipStream_t s)
     return launch_apply_nr<DIM, 1, MODE>(A, nwaves, s);
 }
 
-template <int MW, int MODE>
+template <int MW, int MODE, int LP = 0>
 lat_status launch_rowwalk_nr(const lat_plan *P, const ApplyArgs &A, hipStream_t s)
 {
     ApplyArgs B = A;
     // enough walks to fill the chip in whole waves of workgroups: split rows into x-segments
     B.nseg = P->ngroups * P->nn >= 1024 ? 1 : (P->nn >= 16 ? 2 : 1);
     dim3 grid((unsigned)(P->ngroups * P->nn * B.nseg)), block(512);
-#define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE>), grid, block, 0, s, B, P->goff, P->uidx, P->umask, A.K, \
+#define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE, LP>), grid, block, 0, s, B, P->goff, P->uidx, P->umask, A.K, \
                                    A.alpha_il, A.X, A.Y)
     if (MODE == 2 || A.n_r <= 8) RW(8);
     else if (A.n_r <= 16) RW(16);
@@ -672,6 +738,14 @@ lat_status launch_rowwalk(const lat_plan *P, const ApplyArgs &A, int mode, hipSt
 {
     if (A.m == 16) return launch_rowwalk_mode<2>(P, A, mode, s);
     return launch_rowwalk_mode<1>(P, A, mode, s);
+}
+
+template <int MW>
+lat_status launch_rowwalk_bf16_mw(const lat_plan *P, const ApplyArgs &A, int nlev, hipStream_t s)
+{
+    if (nlev == 1) return launch_rowwalk_nr<MW, 0, 1>(P, A, s);
+    if (nlev == 2) return launch_rowwalk_nr<MW, 0, 2>(P, A, s);
+    return launch_rowwalk_nr<MW, 0, 3>(P, A, s);
 }
 
 lat_status launch_apply3d(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
@@ -759,6 +833,19 @@ lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *
 }
 
 }  // namespace
+
+lat_status lat_apply_rowwalk_bf16(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
+                                  double *Y, int m, int nlev, hipStream_t s)
+{
+    if (P->npacked == 0) return LAT_OK;
+    ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
+    A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
+    hipLaunchKernelGGL(k_alpha_il, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->cap), dim3(256), 0, s, P->ld,
+                       P->cap, n_r, P->perm, coef, P->alpha_il);
+    LAT_LAUNCH_CHECK();
+    A.alpha_il = P->alpha_il;
+    return m == 16 ? launch_rowwalk_bf16_mw<2>(P, A, nlev, s) : launch_rowwalk_bf16_mw<1>(P, A, nlev, s);
+}
 
 extern "C" {
 

@@ -73,6 +73,32 @@ struct lat_plan {
     float *lp_cf32 = nullptr;      // [cap][ld] FP32 coefficients
 };
 
+// ---- bf16 slices (reduced-precision combination on the bf16 matrix cores)
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 lat_bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short lat_s16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float lat_f32x4;
+
+// round-to-nearest-even bf16 of a float (bit pattern)
+__device__ __forceinline__ uint16_t lat_to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double lat_from_bf16(uint16_t b) { return (double)__uint_as_float((uint32_t)b << 16); }
+
+// three bf16 slices of x with FP64 remainders: x ~ s0 + s1 + s2
+__device__ __forceinline__ void lat_slice3(double x, uint16_t s[3])
+{
+    double r = x;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        s[t] = lat_to_bf16((float)r);
+        r -= lat_from_bf16(s[t]);
+    }
+}
+
 #define LAT_HIP(call)                                                        \
     do {                                                                     \
         hipError_t e_ = (call);                                              \
@@ -114,5 +140,8 @@ lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, 
                            double *t2, hipStream_t s);
 
 // Reduced-precision ROM apply (defined in lat_lowp.hip).
+// 2D row-walk ROM apply with the combination in bf16 slices (levels 1..3); coef as alpha
+lat_status lat_apply_rowwalk_bf16(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
+                                  double *Y, int m, int nlev, hipStream_t s);
 lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X, double *Y,
                           int m, int prec, double refine_tol, hipStream_t s);

@@ -18,8 +18,8 @@
 
 namespace {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+using bf16x8 = lat_bf16x8;
+using f32x4 = lat_f32x4;
 
 template <int DIM>
 struct Geo {
@@ -31,26 +31,7 @@ struct Geo {
     static constexpr int EPP = (EPL + 15) / 16 * 16;      // padded to the 16-row matrix tiles (48 / 96)
 };
 
-// round-to-nearest-even bf16 of a float (bit pattern)
-__device__ __forceinline__ uint16_t to_bf16(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ double from_bf16(uint16_t b) { return (double)__uint_as_float((uint32_t)b << 16); }
-
-// three bf16 slices of x with FP64 remainders
-__device__ __forceinline__ void slice3(double x, uint16_t s[3])
-{
-    double r = x;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        s[t] = to_bf16((float)r);
-        r -= from_bf16(s[t]);
-    }
-}
+__device__ __forceinline__ void slice3(double x, uint16_t s[3]) { lat_slice3(x, s); }
 
 // stack [a][e][cap] (FP64) -> slices [lev][a][NPL*EPP][64]; row plane*EPP + t holds entry plane*EPL + t
 __global__ void k_slice_stack(int64_t nloc, int E, int EPL, int EPP, int EP, int cap, int n_r,
@@ -99,6 +80,12 @@ __global__ void k_to_f32_coef(int64_t ld, int cap, int n_r, const int32_t *__res
     if (p >= ld) return;
     const int cell = perm[p];
     out[(int64_t)k * ld + p] = (cell >= 0 && k < n_r) ? (float)c[(int64_t)cell * cap + k] : 0.0f;
+}
+
+__global__ void k_fill0(int64_t n, double *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = 0.0;
 }
 
 struct LowpArgs {
@@ -362,7 +349,9 @@ lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const dou
                           int m, int prec, double refine_tol, hipStream_t s)
 {
     if (n_r < 1) {                                   // empty basis: Y = 0 on every owned DOF
-        LAT_HIP(hipMemsetAsync(Y, 0, (size_t)P->npacked * P->dim * m * 64 * sizeof(double), s));
+        const int64_t ny = P->npacked * P->dim * (int64_t)m * 64;
+        hipLaunchKernelGGL(k_fill0, dim3((unsigned)lat_cdiv(ny, 256)), dim3(256), 0, s, ny, Y);
+        LAT_LAUNCH_CHECK();
         return LAT_OK;
     }
     const int nch = 4;
@@ -371,6 +360,9 @@ lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const dou
     const int nwaves = P->ngroups * A.chunks_per_group;
     if (prec == LAT_BF16) {
         if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16) return LAT_E_ARG;
+        const int nlev0 = refine_tol >= 0x1p-8 ? 1 : (refine_tol >= 0x1p-16 ? 2 : 3);
+        if (P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3)
+            return lat_apply_rowwalk_bf16(P, K, n_r, coef, X, Y, m, nlev0, s);
         const int64_t tot = P->nloc * (int64_t)P->EP * 64;
         const int EPL = P->dim == 2 ? Geo<2>::EPL : Geo<3>::EPL, EPP = P->dim == 2 ? Geo<2>::EPP : Geo<3>::EPP;
         hipLaunchKernelGGL(k_slice_stack, dim3((unsigned)lat_cdiv(tot, 256)), dim3(256), 0, s, (int64_t)P->nloc, P->E,
