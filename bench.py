@@ -4,7 +4,8 @@
 One step = one pass of every hot-path stage over the workload (inputs already in HBM):
   DOF maps -> residual + energy + snapshots + plain operators -> greedy selection + RB
   coefficients -> principal operators -> ROM apply (the measured kernel) -> plain per-cell apply
-  -> reverse mode (ROM apply adjoint, coefficient adjoint, residual adjoint).
+  -> reverse mode (ROM apply adjoint, coefficient adjoint, residual adjoint) -> orthonormal basis
+  stack -> reduced-precision ROM apply (bf16 slice products, reported beside the FP64 number).
 `value` is the ROM apply's throughput, GDOF/s = (active local DOFs x right-hand sides) / (apply
 kernel time), with the kernel timed by HIP events on the stream it runs on.
 
@@ -27,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD_INDEX = 1
 HBM_PEAK_GBS = 8000.0
+LOWP_REFINE = 2.0 ** -16       # bf16 slice products up to level 1 (two levels)
 
 
 def log(*a):
@@ -126,17 +128,18 @@ def main():
         "snap_mu": {"snap": P._f64(P.nsnap * P.ld)},
         "snap_lam": {"snap": P._f64(P.nsnap * P.ld)},
         "ops": {k: P._f64(P.nloc * P.E * P.cap) for k in ("K", "K_mu", "K_lam")},
-        "Y": P._f64(P.packed_size(m)), "Yp": P._f64(P.packed_size(m)),
+        "Y": P._f64(P.packed_size(m)), "Yp": P._f64(P.packed_size(m)), "Ylp": P._f64(P.packed_size(m)),
+        "basis": {"stack": P._f64(P.nloc * P.E * P.cap), "coef": P._f64(P.ncells, P.cap)},
     }
     greedy_out = {}
     stages = ["dofmap", "residual_tangent", "select_principal", "principal_ops", "rom_apply", "plain_apply",
-              "adjoint"]
+              "adjoint", "basis_stack", "rom_apply_bf16"]
     ev = {s: [] for s in stages}
     state = {}
 
     def step(record):
         s = torch.cuda.current_stream()
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]  # stage i: marks[i]..marks[i+1]
         marks[0].record(s)
         P.dofmap()
         marks[1].record(s)
@@ -162,6 +165,11 @@ def main():
                         bufs["snap_mu"]["snap"], bufs["snap_lam"]["snap"], ad["mu_bar"], ad["lam_bar"])
         P.residual_adjoint(ug, mu_t, lam_t, w_cil)
         marks[7].record(s)
+        # reduced-precision combo: orthonormal-basis form, bf16 slice products (2 levels)
+        bs = P.basis_stack(g["Z"], g["nu"], g["beta"], n_r, out=bufs["basis"])
+        marks[8].record(s)
+        P.apply_combo(bs["stack"], n_r, bs["coef"], Xp, m, prec=B.BF16, refine_tol=LOWP_REFINE, out=bufs["Ylp"])
+        marks[9].record(s)
         if record:
             for i, st in enumerate(stages):
                 ev[st].append((marks[i], marks[i + 1]))
@@ -211,6 +219,9 @@ def main():
     Kself = np.stack([O.cell_eval(cfg.dim, cfg.nel, keep[s], uloc[s], mu[s], lam[s])["stencil"] for s in sample])
     Ypo = O.plain_apply(cfg.dim, cfg.nel, Kself, l2g_o[sample], X[sample])
     err_plain = float(np.linalg.norm(Yp[sample] - Ypo) / np.linalg.norm(Ypo))
+    Ylp = P.unpack(bufs["Ylp"], m).cpu().numpy()
+    err_lp = float(np.linalg.norm(Ylp[sample] - Yo) / np.linalg.norm(Yo))
+    t_lp = ms_stage["rom_apply_bf16"] * 1e-3
     rom_vs_plain = float(np.linalg.norm(Y - Yp) / np.linalg.norm(Yp))
 
     cpu = None
@@ -240,6 +251,10 @@ def main():
         "cpu_baseline": cpu,
         "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
         "rom_over_plain_speedup": round(t_plain / t_apply, 3),
+        "reduced_precision": {"kernel": "k_apply2d_rw (bf16 slice products on the matrix cores, FP64 level sums "
+                                        "and apply)", "refine_tol": LOWP_REFINE, "levels": 2,
+                              "gdofs": round(dofs_rhs / t_lp / 1e9, 3), "rel_err_vs_fp64_oracle": err_lp,
+                              "over_fp64_plain_speedup": round(t_plain / t_lp, 3)},
         "rel_err_rom_apply_vs_fp64_oracle": err_rom,
         "rel_err_plain_apply_vs_fp64_oracle": err_plain,
         "rom_vs_plain_operator_rel_diff": rom_vs_plain,

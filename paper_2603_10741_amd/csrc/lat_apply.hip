@@ -153,7 +153,10 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     constexpr int KPT = (KB + NW * 64 - 1) / (NW * 64);  // staged per thread
     __shared__ double kt_s[2][E][64];
     constexpr int KSTR = NR + 1;                        // row stride of a staged block (doubles)
-    __shared__ double kb_s[2][MODE == 2 ? 1 : E * KSTR];
+    __shared__ double kb_s[2][MODE == 2 || LP > 0 ? 1 : E * KSTR];
+    // LP > 0: the staged block as bf16 slices [buf][slice][48 rows][KSR], sliced once per node
+    constexpr int KSR = 32 * (NR <= 32 ? 1 : NR / 32) + 8;
+    __shared__ __align__(16) uint16_t ks_s[2][LP > 0 ? LP : 1][LP > 0 ? 48 * KSR : 1];
     const int nn = A.nn, nloc = nn * nn, m = A.m, cap = A.cap;
     const int lb = lat_xcd_block(blockIdx.x, gridDim.x);
     const int nseg = A.nseg;                             // each row is walked in nseg x-segments
@@ -226,7 +229,16 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 #pragma unroll
         for (int t = 0; t < KPT; ++t) {
             const int idx = tid + t * NW * 64;
-            if (idx < KB) kb_s[buf][(idx / NR) * KSTR + idx % NR] = kpre[t];
+            if (idx < KB) {
+                if (LP > 0) {
+                    uint16_t b3[3];
+                    lat_slice3(kpre[t], b3);
+#pragma unroll
+                    for (int v = 0; v < (LP > 0 ? LP : 1); ++v) ks_s[buf][v][(idx / NR) * KSR + idx % NR] = b3[v];
+                } else {
+                    kb_s[buf][(idx / NR) * KSTR + idx % NR] = kpre[t];
+                }
+            }
         }
     };
     // plain mode: this wave's share of the cell's own stencil, one step ahead
@@ -286,22 +298,17 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                         lat_f32x4 acc[LP > 0 ? LP : 1];
 #pragma unroll
                         for (int v = 0; v < (LP > 0 ? LP : 1); ++v) acc[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
-                        const int er = 16 * et + (l & 15) < E ? 16 * et + (l & 15) : E - 1;
+                        const int er = 16 * et + (l & 15);        // rows 36..47 feed unused outputs
 #pragma unroll
                         for (int kbi = 0; kbi < NKB; ++kbi) {
-                            lat_s16x8 sl[LP > 0 ? LP : 1];
-#pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                const int k = 32 * kbi + 8 * (l >> 4) + t;
-                                const double kv = k < NR ? kb[er * KSTR + k] : 0.0;
-                                uint16_t b3[3];
-                                lat_slice3(kv, b3);
-#pragma unroll
-                                for (int v = 0; v < (LP > 0 ? LP : 1); ++v) sl[v][t] = (short)b3[v];
-                            }
+                            const int k0 = 32 * kbi + 8 * (l >> 4);
                             lat_bf16x8 ap[LP > 0 ? LP : 1];
 #pragma unroll
-                            for (int v = 0; v < (LP > 0 ? LP : 1); ++v) ap[v] = __builtin_bit_cast(lat_bf16x8, sl[v]);
+                            for (int v = 0; v < (LP > 0 ? LP : 1); ++v) {
+                                lat_s16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+                                if (k0 < NR) z = *reinterpret_cast<const lat_s16x8 *>(&ks_s[buf][v][er * KSR + k0]);
+                                ap[v] = __builtin_bit_cast(lat_bf16x8, z);
+                            }
 #pragma unroll
                             for (int lev = 0; lev < (LP > 0 ? LP : 1); ++lev)
 #pragma unroll
