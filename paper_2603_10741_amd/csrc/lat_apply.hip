@@ -415,8 +415,8 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 // 3D ROM apply (and its transpose), formation on the matrix cores.  One workgroup of 8 waves =
 // a run of APPLY3_RUN packed nodes (their group's 64 cells are the lanes).  A node's 27 stencil
 // offsets are taken in 9 slices of 3 (27 entries, two 16-row tiles); per slice step:
-//   - each wave issues the loads of the X values its right-hand sides need for the slice's three
-//     neighbour nodes (consumed after the barrier, so they overlap the formation);
+//   - each wave issues the loads of the X values its right-hand sides need for the NEXT slice's
+//     three neighbour nodes (consumed one step later, so they overlap a whole step);
 //   - formation: Ktilde[e][cell] = sum_k K_k[e] alpha[k][cell] with v_mfma_f64_16x16x4 (A operand =
 //     the principal block slice, staged in LDS; B operand = alpha, in registers); wave w forms
 //     entry tile w / 4 of cell tile w % 4 and writes it to LDS;
@@ -495,6 +495,30 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     int nbv, nbv_n;
     uint32_t mlo, mhi, mlo_n, mhi_n;
     nbr_load(q0, nbv, mlo, mhi);
+    // X of a slice's three neighbour nodes for this wave's right-hand sides (raw), issued one
+    // slice step before it is used
+    double xn[3][3][2];
+    int nbn[3];
+    bool ownn[3];
+    auto load_x = [&](int tab, uint32_t tlo, uint32_t thi, int h) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int o = 3 * h + u;
+            const int nb = __builtin_amdgcn_readlane(tab, o);
+            const uint32_t lo = __builtin_amdgcn_readlane(tlo, o), hi = __builtin_amdgcn_readlane(thi, o);
+            nbn[u] = nb;
+            ownn[u] = ((l < 32 ? lo >> l : hi >> (l - 32)) & 1u) != 0;
+            const int64_t nq = nb >= 0 ? nb : 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int rr = r < nrw ? r0 + r : 0;
+                    xn[u][j][r] = X[((nq * 3 + j) * m + rr) * LAT_WAVE + l];
+                }
+        }
+    };
+    load_x(nbv, mlo, mhi, 0);
     fetch(0);
     store(0);
     fetch(1);
@@ -517,26 +541,22 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
 #pragma unroll
         for (int h = 0; h < NSL; ++h) {
             const int buf = (sl0 + h) & 1;
-            // (0) X of the slice's neighbour nodes for this wave's right-hand sides (raw)
+            // (0) this slice's X (loaded a step ago); issue the next slice's (next node's first
+            // slice after the last one: its table was loaded at the start of this node)
             double xv[3][3][2];
             int nbs[3];
             bool ownb[3];
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
-                const int o = 3 * h + u;
-                const int nb = __builtin_amdgcn_readlane(nbv, o);
-                const uint32_t lo = __builtin_amdgcn_readlane(mlo, o), hi = __builtin_amdgcn_readlane(mhi, o);
-                nbs[u] = nb;
-                ownb[u] = ((l < 32 ? lo >> l : hi >> (l - 32)) & 1u) != 0;
-                const int64_t nq = nb >= 0 ? nb : 0;
+                nbs[u] = nbn[u];
+                ownb[u] = ownn[u];
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
 #pragma unroll
-                    for (int r = 0; r < 2; ++r) {
-                        const int rr = r < nrw ? r0 + r : 0;
-                        xv[u][j][r] = X[((nq * 3 + j) * m + rr) * LAT_WAVE + l];
-                    }
+                    for (int r = 0; r < 2; ++r) xv[u][j][r] = xn[u][j][r];
             }
+            if (h + 1 < NSL) load_x(nbv, mlo, mhi, h + 1);
+            else load_x(nbv_n, mlo_n, mhi_n, 0);
             // (1) formation of entry tile et of this slice for cell tile ct -> kt_s[buf]
             {
                 v4d c = {0.0, 0.0, 0.0, 0.0};
