@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--workload", type=int, default=WORKLOAD_INDEX,
+                    help="workload index (default: the 32x32 graded-hole lattice; the others are parity cases)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -101,7 +103,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = L.config(WORKLOAD_INDEX)
+    cfg = L.config(args.workload)
     m = cfg.m
     log("workload", cfg.name)
     keep = L.make_keep(cfg)
@@ -242,7 +244,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "cells": P.ncells, "elements_per_cell": f"{cfg.nel}^2",
+        "config": {"workload": cfg.name, "cells": P.ncells, "elements_per_cell": f"{cfg.nel}^{cfg.dim}",
                    "right_hand_sides": m, "principal_cap": cfg.cap, "tol": cfg.tol, "n_r": n_r,
                    "active_local_dofs": active_dofs, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

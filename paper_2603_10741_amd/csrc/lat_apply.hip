@@ -660,6 +660,152 @@ __global__ __launch_bounds__(256) void k_forms(ApplyArgs A, const int32_t *__res
     for (int k = NR; k < cap; ++k) part[((int64_t)ch * A.ld + p) * cap + k] = 0.0;
 }
 
+// Adjoint forms on the matrix cores: G^s_ik = <Ybar_i, K^s_k X_i> for up to three principal
+// stacks s in one pass over X and Ybar.  G^s = sum over nodes a of K^s[a]^T W[a] with
+// W[a][(o,i,j)][cell] = sum_r Ybar[cell][a,i,r] X[cell][a+o,j,r]: the second factor is per cell
+// (VALU, lanes = cells), the contraction over the stencil entries is a dense
+// (principals x entries) x (entries x cells) product shared by the group (v_mfma_f64_16x16x4).
+// One workgroup of 8 waves = a run of FORMS_RUN packed nodes of one group.  A node's entries are
+// taken in slices of 12 rows (2D: 3 offsets x 4 entries; 3D: 1 offset x 9 entries + 3 zero rows);
+// per slice:
+//   - wave w accumulates its right-hand sides (w, w + 8) into a partial W slice -> LDS, and the
+//     slice's principal rows of every stack are staged in LDS;
+//   - one barrier; each wave forms the B operand W = sum of the 8 partials (fixed order) for its
+//     cell tile w % 4 and accumulates its output tiles (stack, principal tile, cell tile);
+//   - one barrier.
+// The run's partial G goes to part[stack][chunk][lane][cap]; chunks are summed by the fixed tree.
+constexpr int FORMS_RUN = 32;
+
+template <int DIM, int NR, int NS>
+__global__ __launch_bounds__(512) void k_forms_mfma(ApplyArgs A, const int32_t *__restrict__ goff,
+                                                    const int32_t *__restrict__ unode,
+                                                    const int32_t *__restrict__ unbr,
+                                                    const uint64_t *__restrict__ umask, const double *__restrict__ K0,
+                                                    const double *__restrict__ K1, const double *__restrict__ K2,
+                                                    const double *__restrict__ X, const double *__restrict__ Ybar,
+                                                    double *__restrict__ part, int cpg)
+{
+    constexpr int NO = DIM == 2 ? 9 : 27, D2 = DIM * DIM, E = NO * D2;
+    constexpr int OPS = DIM == 2 ? 3 : 1;                // offsets per slice
+    constexpr int ES = OPS * D2;                         // entries per slice (12 / 9)
+    constexpr int ER = 12;                               // slice rows: 3 k-steps of 4
+    constexpr int NSL = NO / OPS;                        // slices per node (3 / 27)
+    constexpr int KR = NR + 1;
+    constexpr int NKT = NR / 16;                         // principal tiles
+    constexpr int NT = NS * NKT * 4;                     // output tiles
+    constexpr int TPW = (NT + 7) / 8;                    // output tiles per wave
+    __shared__ double wp_s[8][ER * 64];
+    __shared__ double kb_s[NS][ER * KR];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63, tid = threadIdx.x;
+    const int blk = lat_xcd_block(blockIdx.x, gridDim.x);
+    const int g = blk / cpg, ch = blk % cpg;
+    const int G = (int)(A.ld / LAT_WAVE);
+    if (g >= G) return;
+    const int q0 = goff[g] + ch * FORMS_RUN;
+    const int q1 = min(goff[g + 1], q0 + FORMS_RUN);
+    const int m = A.m, cap = A.cap, nn = A.nn;
+    const int ct = w & 3;                                // this wave's cell tile (all its output tiles)
+    (void)nn;
+    v4d acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int q = q0; q < q1; ++q) {
+        const int a = unode[q];
+        const bool own = (umask[q] >> l) & 1;            // Ybar counts at owned DOFs only
+        const int nbv = l < NO ? unbr[(int64_t)q * NO + l] : -1;
+        const uint64_t mk = nbv >= 0 ? umask[nbv] : 0ull;
+        const uint32_t mlo = (uint32_t)mk, mhi = (uint32_t)(mk >> 32);
+        double yb[DIM][2];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int rr = w + 8 * r;
+                const double v = Ybar[(((int64_t)q * DIM + i) * m + (rr < m ? rr : 0)) * LAT_WAVE + l];
+                yb[i][r] = (own && rr < m) ? v : 0.0;
+            }
+        for (int sl = 0; sl < NSL; ++sl) {
+            // ---- partial W of this wave's right-hand sides -> wp_s[w]
+#pragma unroll
+            for (int u = 0; u < OPS; ++u) {
+                const int o = sl * OPS + u;
+                const int nb = __builtin_amdgcn_readlane(nbv, o);
+                const uint32_t lo = __builtin_amdgcn_readlane(mlo, o), hi = __builtin_amdgcn_readlane(mhi, o);
+                const bool nbo = nb >= 0 && ((((l < 32 ? lo >> l : hi >> (l - 32)) & 1u)) != 0);
+                const int64_t nq = nb >= 0 ? nb : 0;
+                double xv[DIM][2];
+#pragma unroll
+                for (int j = 0; j < DIM; ++j)
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+                        const int rr = w + 8 * r;
+                        const double v = X[((nq * DIM + j) * m + (rr < m ? rr : 0)) * LAT_WAVE + l];
+                        xv[j][r] = (nbo && rr < m) ? v : 0.0;
+                    }
+#pragma unroll
+                for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                    for (int j = 0; j < DIM; ++j) {
+                        double wv = 0.0;
+#pragma unroll
+                        for (int r = 0; r < 2; ++r) wv = fma(yb[i][r], xv[j][r], wv);
+                        wp_s[w][((u * DIM + i) * DIM + j) * 64 + l] = wv;
+                    }
+            }
+#pragma unroll
+            for (int e = ES; e < ER; ++e) wp_s[w][e * 64 + l] = 0.0;
+            // ---- the slice's principal rows of every stack -> kb_s (rows >= ES are zero)
+            for (int idx = tid; idx < NS * ER * NR; idx += 512) {
+                const int st = idx / (ER * NR), rem = idx % (ER * NR);
+                const int el = rem / NR, k = rem % NR;
+                const double *Ks = st == 0 ? K0 : (st == 1 ? K1 : K2);
+                double v = 0.0;
+                if (el < ES) v = Ks[((int64_t)a * E + sl * ES + el) * cap + k];
+                kb_s[st][el * KR + k] = v;
+            }
+            __syncthreads();
+            // ---- contraction: G^T[k][cell] += K^T[k][e] W[e][cell]
+#pragma unroll
+            for (int ks = 0; ks < ER / 4; ++ks) {
+                const int row = ks * 4 + (l >> 4);
+                double b = 0.0;
+#pragma unroll
+                for (int ww = 0; ww < 8; ++ww) b += wp_s[ww][row * 64 + ct * 16 + (l & 15)];
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    const int j = w + 8 * t;
+                    if (j < NT) {
+                        const int st = j / (NKT * 4), kt = (j / 4) % NKT;
+                        const double av = kb_s[st][row * KR + kt * 16 + (l & 15)];
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // ---- this run's partial G: lane l, reg r -> principal kt*16 + l/16 + 4 r, cell ct*16 + l%16
+    const int64_t ldc = A.ld * cap;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int j = w + 8 * t;
+        if (j < NT) {
+            const int st = j / (NKT * 4), kt = (j / 4) % NKT;
+            const int64_t base = ((int64_t)(st * cpg + ch)) * ldc + ((int64_t)g * LAT_WAVE + ct * 16 + (l & 15)) * cap;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[base + kt * 16 + (l >> 4) + 4 * r] = acc[t][r];
+        }
+    }
+    if (cap > NR) {
+        for (int idx = tid; idx < NS * 64 * (cap - NR); idx += 512) {
+            const int st = idx / (64 * (cap - NR)), rem = idx % (64 * (cap - NR));
+            const int cell = rem / (cap - NR), k = NR + rem % (cap - NR);
+            part[((int64_t)(st * cpg + ch)) * ldc + ((int64_t)g * LAT_WAVE + cell) * cap + k] = 0.0;
+        }
+    }
+}
+
 __global__ void k_alpha_il(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
                            const double *__restrict__ alpha, double *__restrict__ alpha_il)
 {
@@ -833,6 +979,40 @@ lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, cons
     return launch_apply<3, 2>(A, nwaves, s);
 }
 
+// Fused forms for ns (1..3) stacks -> P->form_part laid out [stack][chunk][ld][cap].
+lat_status run_forms_fused(const lat_plan *P, const double *const *stk, int ns, int n_r, const double *X,
+                           const double *Ybar, int m, int *cpg_out, hipStream_t s)
+{
+    ApplyArgs A = base_args(P, m, FORMS_RUN);
+    A.X = X; A.Ybar = Ybar; A.n_r = n_r;
+    const int cpg = A.chunks_per_group;
+    if ((int64_t)ns * cpg > P->napc) return LAT_E_SHAPE;
+    dim3 grid((unsigned)(P->ngroups * cpg)), block(512);
+    const double *k0 = stk[0], *k1 = ns > 1 ? stk[1] : stk[0], *k2 = ns > 2 ? stk[2] : stk[0];
+#define FF(D, NRV, NSV) hipLaunchKernelGGL((k_forms_mfma<D, NRV, NSV>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
+                                           A.umask, k0, k1, k2, X, Ybar, P->form_part, cpg)
+#define FFS(D, NRV)                     \
+    do {                                \
+        if (ns == 1) FF(D, NRV, 1);     \
+        else if (ns == 2) FF(D, NRV, 2); \
+        else FF(D, NRV, 3);             \
+    } while (0)
+#define FFD(D)                                 \
+    do {                                       \
+        if (n_r <= 16) FFS(D, 16);             \
+        else if (n_r <= 32) FFS(D, 32);        \
+        else FFS(D, 64);                       \
+    } while (0)
+    if (P->dim == 2) FFD(2);
+    else FFD(3);
+#undef FFD
+#undef FFS
+#undef FF
+    LAT_LAUNCH_CHECK();
+    *cpg_out = cpg;
+    return LAT_OK;
+}
+
 // G [ld][cap] (plan order) of <Ybar_i, K_k X_i> for a principal stack K.
 lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *X, const double *Ybar, int m,
                      double *out_pl, hipStream_t s)
@@ -905,6 +1085,35 @@ lat_status lat_apply_combo_adjoint(const lat_plan *P, const double *K, const dou
     lat_status st;
     if (Xbar && (st = run_apply(P, 1, K, n_r, alpha, Ybar, Xbar, m, stream)) != LAT_OK) return st;
     const dim3 lg((unsigned)lat_cdiv(P->ld, 256));
+    if (m <= 16 && P->cap >= 16 && (alpha_bar || mu_bar || lam_bar) && P->npacked > 0) {
+        // one pass over X and Ybar for every requested stack
+        const double *stk[3];
+        int role[3], ns = 0;
+        if (alpha_bar) { stk[ns] = K; role[ns++] = 0; }
+        if (mu_bar) { stk[ns] = K_mu; role[ns++] = 1; }
+        if (lam_bar) { stk[ns] = K_lam; role[ns++] = 2; }
+        int cpg = 0;
+        if ((st = run_forms_fused(P, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) return st;
+        const int64_t ldc = P->ld * P->cap;
+        for (int t = 0; t < ns; ++t) {
+            if ((st = lat_tree_reduce(P->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, P->form_out, P->g_t1,
+                                      P->g_t2, stream)) != LAT_OK)
+                return st;
+            if (role[t] == 0) {
+                hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, P->ld, P->cap, P->perm, P->form_out,
+                                   alpha_bar);
+            } else {
+                double *bar = role[t] == 1 ? mu_bar : lam_bar;
+                hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)lat_cdiv(P->ncells, 256)), dim3(256), 0, stream,
+                                   P->ncells, bar);
+                if (n_r > 0)
+                    hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)n_r), dim3(256), 0, stream, P->ncells, P->cap, S,
+                                       P->lane, alpha, P->form_out, bar);
+            }
+            LAT_LAUNCH_CHECK();
+        }
+        return LAT_OK;
+    }
     if (alpha_bar) {
         if ((st = run_forms(P, K, n_r, X, Ybar, m, P->form_out, stream)) != LAT_OK) return st;
         hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, P->ld, P->cap, P->perm, P->form_out, alpha_bar);
