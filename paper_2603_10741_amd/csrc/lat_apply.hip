@@ -428,7 +428,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 // step suffices and two workgroups fit on a CU.
 constexpr int APPLY3_RUN = 16;
 
-template <int NR, int MODE>
+template <int NR, int MODE, int LP>
 __global__ __launch_bounds__(512) void k_apply3d_mfma(
     ApplyArgs A, const int32_t *__restrict__ goff, const int32_t *__restrict__ unode,
     const int32_t *__restrict__ unbr, const uint64_t *__restrict__ umask, const double *__restrict__ K,
@@ -437,8 +437,11 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
 {
     constexpr int E = 243, NO = 27, ES = 27, ER = 32, KR = NR + 1, TR = 65, NSL = 9;
     constexpr int SPT = (ER * NR + 511) / 512;           // staged values per thread and slice
-    __shared__ double kb_s[2][ER * KR];
+    __shared__ double kb_s[2][LP > 0 ? 1 : ER * KR];
     __shared__ double kt_s[2][ER * TR];
+    // LP > 0: the staged slice as bf16 slices [buf][slice][ER rows][KSR]
+    constexpr int KSR = 32 * (NR <= 32 ? 1 : NR / 32) + 8;
+    __shared__ __align__(16) uint16_t ks_s[2][LP > 0 ? LP : 1][LP > 0 ? ER * KSR : 1];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int run = lat_xcd_block(blockIdx.x, gridDim.x);
@@ -480,7 +483,17 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
             const int idx = tid + 512 * t;
-            if (idx < ER * NR) kb_s[buf][(idx / NR) * KR + idx % NR] = kval[t] ? kpre[t] : 0.0;
+            if (idx < ER * NR) {
+                const double v = kval[t] ? kpre[t] : 0.0;
+                if (LP > 0) {
+                    uint16_t b3[3];
+                    lat_slice3(v, b3);
+#pragma unroll
+                    for (int lv = 0; lv < (LP > 0 ? LP : 1); ++lv) ks_s[buf][lv][(idx / NR) * KSR + idx % NR] = b3[lv];
+                } else {
+                    kb_s[buf][(idx / NR) * KR + idx % NR] = v;
+                }
+            }
         }
     };
     // neighbour table of node q, one offset per lane: packed index and owner mask
@@ -491,7 +504,9 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
         mhi = (uint32_t)(mk >> 32);
     };
     int gcur = -1;
-    double aB[NR / 4];
+    double aB[LP > 0 ? 1 : NR / 4];
+    constexpr int NKB = NR <= 32 ? 1 : NR / 32;
+    lat_bf16x8 cB[LP > 0 ? LP : 1][NKB];
     int nbv, nbv_n;
     uint32_t mlo, mhi, mlo_n, mhi_n;
     nbr_load(q0, nbv, mlo, mhi);
@@ -527,9 +542,28 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
         const int g = qgroup[q];
         if (g != gcur) {                                 // alpha of this group as the B operand
             gcur = g;
+            if (LP == 0) {
 #pragma unroll
-            for (int s2 = 0; s2 < NR / 4; ++s2)
-                aB[s2] = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
+                for (int s2 = 0; s2 < NR / 4; ++s2)
+                    aB[s2] = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
+            } else {
+                // bf16 slices of the coefficients: lane l holds c[k = 32 kb + 8 (l / 16) ..][cell]
+#pragma unroll
+                for (int kb = 0; kb < NKB; ++kb) {
+                    lat_s16x8 sl[LP > 0 ? LP : 1];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int k = 32 * kb + 8 * (l >> 4) + t;
+                        const double c = k < NR ? alpha_il[(int64_t)k * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)] : 0.0;
+                        uint16_t b3[3];
+                        lat_slice3(c, b3);
+#pragma unroll
+                        for (int v = 0; v < (LP > 0 ? LP : 1); ++v) sl[v][t] = (short)b3[v];
+                    }
+#pragma unroll
+                    for (int v = 0; v < (LP > 0 ? LP : 1); ++v) cB[v][kb] = __builtin_bit_cast(lat_bf16x8, sl[v]);
+                }
+            }
         }
         nbr_load(q + 1, nbv_n, mlo_n, mhi_n);            // next node's table, used one node later
         double acc[3][2];
@@ -558,13 +592,43 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             if (h + 1 < NSL) load_x(nbv, mlo, mhi, h + 1);
             else load_x(nbv_n, mlo_n, mhi_n, 0);
             // (1) formation of entry tile et of this slice for cell tile ct -> kt_s[buf]
-            {
+            if (LP == 0) {
                 v4d c = {0.0, 0.0, 0.0, 0.0};
                 const double *pa = &kb_s[buf][(16 * et + (l & 15)) * KR + (l >> 4)];
 #pragma unroll
                 for (int s2 = 0; s2 < NR / 4; ++s2) c = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s2], aB[s2], c, 0, 0, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) kt_s[buf][(16 * et + (l >> 4) + 4 * r) * TR + ct * 16 + (l & 15)] = c[r];
+            } else {
+                // bf16 slice products by level p + q, FP32 accumulation, FP64 level sums; output
+                // rows 4 (l / 16) + r of the tile
+                lat_f32x4 acc32[LP > 0 ? LP : 1];
+#pragma unroll
+                for (int v = 0; v < (LP > 0 ? LP : 1); ++v) acc32[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
+                const int er = 16 * et + (l & 15);
+#pragma unroll
+                for (int kbi = 0; kbi < NKB; ++kbi) {
+                    const int k0 = 32 * kbi + 8 * (l >> 4);
+                    lat_bf16x8 ap[LP > 0 ? LP : 1];
+#pragma unroll
+                    for (int v = 0; v < (LP > 0 ? LP : 1); ++v) {
+                        lat_s16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+                        if (k0 < NR) z = *reinterpret_cast<const lat_s16x8 *>(&ks_s[buf][v][er * KSR + k0]);
+                        ap[v] = __builtin_bit_cast(lat_bf16x8, z);
+                    }
+#pragma unroll
+                    for (int lev = 0; lev < (LP > 0 ? LP : 1); ++lev)
+#pragma unroll
+                        for (int pc = 0; pc <= lev; ++pc)
+                            acc32[lev] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[lev - pc], cB[pc][kbi], acc32[lev], 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int lev = (LP > 0 ? LP : 1) - 1; lev >= 0; --lev) v += (double)acc32[lev][r];
+                    kt_s[buf][(16 * et + 4 * (l >> 4) + r) * TR + ct * 16 + (l & 15)] = v;
+                }
             }
             // (2) stage the next slice, fetch the one after
             store(buf ^ 1);
@@ -921,11 +985,12 @@ lat_status launch_rowwalk_bf16_mw(const lat_plan *P, const ApplyArgs &A, int nle
     return launch_rowwalk_nr<MW, 0, 3>(P, A, s);
 }
 
+template <int LP>
 lat_status launch_apply3d(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
 {
     dim3 grid((unsigned)lat_cdiv(P->npacked, APPLY3_RUN)), block(512);
     const int32_t *qgroup = P->goff + P->ngroups + 1;
-#define A3(NRV, MD) hipLaunchKernelGGL((k_apply3d_mfma<NRV, MD>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
+#define A3(NRV, MD) hipLaunchKernelGGL((k_apply3d_mfma<NRV, MD, LP>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
                                        A.umask, A.K, A.alpha_il, A.X, A.Y, (int)P->npacked, qgroup)
 #define A3M(MD)                          \
     do {                                 \
@@ -973,7 +1038,7 @@ lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, cons
         if (mode == 1) return launch_apply<2, 1>(A, nwaves, s);
         return launch_apply<2, 2>(A, nwaves, s);
     }
-    if (mode != 2 && m <= 16) return launch_apply3d(P, A, mode, s);
+    if (mode != 2 && m <= 16) return launch_apply3d<0>(P, A, mode, s);
     if (mode == 0) return launch_apply<3, 0>(A, nwaves, s);
     if (mode == 1) return launch_apply<3, 1>(A, nwaves, s);
     return launch_apply<3, 2>(A, nwaves, s);
@@ -1051,6 +1116,11 @@ lat_status lat_apply_rowwalk_bf16(const lat_plan *P, const double *K, int n_r, c
                        P->cap, n_r, P->perm, coef, P->alpha_il);
     LAT_LAUNCH_CHECK();
     A.alpha_il = P->alpha_il;
+    if (P->dim == 3) {
+        if (nlev == 1) return launch_apply3d<1>(P, A, 0, s);
+        if (nlev == 2) return launch_apply3d<2>(P, A, 0, s);
+        return launch_apply3d<3>(P, A, 0, s);
+    }
     return m == 16 ? launch_rowwalk_bf16_mw<2>(P, A, nlev, s) : launch_rowwalk_bf16_mw<1>(P, A, nlev, s);
 }
 

@@ -361,7 +361,7 @@ lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const dou
     if (prec == LAT_BF16) {
         if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16) return LAT_E_ARG;
         const int nlev0 = refine_tol >= 0x1p-8 ? 1 : (refine_tol >= 0x1p-16 ? 2 : 3);
-        if (P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3)
+        if ((P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3) || (P->dim == 3 && m <= 16))
             return lat_apply_rowwalk_bf16(P, K, n_r, coef, X, Y, m, nlev0, s);
         const int64_t tot = P->nloc * (int64_t)P->EP * 64;
         const int EPL = P->dim == 2 ? Geo<2>::EPL : Geo<3>::EPL, EPP = P->dim == 2 ? Geo<2>::EPP : Geo<3>::EPP;
