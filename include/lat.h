@@ -154,11 +154,14 @@ lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, 
  * is the same operator when the snapshots use the full rule.  n_r is a HOST value, alpha
  * [N_s][cap] canonical, X and Y packed with m right-hand sides.
  * prec = LAT_F64: FP64 throughout (transpose != 0 applies the transposed operator).
- * prec = LAT_F32: stack and coefficients rounded to FP32, FP32 combination and apply.
+ * prec = LAT_F32: stack and coefficients rounded to FP32; the combination runs on the FP32
+ *   matrix cores (2D with m in {8, 16}, 3D with m <= 16; the apply of the combined stencil is
+ *   then FP64), otherwise on the FP32 VALU with an FP32 apply.
  * prec = LAT_BF16: the combination runs on the bf16 matrix cores with FP32 accumulation on
  *   operands split into bf16 slices; the slice products are grouped in levels of 2^-8 relative
  *   size, 1 to 3 levels as refine_tol requires (>= 2^-8: 1, >= 2^-16: 2, else 3), each level summed
- *   in FP64; the apply runs in FP32.  Requires m in {1, 2, 4, 8, 16}.
+ *   in FP64; the apply is FP64 (2D with m in {8, 16}, 3D with m <= 16), FP32 otherwise.
+ *   Requires m in {1, 2, 4, 8, 16}.
  * X and Y stay FP64 for every prec; transpose is LAT_F64 only. */
 lat_status lat_apply_combo(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
                            const double *X, double *Y, int32_t m, lat_prec prec, double refine_tol,

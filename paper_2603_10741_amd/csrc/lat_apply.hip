@@ -149,14 +149,17 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                                                     double *__restrict__ Y)
 {
     constexpr int E = 36, NW = 8;
+    constexpr bool BFS = LP >= 1 && LP <= 3;            // bf16 slice products (LP levels)
+    constexpr bool F32M = LP == 4;                       // FP32 operands on the FP32 matrix cores
+    constexpr int NLV = BFS ? LP : 1;
     constexpr int KB = MODE == 2 ? 1 : E * NR;          // principal block of one node (doubles)
     constexpr int KPT = (KB + NW * 64 - 1) / (NW * 64);  // staged per thread
     __shared__ double kt_s[2][E][64];
     constexpr int KSTR = NR + 1;                        // row stride of a staged block (doubles)
-    __shared__ double kb_s[2][MODE == 2 || LP > 0 ? 1 : E * KSTR];
-    // LP > 0: the staged block as bf16 slices [buf][slice][48 rows][KSR], sliced once per node
+    __shared__ double kb_s[2][MODE == 2 || BFS ? 1 : E * KSTR];
+    // BFS: the staged block as bf16 slices [buf][slice][48 rows][KSR], sliced once per node
     constexpr int KSR = 32 * (NR <= 32 ? 1 : NR / 32) + 8;
-    __shared__ __align__(16) uint16_t ks_s[2][LP > 0 ? LP : 1][LP > 0 ? 48 * KSR : 1];
+    __shared__ __align__(16) uint16_t ks_s[2][NLV][BFS ? 48 * KSR : 1];
     const int nn = A.nn, nloc = nn * nn, m = A.m, cap = A.cap;
     const int lb = lat_xcd_block(blockIdx.x, gridDim.x);
     const int nseg = A.nseg;                             // each row is walked in nseg x-segments
@@ -172,20 +175,20 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     // alpha as the B operand of v_mfma_f64_16x16x4: wave w combines for cells ct*16 .. ct*16+15
     // (ct = w & 3); lane l holds alpha[k = 4 s + l / 16][cell = ct*16 + l % 16] in aB[s]
     const int ct = w & 3;
-    double aB[MODE == 2 || LP > 0 ? 1 : NR / 4];
-    if (MODE != 2 && LP == 0) {
+    double aB[MODE == 2 || BFS ? 1 : NR / 4];
+    if (MODE != 2 && !BFS) {
 #pragma unroll
         for (int s = 0; s < NR / 4; ++s)
             aB[s] = alpha_il[(int64_t)(4 * s + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
     }
-    // LP > 0: the coefficients as bf16 slices, B operand of v_mfma_f32_16x16x32_bf16: lane l holds
+    // BFS: the coefficients as bf16 slices, B operand of v_mfma_f32_16x16x32_bf16: lane l holds
     // c[k = 32 kb + 8 (l / 16) .. + 7][cell = ct*16 + l % 16] in cB[slice][kb]
     constexpr int NKB = NR <= 32 ? 1 : NR / 32;
-    lat_bf16x8 cB[LP > 0 ? LP : 1][NKB];
-    if (LP > 0) {
+    lat_bf16x8 cB[NLV][NKB];
+    if (BFS) {
 #pragma unroll
         for (int kb = 0; kb < NKB; ++kb) {
-            lat_s16x8 sl[LP > 0 ? LP : 1];
+            lat_s16x8 sl[NLV];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int k = 32 * kb + 8 * (l >> 4) + t;
@@ -193,10 +196,10 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                 uint16_t b3[3];
                 lat_slice3(c, b3);
 #pragma unroll
-                for (int v = 0; v < (LP > 0 ? LP : 1); ++v) sl[v][t] = (short)b3[v];
+                for (int v = 0; v < NLV; ++v) sl[v][t] = (short)b3[v];
             }
 #pragma unroll
-            for (int v = 0; v < (LP > 0 ? LP : 1); ++v) cB[v][kb] = __builtin_bit_cast(lat_bf16x8, sl[v]);
+            for (int v = 0; v < NLV; ++v) cB[v][kb] = __builtin_bit_cast(lat_bf16x8, sl[v]);
         }
     }
     // principal-block staging (ROM modes): block[e * NR + k] = K_k[row(e)][ent(e)]
@@ -230,11 +233,11 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
         for (int t = 0; t < KPT; ++t) {
             const int idx = tid + t * NW * 64;
             if (idx < KB) {
-                if (LP > 0) {
+                if (BFS) {
                     uint16_t b3[3];
                     lat_slice3(kpre[t], b3);
 #pragma unroll
-                    for (int v = 0; v < (LP > 0 ? LP : 1); ++v) ks_s[buf][v][(idx / NR) * KSR + idx % NR] = b3[v];
+                    for (int v = 0; v < NLV; ++v) ks_s[buf][v][(idx / NR) * KSR + idx % NR] = b3[v];
                 } else {
                     kb_s[buf][(idx / NR) * KSTR + idx % NR] = kpre[t];
                 }
@@ -290,27 +293,27 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                 const bool heavy = (w < 4) == ((x & 1) == 0);
                 const double *kb = &kb_s[buf][0];
                 const int c16 = ct * 16 + (l & 15);
-                if (LP > 0) {
+                if (BFS) {
                     // bf16 slices: A operand lane l = entry 16 et + l % 16, k = 32 kb + 8 (l / 16) .. + 7;
                     // slice products grouped by level p + q, FP32 accumulation per level, levels
                     // summed in FP64; output rows 4 (l / 16) + r, column = cell
                     auto tile = [&](int et) __attribute__((always_inline)) {
-                        lat_f32x4 acc[LP > 0 ? LP : 1];
+                        lat_f32x4 acc[NLV];
 #pragma unroll
-                        for (int v = 0; v < (LP > 0 ? LP : 1); ++v) acc[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
+                        for (int v = 0; v < NLV; ++v) acc[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
                         const int er = 16 * et + (l & 15);        // rows 36..47 feed unused outputs
 #pragma unroll
                         for (int kbi = 0; kbi < NKB; ++kbi) {
                             const int k0 = 32 * kbi + 8 * (l >> 4);
-                            lat_bf16x8 ap[LP > 0 ? LP : 1];
+                            lat_bf16x8 ap[NLV];
 #pragma unroll
-                            for (int v = 0; v < (LP > 0 ? LP : 1); ++v) {
+                            for (int v = 0; v < NLV; ++v) {
                                 lat_s16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
                                 if (k0 < NR) z = *reinterpret_cast<const lat_s16x8 *>(&ks_s[buf][v][er * KSR + k0]);
                                 ap[v] = __builtin_bit_cast(lat_bf16x8, z);
                             }
 #pragma unroll
-                            for (int lev = 0; lev < (LP > 0 ? LP : 1); ++lev)
+                            for (int lev = 0; lev < NLV; ++lev)
 #pragma unroll
                                 for (int pc = 0; pc <= lev; ++pc)
                                     acc[lev] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[lev - pc], cB[pc][kbi], acc[lev], 0, 0, 0);
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                             const int e = 16 * et + 4 * (l >> 4) + r;
                             double v = 0.0;
 #pragma unroll
-                            for (int lev = (LP > 0 ? LP : 1) - 1; lev >= 0; --lev) v += (double)acc[lev][r];
+                            for (int lev = NLV - 1; lev >= 0; --lev) v += (double)acc[lev][r];
                             if (e < E) kt_s[buf][e][c16] = v;
                         }
                     };
@@ -329,6 +332,28 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                         tile(2);
                     } else {
                         tile(1);
+                    }
+                } else if (F32M) {
+                    // FP32 operands (rounded from the staged FP64 block and alpha) on
+                    // v_mfma_f32_16x16x4f32: output rows 4 (l / 16) + r of the tile
+                    auto tile32 = [&](int et) __attribute__((always_inline)) {
+                        lat_f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                        const int er = 16 * et + (l & 15) < E ? 16 * et + (l & 15) : E - 1;
+                        const double *rp = kb + er * KSTR + (l >> 4);
+#pragma unroll
+                        for (int s2 = 0; s2 < NR / 4; ++s2)
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32((float)rp[4 * s2], (float)aB[s2], c, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int e = 16 * et + 4 * (l >> 4) + r;
+                            if (e < E) kt_s[buf][e][c16] = (double)c[r];
+                        }
+                    };
+                    if (heavy) {
+                        tile32(0);
+                        tile32(2);
+                    } else {
+                        tile32(1);
                     }
                 } else if (heavy) {
                     v4d c0 = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
@@ -436,12 +461,15 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     const int32_t *__restrict__ qgroup)
 {
     constexpr int E = 243, NO = 27, ES = 27, ER = 32, KR = NR + 1, TR = 65, NSL = 9;
+    constexpr bool BFS = LP >= 1 && LP <= 3;            // bf16 slice products (LP levels)
+    constexpr bool F32M = LP == 4;                       // FP32 operands on the FP32 matrix cores
+    constexpr int NLV = BFS ? LP : 1;
     constexpr int SPT = (ER * NR + 511) / 512;           // staged values per thread and slice
-    __shared__ double kb_s[2][LP > 0 ? 1 : ER * KR];
+    __shared__ double kb_s[2][BFS ? 1 : ER * KR];
     __shared__ double kt_s[2][ER * TR];
-    // LP > 0: the staged slice as bf16 slices [buf][slice][ER rows][KSR]
+    // BFS: the staged slice as bf16 slices [buf][slice][ER rows][KSR]
     constexpr int KSR = 32 * (NR <= 32 ? 1 : NR / 32) + 8;
-    __shared__ __align__(16) uint16_t ks_s[2][LP > 0 ? LP : 1][LP > 0 ? ER * KSR : 1];
+    __shared__ __align__(16) uint16_t ks_s[2][NLV][BFS ? ER * KSR : 1];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int run = lat_xcd_block(blockIdx.x, gridDim.x);
@@ -485,11 +513,11 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             const int idx = tid + 512 * t;
             if (idx < ER * NR) {
                 const double v = kval[t] ? kpre[t] : 0.0;
-                if (LP > 0) {
+                if (BFS) {
                     uint16_t b3[3];
                     lat_slice3(v, b3);
 #pragma unroll
-                    for (int lv = 0; lv < (LP > 0 ? LP : 1); ++lv) ks_s[buf][lv][(idx / NR) * KSR + idx % NR] = b3[lv];
+                    for (int lv = 0; lv < NLV; ++lv) ks_s[buf][lv][(idx / NR) * KSR + idx % NR] = b3[lv];
                 } else {
                     kb_s[buf][(idx / NR) * KR + idx % NR] = v;
                 }
@@ -504,9 +532,9 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
         mhi = (uint32_t)(mk >> 32);
     };
     int gcur = -1;
-    double aB[LP > 0 ? 1 : NR / 4];
+    double aB[BFS ? 1 : NR / 4];
     constexpr int NKB = NR <= 32 ? 1 : NR / 32;
-    lat_bf16x8 cB[LP > 0 ? LP : 1][NKB];
+    lat_bf16x8 cB[NLV][NKB];
     int nbv, nbv_n;
     uint32_t mlo, mhi, mlo_n, mhi_n;
     nbr_load(q0, nbv, mlo, mhi);
@@ -542,7 +570,7 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
         const int g = qgroup[q];
         if (g != gcur) {                                 // alpha of this group as the B operand
             gcur = g;
-            if (LP == 0) {
+            if (!BFS) {
 #pragma unroll
                 for (int s2 = 0; s2 < NR / 4; ++s2)
                     aB[s2] = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
@@ -550,7 +578,7 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
                 // bf16 slices of the coefficients: lane l holds c[k = 32 kb + 8 (l / 16) ..][cell]
 #pragma unroll
                 for (int kb = 0; kb < NKB; ++kb) {
-                    lat_s16x8 sl[LP > 0 ? LP : 1];
+                    lat_s16x8 sl[NLV];
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         const int k = 32 * kb + 8 * (l >> 4) + t;
@@ -558,10 +586,10 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
                         uint16_t b3[3];
                         lat_slice3(c, b3);
 #pragma unroll
-                        for (int v = 0; v < (LP > 0 ? LP : 1); ++v) sl[v][t] = (short)b3[v];
+                        for (int v = 0; v < NLV; ++v) sl[v][t] = (short)b3[v];
                     }
 #pragma unroll
-                    for (int v = 0; v < (LP > 0 ? LP : 1); ++v) cB[v][kb] = __builtin_bit_cast(lat_bf16x8, sl[v]);
+                    for (int v = 0; v < NLV; ++v) cB[v][kb] = __builtin_bit_cast(lat_bf16x8, sl[v]);
                 }
             }
         }
@@ -592,7 +620,15 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             if (h + 1 < NSL) load_x(nbv, mlo, mhi, h + 1);
             else load_x(nbv_n, mlo_n, mhi_n, 0);
             // (1) formation of entry tile et of this slice for cell tile ct -> kt_s[buf]
-            if (LP == 0) {
+            if (F32M) {
+                lat_f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                const double *pa = &kb_s[buf][(16 * et + (l & 15)) * KR + (l >> 4)];
+#pragma unroll
+                for (int s2 = 0; s2 < NR / 4; ++s2)
+                    c = __builtin_amdgcn_mfma_f32_16x16x4f32((float)pa[4 * s2], (float)aB[s2], c, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) kt_s[buf][(16 * et + 4 * (l >> 4) + r) * TR + ct * 16 + (l & 15)] = (double)c[r];
+            } else if (!BFS) {
                 v4d c = {0.0, 0.0, 0.0, 0.0};
                 const double *pa = &kb_s[buf][(16 * et + (l & 15)) * KR + (l >> 4)];
 #pragma unroll
@@ -602,22 +638,22 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             } else {
                 // bf16 slice products by level p + q, FP32 accumulation, FP64 level sums; output
                 // rows 4 (l / 16) + r of the tile
-                lat_f32x4 acc32[LP > 0 ? LP : 1];
+                lat_f32x4 acc32[NLV];
 #pragma unroll
-                for (int v = 0; v < (LP > 0 ? LP : 1); ++v) acc32[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int v = 0; v < NLV; ++v) acc32[v] = lat_f32x4{0.f, 0.f, 0.f, 0.f};
                 const int er = 16 * et + (l & 15);
 #pragma unroll
                 for (int kbi = 0; kbi < NKB; ++kbi) {
                     const int k0 = 32 * kbi + 8 * (l >> 4);
-                    lat_bf16x8 ap[LP > 0 ? LP : 1];
+                    lat_bf16x8 ap[NLV];
 #pragma unroll
-                    for (int v = 0; v < (LP > 0 ? LP : 1); ++v) {
+                    for (int v = 0; v < NLV; ++v) {
                         lat_s16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
                         if (k0 < NR) z = *reinterpret_cast<const lat_s16x8 *>(&ks_s[buf][v][er * KSR + k0]);
                         ap[v] = __builtin_bit_cast(lat_bf16x8, z);
                     }
 #pragma unroll
-                    for (int lev = 0; lev < (LP > 0 ? LP : 1); ++lev)
+                    for (int lev = 0; lev < NLV; ++lev)
 #pragma unroll
                         for (int pc = 0; pc <= lev; ++pc)
                             acc32[lev] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[lev - pc], cB[pc][kbi], acc32[lev], 0, 0, 0);
@@ -626,7 +662,7 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
                 for (int r = 0; r < 4; ++r) {
                     double v = 0.0;
 #pragma unroll
-                    for (int lev = (LP > 0 ? LP : 1) - 1; lev >= 0; --lev) v += (double)acc32[lev][r];
+                    for (int lev = NLV - 1; lev >= 0; --lev) v += (double)acc32[lev][r];
                     kt_s[buf][(16 * et + 4 * (l >> 4) + r) * TR + ct * 16 + (l & 15)] = v;
                 }
             }
@@ -982,7 +1018,8 @@ lat_status launch_rowwalk_bf16_mw(const lat_plan *P, const ApplyArgs &A, int nle
 {
     if (nlev == 1) return launch_rowwalk_nr<MW, 0, 1>(P, A, s);
     if (nlev == 2) return launch_rowwalk_nr<MW, 0, 2>(P, A, s);
-    return launch_rowwalk_nr<MW, 0, 3>(P, A, s);
+    if (nlev == 3) return launch_rowwalk_nr<MW, 0, 3>(P, A, s);
+    return launch_rowwalk_nr<MW, 0, 4>(P, A, s);
 }
 
 template <int LP>
@@ -1106,8 +1143,8 @@ lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *
 
 }  // namespace
 
-lat_status lat_apply_rowwalk_bf16(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
-                                  double *Y, int m, int nlev, hipStream_t s)
+lat_status lat_apply_lowp_walk(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
+                               double *Y, int m, int nlev, hipStream_t s)
 {
     if (P->npacked == 0) return LAT_OK;
     ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
@@ -1119,7 +1156,8 @@ lat_status lat_apply_rowwalk_bf16(const lat_plan *P, const double *K, int n_r, c
     if (P->dim == 3) {
         if (nlev == 1) return launch_apply3d<1>(P, A, 0, s);
         if (nlev == 2) return launch_apply3d<2>(P, A, 0, s);
-        return launch_apply3d<3>(P, A, 0, s);
+        if (nlev == 3) return launch_apply3d<3>(P, A, 0, s);
+        return launch_apply3d<4>(P, A, 0, s);
     }
     return m == 16 ? launch_rowwalk_bf16_mw<2>(P, A, nlev, s) : launch_rowwalk_bf16_mw<1>(P, A, nlev, s);
 }

@@ -140,8 +140,9 @@ lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, 
                            double *t2, hipStream_t s);
 
 // Reduced-precision ROM apply (defined in lat_lowp.hip).
-// ROM apply with the combination in bf16 slices (levels 1..3; 2D row walk, 3D slice walk); coef as alpha
-lat_status lat_apply_rowwalk_bf16(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
-                                  double *Y, int m, int nlev, hipStream_t s);
+// ROM apply with a reduced-precision combination inside the 2D row walk / 3D slice walk:
+// nlev 1..3 = bf16 slice products of that many levels, 4 = FP32 operands; coef plays alpha
+lat_status lat_apply_lowp_walk(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
+                               double *Y, int m, int nlev, hipStream_t s);
 lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X, double *Y,
                           int m, int prec, double refine_tol, hipStream_t s);

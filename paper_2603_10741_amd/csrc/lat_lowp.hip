@@ -362,7 +362,7 @@ lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const dou
         if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16) return LAT_E_ARG;
         const int nlev0 = refine_tol >= 0x1p-8 ? 1 : (refine_tol >= 0x1p-16 ? 2 : 3);
         if ((P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3) || (P->dim == 3 && m <= 16))
-            return lat_apply_rowwalk_bf16(P, K, n_r, coef, X, Y, m, nlev0, s);
+            return lat_apply_lowp_walk(P, K, n_r, coef, X, Y, m, nlev0, s);
         const int64_t tot = P->nloc * (int64_t)P->EP * 64;
         const int EPL = P->dim == 2 ? Geo<2>::EPL : Geo<3>::EPL, EPP = P->dim == 2 ? Geo<2>::EPP : Geo<3>::EPP;
         hipLaunchKernelGGL(k_slice_stack, dim3((unsigned)lat_cdiv(tot, 256)), dim3(256), 0, s, (int64_t)P->nloc, P->E,
@@ -375,6 +375,8 @@ lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const dou
         const int nkb = n_r <= 32 ? 1 : 2;
         return P->dim == 2 ? launch_bf16<2>(A, nkb, nlev, nwaves, s) : launch_bf16<3>(A, nkb, nlev, nwaves, s);
     }
+    if ((P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3) || (P->dim == 3 && m <= 16))
+        return lat_apply_lowp_walk(P, K, n_r, coef, X, Y, m, 4, s);
     const int64_t nst = P->nloc * (int64_t)P->E * P->cap;
     hipLaunchKernelGGL(k_to_f32_stack, dim3((unsigned)lat_cdiv(nst, 256)), dim3(256), 0, s, nst, K, P->lp_kf32);
     hipLaunchKernelGGL(k_to_f32_coef, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->cap), dim3(256), 0, s, P->ld,
