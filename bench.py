@@ -44,12 +44,21 @@ def measured_traffic(workload):
     if workload != "hole2d_32x32_n32_graded" or not os.path.exists(TRAFFIC_PROFILE):
         return None
     text = open(TRAFFIC_PROFILE).read()
-    sha = re.search(r"lat_apply\.hip\): ([0-9a-f]{64})", text)
+    sha = re.search(r"row-walk source sha256: ([0-9a-f]{64})", text)
     val = re.search(r"rom_apply traffic bytes per launch: (\d+)", text)
-    src = os.path.join(ROOT, "paper_2603_10741_amd", "csrc", "lat_apply.hip")
-    if not sha or not val or hashlib.sha256(open(src, "rb").read()).hexdigest() != sha.group(1):
+    if not sha or not val or rowwalk_source_sha() != sha.group(1):
         return None
     return int(val.group(1))
+
+
+def rowwalk_source_sha():
+    """sha256 of the 2D row-walk kernel and its launcher (the code the traffic was measured on)."""
+    src = open(os.path.join(ROOT, "paper_2603_10741_amd", "csrc", "lat_apply.hip")).read()
+    k0 = src.index("// 2D row walk, software pipelined.")
+    k1 = src.index("// 3D ROM apply (and its transpose)")
+    l0 = src.index("lat_status launch_rowwalk_nr(")
+    l1 = src.index("lat_status launch_rowwalk_mode(")
+    return hashlib.sha256((src[k0:k1] + src[l0:l1]).encode()).hexdigest()
 
 
 def cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=12.0):
