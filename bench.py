@@ -258,12 +258,14 @@ def main():
                    "active_local_dofs": active_dofs, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_apply2d_rw<2,32,0> (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(alg_bytes)},
+                     "kernel": ("k_apply2d_rw<2,32,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
+                     + " (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(alg_bytes)},
         "cpu_baseline": cpu,
         "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
         "rom_over_plain_speedup": round(t_plain / t_apply, 3),
-        "reduced_precision": {"kernel": "k_apply2d_rw (bf16 slice products on the matrix cores, FP64 level sums "
-                                        "and apply)", "refine_tol": LOWP_REFINE, "levels": 2,
+        "reduced_precision": {"kernel": ("k_apply2d_rw" if cfg.dim == 2 else "k_apply3d_mfma")
+                              + " (bf16 slice products on the matrix cores, FP64 level sums and apply)",
+                              "refine_tol": LOWP_REFINE, "levels": 2,
                               "gdofs": round(dofs_rhs / t_lp / 1e9, 3), "rel_err_vs_fp64_oracle": err_lp,
                               "over_fp64_plain_speedup": round(t_plain / t_lp, 3)},
         "rel_err_rom_apply_vs_fp64_oracle": err_rom,

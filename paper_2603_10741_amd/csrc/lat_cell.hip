@@ -13,6 +13,8 @@
 // Every output entry is written by exactly one thread: no atomics, bitwise reproducible.
 #include "lat_internal.h"
 
+#include <type_traits>
+
 namespace {
 
 template <int DIM>
@@ -78,7 +80,10 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
     const int nel = A.nel, nn = nel + 1;
     const int64_t ld = A.ld;
     const int a = blockIdx.y;
-    const int row0 = DIM == 2 ? 0 : (int)blockIdx.z;
+    // 3D: blockIdx.z = row i (3) x offset plane (3); a thread accumulates the 9 offsets of its
+    // plane, which keeps the accumulators in registers (all 27 would spill)
+    const int row0 = DIM == 2 ? 0 : (int)blockIdx.z / 3;
+    const int pz = DIM == 2 ? 1 : (int)blockIdx.z % 3;
     int64_t p;
     int cell, slot = 0;
     if (PRINCIPAL) {
@@ -103,11 +108,12 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
     }
     const int ia[3] = {a % nn, (a / nn) % nn, DIM == 3 ? a / (nn * nn) : 0};
 
-    double acc[G::NO][NROW][DIM];
+    constexpr int NOP = 9;                       // offsets per plane (all of them in 2D)
+    double acc[NOP][NROW][DIM];
     double facc[NROW];
     double en = 0.0;
 #pragma unroll
-    for (int o = 0; o < G::NO; ++o)
+    for (int o = 0; o < NOP; ++o)
 #pragma unroll
         for (int r = 0; r < NROW; ++r)
 #pragma unroll
@@ -115,9 +121,10 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
 #pragma unroll
     for (int r = 0; r < NROW; ++r) facc[r] = 0.0;
 
-    if (cell >= 0) {
-#pragma unroll
-        for (int k = 0; k < G::NC; ++k) {          // node a is corner k of this element
+    // one element around node a per call; k (node a is corner k of the element) is a compile-time
+    // constant so that every accumulator index below is static
+    auto element = [&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
             int ie[3] = {0, 0, 0};
             bool ok = true;
 #pragma unroll
@@ -125,9 +132,12 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
                 ie[ax] = ia[ax] - ((k >> ax) & 1);
                 ok = ok && ie[ax] >= 0 && ie[ax] < nel;
             }
-            if (!ok) continue;
+            if (!ok) return;
+            // 3D: element k touches plane pz only from below (pz = 0: k above node a's layer) or
+            // above (pz = 2); plane 1 takes every element (and carries the force and energy)
+            if (DIM == 3 && ((pz == 0 && !((k >> 2) & 1)) || (pz == 2 && ((k >> 2) & 1)))) return;
             const int e = ie[0] + nel * (ie[1] + nel * ie[2]);
-            if (!A.keep_il[(int64_t)e * ld + p]) continue;
+            if (!A.keep_il[(int64_t)e * ld + p]) return;
             double ue[G::NC][DIM];
 #pragma unroll
             for (int c = 0; c < G::NC; ++c) {
@@ -197,9 +207,9 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
                     double Fg = 0.0;
 #pragma unroll
                     for (int J = 0; J < DIM; ++J) Fg += F[i][J] * gk[J];
-                    facc[r] += wq * (mu * (Fg - pk[i]) + lam * lnJ * pk[i]);
+                    if (pz == 1) facc[r] += wq * (mu * (Fg - pk[i]) + lam * lnJ * pk[i]);
                 }
-                if (k == 0) {                           // element energy, owned by its corner 0
+                if (k == 0 && pz == 1) {                // element energy, owned by its corner 0
                     double I1 = DIM == 2 ? 1.0 : 0.0;
 #pragma unroll
                     for (int i = 0; i < DIM; ++i)
@@ -210,9 +220,10 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
                 const double c2 = mu - lam * lnJ;
 #pragma unroll
                 for (int c = 0; c < G::NC; ++c) {
-                    int oi = 0, sc = 1;
+                    int oi = 0, sc = 1;                 // in-plane offset index (x fastest)
 #pragma unroll
-                    for (int ax = 0; ax < DIM; ++ax) { oi += (((c >> ax) & 1) - ((k >> ax) & 1) + 1) * sc; sc *= 3; }
+                    for (int ax = 0; ax < 2; ++ax) { oi += (((c >> ax) & 1) - ((k >> ax) & 1) + 1) * sc; sc *= 3; }
+                    if (DIM == 3 && (((c >> 2) & 1) - ((k >> 2) & 1) + 1) != pz) continue;
                     double gc[DIM], pc[DIM], gkgc = 0.0;
 #pragma unroll
                     for (int J = 0; J < DIM; ++J) { gc[J] = shape_grad<DIM, RULE>(q, c, J, invh); gkgc += gk[J] * gc[J]; }
@@ -235,40 +246,52 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
                     }
                 }
             }
+    };
+    if (cell >= 0) {
+        element(std::integral_constant<int, 0>{});
+        element(std::integral_constant<int, 1>{});
+        element(std::integral_constant<int, 2>{});
+        element(std::integral_constant<int, 3>{});
+        if (DIM == 3) {
+            element(std::integral_constant<int, 4>{});
+            element(std::integral_constant<int, 5>{});
+            element(std::integral_constant<int, 6>{});
+            element(std::integral_constant<int, 7>{});
         }
     }
     // ---- outputs
     constexpr int E = G::E;
+    const int obase = DIM == 3 ? 9 * pz : 0;
     if (PRINCIPAL) {
 #pragma unroll
-        for (int o = 0; o < G::NO; ++o)
+        for (int o = 0; o < NOP; ++o)
 #pragma unroll
             for (int r = 0; r < NROW; ++r)
 #pragma unroll
                 for (int j = 0; j < DIM; ++j) {
                     const int i = DIM == 2 ? r : row0;
-                    const int ent = (o * DIM + i) * DIM + j;
+                    const int ent = ((obase + o) * DIM + i) * DIM + j;
                     A.Kst[((int64_t)a * E + ent) * A.cap + slot] = acc[o][r][j];
                 }
         return;
     }
-    if (A.f) {
+    if (A.f && pz == 1) {
 #pragma unroll
         for (int r = 0; r < NROW; ++r) {
             const int i = DIM == 2 ? r : row0;
             A.f[((int64_t)a * DIM + i) * ld + p] = facc[r];
         }
     }
-    if (A.epart && row0 == 0) A.epart[(int64_t)a * ld + p] = en;
+    if (A.epart && row0 == 0 && pz == 1) A.epart[(int64_t)a * ld + p] = en;
     if (A.T) {
 #pragma unroll
-        for (int o = 0; o < G::NO; ++o)
+        for (int o = 0; o < NOP; ++o)
 #pragma unroll
             for (int r = 0; r < NROW; ++r)
 #pragma unroll
                 for (int j = 0; j < DIM; ++j) {
                     const int i = DIM == 2 ? r : row0;
-                    const int ent = (o * DIM + i) * DIM + j;
+                    const int ent = ((obase + o) * DIM + i) * DIM + j;
                     A.T[((int64_t)a * E + ent) * ld + p] = acc[o][r][j];
                 }
     }
@@ -278,13 +301,13 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
         if (qi >= 0) {
             const int64_t q = A.goff[g] + qi;
 #pragma unroll
-            for (int o = 0; o < G::NO; ++o)
+            for (int o = 0; o < NOP; ++o)
 #pragma unroll
                 for (int r = 0; r < NROW; ++r)
 #pragma unroll
                     for (int j = 0; j < DIM; ++j) {
                         const int i = DIM == 2 ? r : row0;
-                        const int ent = (o * DIM + i) * DIM + j;
+                        const int ent = ((obase + o) * DIM + i) * DIM + j;
                         A.ops[(q * E + ent) * LAT_WAVE + l] = acc[o][r][j];
                     }
         }
@@ -467,10 +490,10 @@ template <int DIM, int RULE, bool PRINCIPAL>
 lat_status launch_cell(const lat_plan *P, CellArgs &A, hipStream_t s)
 {
     if (PRINCIPAL) {
-        dim3 grid(1, (unsigned)P->nloc, DIM == 3 ? 3 : 1);
+        dim3 grid(1, (unsigned)P->nloc, DIM == 3 ? 9 : 1);
         hipLaunchKernelGGL((k_cell<DIM, RULE, true>), grid, dim3(64), 0, s, A);
     } else {
-        dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc, DIM == 3 ? 3 : 1);
+        dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc, DIM == 3 ? 9 : 1);
         hipLaunchKernelGGL((k_cell<DIM, RULE, false>), grid, dim3(256), 0, s, A);
     }
     LAT_LAUNCH_CHECK();
