@@ -85,6 +85,63 @@ __global__ __launch_bounds__(256) void k_aa_contract(int64_t nsnap, int64_t ld, 
     for (int k = NR; k < cap; ++k) part[(b * ld + p) * cap + k] = 0.0;
 }
 
+// The same contraction on the matrix cores: part[chunk] = V_chunk^T U_chunk, a
+// (lanes x rows) x (rows x principals) product, with v_mfma_f64_16x16x4 tiles of 16 lanes x 16
+// principals.  A workgroup of 4 waves takes 256 lanes and one chunk of rows; wave w owns lanes
+// 64 w .. 64 w + 63 (4 lane tiles) and every principal tile, so V is read once and U once per
+// 256 lanes.  Rows go 4 at a time (one MFMA k-step); the sum over a chunk is in row order per
+// MFMA, and chunks are combined by the fixed tree.
+typedef double aa_v4d __attribute__((ext_vector_type(4)));
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_aa_contract_mfma(int64_t nsnap, int64_t ld, int cap, int rows_per_chunk,
+                                                          const double *__restrict__ V, const double *__restrict__ U,
+                                                          double *__restrict__ part)
+{
+    constexpr int NKT = NR / 16;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63;
+    const int64_t pw = (int64_t)blockIdx.x * 256 + 64 * w;           // this wave's first lane
+    if (pw >= ld) return;                                             // wave-uniform (ld % 64 == 0)
+    const int64_t b = blockIdx.y;
+    const int64_t j0 = b * rows_per_chunk, j1 = j0 + rows_per_chunk < nsnap ? j0 + rows_per_chunk : nsnap;
+    aa_v4d acc[4][NKT];
+#pragma unroll
+    for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) acc[pt][kt] = aa_v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = j0; j < j1; j += 4) {
+        const int64_t jr = j + (l >> 4);                              // this lane's row of the k-step
+        const bool live = jr < j1;
+        const int64_t jc = live ? jr : j0;
+        double a[4], bv[NKT];
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt) {
+            const double v = V[jc * ld + pw + 16 * pt + (l & 15)];
+            a[pt] = live ? v : 0.0;
+        }
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+            const double u = U[jc * cap + 16 * kt + (l & 15)];
+            bv[kt] = live ? u : 0.0;
+        }
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+            for (int kt = 0; kt < NKT; ++kt) acc[pt][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[pt], bv[kt], acc[pt][kt], 0, 0, 0);
+    }
+    // lane l, reg r -> lane row (l / 16) + 4 r of the tile, principal column l % 16
+#pragma unroll
+    for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[(b * ld + pw + 16 * pt + (l >> 4) + 4 * r) * cap + 16 * kt + (l & 15)] = acc[pt][kt][r];
+    for (int k = NR; k < cap; ++k)
+        part[(b * ld + pw + l) * cap + k] = 0.0;
+}
+
 // per-cell term: bar_c += q_c . A[p_c]   (A = Z^T t^x, plan order [ld][cap])
 __global__ void k_aa_cellterm(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
                               const double *__restrict__ qv, const double *__restrict__ Am,
@@ -146,7 +203,11 @@ lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U
 {
     const int rows = P->aa_rows;
     dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->aa_nchunk);
-    if (n_r <= 8) hipLaunchKernelGGL(k_aa_contract<8>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+    if (n_r > 8 && P->cap >= 16) {
+        if (n_r <= 16) hipLaunchKernelGGL(k_aa_contract_mfma<16>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+        else if (n_r <= 32) hipLaunchKernelGGL(k_aa_contract_mfma<32>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+        else hipLaunchKernelGGL(k_aa_contract_mfma<64>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+    } else if (n_r <= 8) hipLaunchKernelGGL(k_aa_contract<8>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
     else if (n_r <= 16) hipLaunchKernelGGL(k_aa_contract<16>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
     else if (n_r <= 32) hipLaunchKernelGGL(k_aa_contract<32>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
     else hipLaunchKernelGGL(k_aa_contract<64>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
