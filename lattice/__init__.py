@@ -325,3 +325,60 @@ def make_rhs(cfg: LatticeConfig, cells: Optional[Sequence[int]] = None, m: Optio
         rng = np.random.default_rng([seed, stream, int(ids[c]), m])
         out[t] = rng.standard_normal((cfg.n_local_nodes, cfg.dim, m))
     return out
+
+
+# ----------------------------------------------------------------------------- boundary-value problems
+@dataclasses.dataclass(frozen=True)
+class LoadCase:
+    """Loading of a lattice for the load-stepped Newton solve.
+
+    kind "compress_shear": the bottom face (last coordinate 0) is clamped, the top face
+      (last coordinate = lattice height H) is moved by (shear H, -strain H) [2D] or
+      (shear H, 0, -strain H) [3D]; every component of both faces is prescribed.
+    kind "uniaxial_roller": only the last component is prescribed on the bottom (0) and top
+      (-strain H) faces; the node at the origin is pinned in the other components and, in 3D,
+      the node at (W, 0, 0) in the second component, so that no rigid motion remains.
+    """
+    kind: str
+    strain: float
+    shear: float = 0.0
+    n_inc: int = 4
+
+
+def make_bvp(cfg: LatticeConfig, case: LoadCase) -> dict:
+    """Dirichlet data on the background node grid for a load case.
+
+    Returns fixed uint8 [G][d] (1 = prescribed component) and ubar float64 [G][d]: the affine
+    displacement field of the whole load at every background node, which equals the prescribed
+    value on the constrained components (the solver adds ubar / n_inc to every node at the start
+    of each increment).  f_ext float64 [G][d] is zero (displacement-driven cases).
+    """
+    d = cfg.dim
+    shp = background_shape(cfg)
+    h = 1.0 / cfg.nel
+    axes = [np.arange(s) for s in shp]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+    I = [g.reshape(-1) for g in grids]                  # integer grid coordinates, x fastest
+    G = I[0].size
+    top = shp[d - 1] - 1
+    H = top * h
+    z = I[d - 1] * h
+    fixed = np.zeros((G, d), np.uint8)
+    ubar = np.zeros((G, d))
+    bot_m = I[d - 1] == 0
+    top_m = I[d - 1] == top
+    if case.kind == "compress_shear":
+        fixed[bot_m | top_m, :] = 1
+        ubar[:, 0] = case.shear * z
+        ubar[:, d - 1] = -case.strain * z
+    elif case.kind == "uniaxial_roller":
+        fixed[bot_m | top_m, d - 1] = 1
+        origin = np.all([I[ax] == 0 for ax in range(d)], axis=0)
+        fixed[origin, :d - 1] = 1
+        if d == 3:
+            xend = (I[0] == shp[0] - 1) & (I[1] == 0) & (I[2] == 0)
+            fixed[xend, 1] = 1
+        ubar[:, d - 1] = -case.strain * z
+    else:
+        raise ValueError(case.kind)
+    return {"fixed": fixed, "ubar": ubar, "f_ext": np.zeros((G, d)), "height": H}

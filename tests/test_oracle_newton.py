@@ -1,0 +1,148 @@
+"""Pins of the oracle's load-stepped Newton-Raphson (Sec. 2.2.5) against facts it does not compute.
+
+* Armijo's rule (smallest m with the sufficient-decrease inequality) by brute force on scalar
+  residuals, including an inadmissible trial.
+* The assembled ROM matrix against the C oracle's per-cell combination apply (two independent
+  codings of eq. romstiffnessmatrix + eq. residualvector), and its symmetry (the tangent of a
+  hyperelastic potential).
+* Uniaxial stretch of a solid block on rollers: an affine field solves the discrete problem
+  exactly, with the lateral stretch the root of the neo-Hookean zero-lateral-stress condition
+  (plane strain: mu (a - 1/a) + lam ln(a l) / a = 0; 3D with two equal lateral stretches:
+  mu (a - 1/a) + lam ln(a^2 l) / a = 0).
+* Equilibrium: at the converged state the total energy is stationary along free directions.
+* With an exact tangent (tolerance below round-off, all cells principal) Newton converges
+  quadratically; the converged state does not depend on the number of load increments.
+* After the affine predictor of the first increment, the cells of one column of the graded
+  lattice are identical, so the greedy needs exactly one principal cell per column.
+"""
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+import lattice as L
+import oracle as O
+from oracle import newton as ON
+
+
+def _graded_case(sub=(4, 4), strain=0.04, shear=0.01):
+    cfg = L.config(0).with_(radius=(0.25, 0.35)).with_sub(sub)
+    bvp = L.make_bvp(cfg, L.LoadCase("compress_shear", strain, shear, 4))
+    mu, lam = L.make_material(cfg)
+    P = ON.Problem(2, cfg.ncell_eff, cfg.nel, L.make_keep(cfg), mu, lam, bvp["fixed"], bvp["ubar"])
+    return cfg, P
+
+
+def test_armijo_brute_force():
+    # Newton on g(x) = atan(x) from x = 3 overshoots: the full step must be cut.
+    x0 = 3.0
+    g = np.arctan
+    dx = -g(x0) * (1 + x0 * x0)
+    phi = lambda s: (abs(g(x0 + s * dx)), None)
+    m, s, val, _ = ON.armijo(phi, abs(g(x0)))
+    want = next(k for k in range(31) if abs(g(x0 + 0.5 ** k * dx)) <= (1 - 1e-4 * 0.5 ** k) * abs(g(x0)))
+    assert m == want and m >= 1 and s == 0.5 ** m
+    # an inadmissible first trial is skipped, a good second one is taken
+    vals = {1.0: np.inf, 0.5: 0.1}
+    m, s, val, _ = ON.armijo(lambda s: (vals.get(s, 5.0), None), 1.0)
+    assert (m, s, val) == (1, 0.5, 0.1)
+    # the sufficient-decrease factor is (1 - c s): 0.99995 passes at s = 0.5, 0.99996 does not
+    assert ON.armijo(lambda s: (0.99995 if s == 0.5 else 2.0, None), 1.0)[0] == 1
+    assert ON.armijo(lambda s: (0.99996 if s == 0.5 else 2.0, None), 1.0, max_bt=1) is None
+
+
+def test_rom_matrix_matches_combination_apply():
+    cfg = L.config(0).with_sub((3, 2))
+    keep = L.make_keep(cfg)
+    l2g, _, g2bg = O.dofmap(2, cfg.ncell_eff, cfg.nel, keep)
+    ub = L.make_displacement(cfg)
+    uglob = ub[g2bg]
+    T = O.cells_eval(2, cfg.nel, keep, O.gather_local(uglob, l2g), 1.0, 10.0, want_f=False, want_energy=False)["T"]
+    g = O.greedy(T, 1e-3, 6)
+    S = g["S"][:g["n_r"]]
+    K = ON.rom_matrix(2, cfg.nel, T[S], g["alpha"], l2g, g2bg.size)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((g2bg.size, 2))
+    y1 = (K @ x.ravel()).reshape(-1, 2)
+    Xl = O.gather_local(x, l2g)[..., None]
+    y2 = O.assemble(O.combo_apply(2, cfg.nel, T[S], g["alpha"], l2g, Xl)[..., 0], l2g, g2bg.size)
+    assert np.abs(y1 - y2).max() <= 1e-12 * np.abs(y2).max()
+    assert abs(K - K.T).max() <= 1e-12 * abs(K).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_uniaxial_roller_closed_form(dim):
+    if dim == 2:
+        ncell, nel, cfg0, rad, lam = (2, 2), 4, 0, (0.0, 0.0), 10.0
+    else:
+        ncell, nel, cfg0, rad, lam = (2, 2, 2), 2, 2, (2.0, 2.0), 5.0
+    cfg = L.config(cfg0).with_(ncell=ncell, nel=nel, radius=rad)
+    keep = L.make_keep(cfg)
+    assert keep.all()
+    mu, l3 = 1.0, 0.9
+    bvp = L.make_bvp(cfg, L.LoadCase("uniaxial_roller", 1.0 - l3))
+    P = ON.Problem(dim, ncell, nel, keep, mu, lam, bvp["fixed"], bvp["ubar"])
+    out = ON.newton_solve(P, n_inc=4, rb_tol=1e-8, cap=8, newton_tol=1e-12)
+    assert out["status"] == O.OK
+    assert all(r["n_r"] == 1 for r in out["records"])       # homogeneous state: every cell alike
+    nlat = dim - 1
+    a = so.brentq(lambda a: mu * (a - 1 / a) + lam * np.log(a ** nlat * l3) / a, 0.5, 2.0, xtol=1e-15)
+    shp = [c * nel + 1 for c in ncell]
+    X = np.zeros((P.ng, dim))
+    r = P.g2bg.copy()
+    for ax in range(dim):
+        X[:, ax] = (r % shp[ax]) / nel
+        r //= shp[ax]
+    uex = X * (a - 1)
+    uex[:, -1] = X[:, -1] * (l3 - 1)
+    assert np.abs(out["u"] - uex).max() <= 1e-11
+
+
+@pytest.fixture(scope="module")
+def exact_graded():
+    cfg, P = _graded_case()
+    out = ON.newton_solve(P, n_inc=4, rb_tol=1e-13, cap=16, newton_tol=1e-10)
+    return cfg, P, out
+
+
+def test_equilibrium_is_energy_stationary(exact_graded):
+    cfg, P, out = exact_graded
+    assert out["status"] == O.OK
+    u = out["u"]
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(u.shape)
+    v[P.fixed] = 0.0
+    h = 1e-6
+    d_sol = (P.total_energy(u + h * v, 1.0) - P.total_energy(u - h * v, 1.0)) / (2 * h)
+    # the same derivative at the predictor state of the last increment is far from zero
+    u_pred = u - P.ubar / 4
+    d_pred = (P.total_energy(u_pred + h * v, 1.0) - P.total_energy(u_pred - h * v, 1.0)) / (2 * h)
+    assert abs(d_pred) > 1e-3
+    assert abs(d_sol) <= 1e-6 * abs(d_pred)
+
+
+def test_exact_tangent_converges_quadratically(exact_graded):
+    cfg, P, out = exact_graded
+    recs = out["records"]
+    assert all(r["backtracks"] == 0 for r in recs)
+    for t in range(1, 5):
+        e = [r["res_after"] / r["res0"] for r in recs if r["increment"] == t]
+        assert len(e) <= 4
+        for k in range(len(e) - 1):
+            if e[k] < 1e-2:
+                assert e[k + 1] <= 10.0 * e[k] ** 2 + 1e-13
+
+
+def test_load_path_independence(exact_graded):
+    cfg, P, out4 = exact_graded
+    out2 = ON.newton_solve(P, n_inc=2, rb_tol=1e-13, cap=16, newton_tol=1e-10)
+    assert out2["status"] == O.OK
+    assert np.abs(out2["u"] - out4["u"]).max() <= 1e-8 * np.abs(out4["u"]).max()
+
+
+def test_first_iteration_one_principal_cell_per_column():
+    cfg, P = _graded_case()
+    out = ON.newton_solve(P, n_inc=4, rb_tol=1e-4, cap=16, max_newton=1)
+    first = out["records"][0]
+    assert first["increment"] == 1 and first["iteration"] == 0
+    assert first["n_r"] == cfg.ncell_eff[0]
+    assert first["achieved"] <= 1e-12
