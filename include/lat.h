@@ -10,7 +10,9 @@
  *   - greedy selection of principal cells and RB coefficients    (Algorithm 1, Sec. 3.2.2)
  *   - the ROM operator apply Y_i = sum_k alpha_ik K_k X_i         (eq. romstiffnessmatrix)
  *   - the plain per-cell apply Y_i = K_i X_i (the standard operator, Sec. 3.1.4)
- *   - reverse-mode (adjoint) forms of the residual and of the ROM apply.
+ *   - reverse-mode (adjoint) forms of the residual and of the ROM apply
+ *   - the load-stepped Newton-Raphson solve on the ROM tangent with Armijo backtracking and its
+ *     matrix-free preconditioned MINRES tangent solves                 (Sec. 2.2.5, eq. linsys).
  *
  * General conventions
  *   - Every array argument is a DEVICE pointer owned by the caller, unless its comment says
@@ -63,7 +65,9 @@ typedef enum {
     LAT_E_NOMEM = 4,      /* device allocation failed */
     LAT_E_INVERTED = 5,   /* (device status) J <= 0 at a Gauss point */
     LAT_E_NONFINITE = 6,  /* (device status) non-finite displacement or Jacobian */
-    LAT_W_CAP = 7         /* (device status) greedy stopped at the cap above the tolerance */
+    LAT_W_CAP = 7,        /* (device status) greedy stopped at the cap above the tolerance */
+    LAT_E_NOCONV = 8,     /* an iterative solve stopped at its iteration limit */
+    LAT_E_SINGULAR = 9    /* the tangent solve met an operator singular on its Krylov space */
 } lat_status;
 
 typedef enum { LAT_RULE_FULL = 0, LAT_RULE_REDUCED = 1 } lat_rule;   /* 2^d Gauss points / 1 point */
@@ -225,6 +229,90 @@ lat_status lat_cil_to_canon(const lat_plan *plan, const double *cil, int64_t k, 
 lat_status lat_canon_to_cil(const lat_plan *plan, const double *canon, int64_t k, double *cil, hipStream_t stream);
 /* Packed plain-ops -> canonical stencils [N_s][n_snap] (zero outside each group's union). */
 lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, double *canon, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Nonlinear solve on the ROM tangent (Sec. 2.2.5, Newton-Raphson method; the reduced basis is
+ * rebuilt at every iteration, Sec. 3.2.3).  Global vectors are [n_global][d], node-major, in the
+ * plan's global numbering; `fixed` is a device uint8 [n_global][d] (1 = prescribed component).
+ * These calls synchronise `stream`, allocate their device workspace for the duration of the call
+ * and free it before returning.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Tangent solve K~ x = b on the free components (eq. linsys with the ROM operator of
+ * eq. romstiffnessmatrix, K~ = sum_s A^s M_s (sum_k alpha_sk K_k) M_s A^{sT}) by MINRES
+ * preconditioned with D = |diag K~|: K~ is symmetric but may be indefinite (a pre-stressed lattice
+ * near buckling), and MINRES minimises ||b - K~ x||_{D^-1} over the Krylov space for any
+ * symmetric non-singular K~.  Matrix-free: every product is one ROM apply (one right-hand side)
+ * followed by an owner-ordered assembly.  K, n_r (HOST), alpha as for lat_apply_combo.
+ * b [n_global][d] (prescribed components ignored), x [n_global][d] out (prescribed components 0;
+ * x starts from 0).  Stops when the residual estimate of the rotations satisfies
+ * ||r||_{D^-1} <= tol ||b||_{D^-1} (tol > 0), after at most maxit iterations, checking on the host
+ * every `check` iterations (>= 1).  HOST outputs: iters, relres = ||r||_{D^-1} / ||b||_{D^-1}
+ * (0 when b = 0).  Returns LAT_OK when converged, LAT_E_NOCONV at maxit (x holds the last
+ * iterate), LAT_E_SINGULAR when K~ is singular on the Krylov space (x holds the last iterate). */
+lat_status lat_rom_solve(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
+                         const uint8_t *fixed, const double *b, double *x, double tol, int32_t maxit,
+                         int32_t check, int32_t *iters, double *relres, hipStream_t stream);
+
+/* Options of lat_newton_solve (HOST struct). */
+typedef struct {
+    int32_t n_inc;          /* load increments, >= 1 */
+    int32_t max_newton;     /* Newton iterations per increment, >= 1 */
+    int32_t max_backtrack;  /* Armijo reductions per iteration, >= 0 */
+    int32_t cap;            /* principal-cell cap per iteration, 1..plan cap */
+    int32_t cg_maxit;       /* MINRES iterations per tangent solve, >= 1 */
+    int32_t cg_check;       /* iterations between host convergence reads, >= 1 */
+    int32_t snap_rule;      /* lat_rule of the snapshots fed to the greedy */
+    int32_t reserved;       /* 0 */
+    double rb_tol;          /* greedy tolerance (Algorithm 1), > 0 */
+    double newton_tol;      /* stop an increment at ||r|| / ||r(u_0)|| <= newton_tol, > 0 */
+    double armijo_beta;     /* step reduction factor, in (0, 1) */
+    double armijo_c;        /* sufficient-decrease constant, in [0, 1) */
+    double cg_tol;          /* relative residual ||r||_{D^-1} of each tangent solve, > 0 */
+} lat_newton_opts;
+
+/* One Newton iteration (HOST struct). */
+typedef struct {
+    int32_t increment;      /* 1..n_inc */
+    int32_t iteration;      /* 0-based within the increment */
+    int32_t n_r;            /* principal cells of this iteration's reduced basis */
+    int32_t backtracks;     /* Armijo exponent m of the accepted step beta^m */
+    int32_t cg_iters;       /* MINRES iterations of the tangent solve */
+    int32_t greedy_status;  /* LAT_OK or LAT_W_CAP */
+    int32_t cg_status;      /* LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR */
+    int32_t reserved;
+    double step;            /* beta^m */
+    double res_before;      /* ||r(u_k)||_2 */
+    double res_after;       /* ||r(u_k + beta^m du)||_2 */
+    double res0;            /* ||r(u_0)||_2 of the increment */
+    double rb_achieved;     /* the greedy's max_s ||Delta^s||_inf at exit */
+    double cg_relres;       /* ||r||_{D^-1} / ||rhs||_{D^-1} at the end of the tangent solve */
+    double t_init_ms;       /* greedy + principal tangents + preconditioner */
+    double t_solve_ms;      /* tangent solve */
+    double t_eval_ms;       /* residual + snapshot evaluations (predictor and line-search trials) */
+} lat_newton_record;
+
+/* Load-stepped Newton-Raphson with Armijo backtracking (Sec. 2.2.5) on the ROM tangent.
+ * mu, lam [N_s] (device, canonical); fixed [n_global][d]; ubar [n_global][d]: the displacement
+ * added to every node over the whole load (increment t adds ubar / n_inc to u at its start, which
+ * carries the prescribed components to t / n_inc of their final value and is the increment's
+ * first iterate); f_ext [n_global][d] external nodal forces of the whole load, scaled by t / n_inc
+ * (may be NULL).  u [n_global][d] device, in: the initial state, out: the final state.
+ * Residual r(u) = sum_s A^s f^{int,s} - (t/n_inc) f_ext, zero on prescribed components.
+ * Each iteration: snapshots at u (opts->snap_rule) -> greedy (rb_tol, cap) -> principal tangents
+ * -> tangent solve K~ du = -r (lat_rom_solve's method; its status goes to the record and a
+ * solve stopped early still provides the direction) -> the smallest m <= max_backtrack with
+ * ||r(u + beta^m du)|| <= (1 - c beta^m) ||r(u)|| (a trial with J <= 0 anywhere fails) ->
+ * u += beta^m du; the increment ends when ||r|| <= newton_tol ||r(u_0)||.
+ * records: HOST array of max_records entries (may be NULL), one per Newton iteration in order;
+ * *n_records (HOST, may be NULL) receives the number of iterations run (which may exceed
+ * max_records).  Returns LAT_OK, LAT_E_NOCONV (iteration or backtracking limit; u holds the last
+ * accepted state), LAT_E_INVERTED / LAT_E_NONFINITE (an increment's first iterate is not
+ * admissible), or an argument/device error. */
+lat_status lat_newton_solve(const lat_plan *plan, const double *mu, const double *lam, const uint8_t *fixed,
+                            const double *ubar, const double *f_ext, const lat_newton_opts *opts, double *u,
+                            lat_newton_record *records, int32_t max_records, int32_t *n_records,
+                            hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -335,9 +335,9 @@ class LoadCase:
     kind "compress_shear": the bottom face (last coordinate 0) is clamped, the top face
       (last coordinate = lattice height H) is moved by (shear H, -strain H) [2D] or
       (shear H, 0, -strain H) [3D]; every component of both faces is prescribed.
-    kind "uniaxial_roller": only the last component is prescribed on the bottom (0) and top
-      (-strain H) faces; the node at the origin is pinned in the other components and, in 3D,
-      the node at (W, 0, 0) in the second component, so that no rigid motion remains.
+    kind "uniaxial_roller": symmetry rollers: the last component is prescribed on the bottom (0)
+      and top (-strain H) faces, the first component on the face x = 0 and, in 3D, the second
+      component on the face y = 0 (all 0), so that no rigid motion remains.
     """
     kind: str
     strain: float
@@ -373,11 +373,8 @@ def make_bvp(cfg: LatticeConfig, case: LoadCase) -> dict:
         ubar[:, d - 1] = -case.strain * z
     elif case.kind == "uniaxial_roller":
         fixed[bot_m | top_m, d - 1] = 1
-        origin = np.all([I[ax] == 0 for ax in range(d)], axis=0)
-        fixed[origin, :d - 1] = 1
-        if d == 3:
-            xend = (I[0] == shp[0] - 1) & (I[1] == 0) & (I[2] == 0)
-            fixed[xend, 1] = 1
+        for ax in range(d - 1):
+            fixed[I[ax] == 0, ax] = 1
         ubar[:, d - 1] = -case.strain * z
     else:
         raise ValueError(case.kind)

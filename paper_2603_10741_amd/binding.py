@@ -16,10 +16,33 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # LAT_LIBRARY may name another build of the same ABI (e.g. a tuning variant)
 LIB_PATH = os.environ.get("LAT_LIBRARY") or os.path.join(_HERE, "liblat.so")
 
-LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP = range(8)
+(LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP, LAT_E_NOCONV,
+ LAT_E_SINGULAR) = range(10)
 RULE_FULL, RULE_REDUCED = 0, 1
 F64, F32, BF16 = 0, 1, 2
 INFO_KEYS = ["dim", "nel", "ncells", "nloc", "nelem", "E", "nsnap", "ld", "ngroups", "npacked", "nglobal", "cap"]
+
+
+class NewtonOpts(ctypes.Structure):
+    """lat_newton_opts"""
+    _fields_ = [("n_inc", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
+                ("cap", ctypes.c_int32), ("cg_maxit", ctypes.c_int32), ("cg_check", ctypes.c_int32),
+                ("snap_rule", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rb_tol", ctypes.c_double),
+                ("newton_tol", ctypes.c_double), ("armijo_beta", ctypes.c_double), ("armijo_c", ctypes.c_double),
+                ("cg_tol", ctypes.c_double)]
+
+
+class NewtonRecord(ctypes.Structure):
+    """lat_newton_record"""
+    _fields_ = [("increment", ctypes.c_int32), ("iteration", ctypes.c_int32), ("n_r", ctypes.c_int32),
+                ("backtracks", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("greedy_status", ctypes.c_int32),
+                ("cg_status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("step", ctypes.c_double),
+                ("res_before", ctypes.c_double), ("res_after", ctypes.c_double), ("res0", ctypes.c_double),
+                ("rb_achieved", ctypes.c_double), ("cg_relres", ctypes.c_double), ("t_init_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_eval_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class LatError(RuntimeError):
@@ -62,6 +85,8 @@ def _lib():
             "lat_cil_to_canon": (ctypes.c_int, [P, P, I64, P, P]),
             "lat_canon_to_cil": (ctypes.c_int, [P, P, I64, P, P]),
             "lat_plain_ops_to_canon": (ctypes.c_int, [P, P, P, P]),
+            "lat_rom_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, F, I32, I32, P, P, P]),
+            "lat_newton_solve": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, I32, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -77,7 +102,7 @@ def exported_symbols():
             "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_apply_combo", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
-            "lat_plain_ops_to_canon"]
+            "lat_plain_ops_to_canon", "lat_rom_solve", "lat_newton_solve"]
 
 
 def _ptr(t):
@@ -277,3 +302,33 @@ class Plan:
         out = self._f64(self.ncells, self.nsnap)
         _ok(_lib().lat_plain_ops_to_canon(self._p, _ptr(ops), _ptr(out), _stream()), "plain_ops_to_canon")
         return out
+
+    # ------------------------------------------------------------------ nonlinear solve
+    def rom_solve(self, K, n_r, alpha, fixed, b, tol=1e-10, maxit=20000, check=32, x=None):
+        """K~ x = b on the free components (lat_rom_solve).  Returns (x, status, iters, relres);
+        status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other codes raise."""
+        x = self._f64(max(self.nglobal, 1) * self.dim) if x is None else x
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        st = _lib().lat_rom_solve(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(fixed), _ptr(b), _ptr(x), float(tol),
+                                  int(maxit), int(check), ctypes.byref(it), ctypes.byref(rel), _stream())
+        if st not in (LAT_OK, LAT_E_NOCONV, LAT_E_SINGULAR):
+            raise LatError(st, "rom_solve")
+        return x, st, it.value, rel.value
+
+    def newton_solve(self, mu, lam, fixed, ubar, u, f_ext=None, n_inc=4, max_newton=30, max_backtrack=30, cap=None,
+                     rb_tol=3e-4, newton_tol=1e-6, armijo_beta=0.5, armijo_c=1e-4, cg_tol=1e-10, cg_maxit=20000,
+                     cg_check=32, snap_rule=RULE_FULL, max_records=1024):
+        """Load-stepped Newton-Raphson with Armijo backtracking (lat_newton_solve); u is updated in
+        place.  Returns (status, records); status is LAT_OK, LAT_E_NOCONV, LAT_E_INVERTED or
+        LAT_E_NONFINITE, other codes raise."""
+        o = NewtonOpts(int(n_inc), int(max_newton), int(max_backtrack), int(cap if cap is not None else self.cap),
+                       int(cg_maxit), int(cg_check), int(snap_rule), 0, float(rb_tol), float(newton_tol),
+                       float(armijo_beta), float(armijo_c), float(cg_tol))
+        recs = (NewtonRecord * max(int(max_records), 1))()
+        nrec = ctypes.c_int32(0)
+        st = _lib().lat_newton_solve(self._p, _ptr(mu), _ptr(lam), _ptr(fixed), _ptr(ubar), _ptr(f_ext), ctypes.byref(o),
+                                     _ptr(u), recs, int(max_records), ctypes.byref(nrec), _stream())
+        if st not in (LAT_OK, LAT_E_NOCONV, LAT_E_INVERTED, LAT_E_NONFINITE):
+            raise LatError(st, "newton_solve")
+        return st, [recs[i].as_dict() for i in range(min(nrec.value, int(max_records)))]

@@ -1,0 +1,613 @@
+// Load-stepped Newton-Raphson on the ROM tangent (Sec. 2.2.5) and the matrix-free tangent solve
+// K~ du = -r (eq. linsys with the operator of eq. romstiffnessmatrix) by preconditioned MINRES.
+//
+// K~ is symmetric (every principal tangent is the Hessian of a stored energy) but need not be
+// definite: the tangent of a pre-stressed lattice loses definiteness near buckling, and the
+// Newton step is still defined there.  MINRES (Lanczos on K~ with the preconditioner
+// D = |diag K~|, the tridiagonal factor reduced by Givens rotations) minimises ||b - K~ x||_{D^-1}
+// over the Krylov space for any symmetric non-singular K~, so the step equals that of a direct
+// solve up to the tolerance.
+//
+// A product K~ z is one ROM apply with a single right-hand side on the packed layout, followed
+// by an owner-ordered assembly onto the global nodes that also forms the partial sums of z.K~z.
+// The Lanczos and rotation scalars live in a small device control block and are finalised by
+// single-workgroup kernels, so the host only reads the control block every `check` iterations.
+// Every reduction has a fixed order (per-block LDS trees, then one block summing the block
+// partials in index order): a solve is reproducible bit for bit on a given plan.
+#include <chrono>
+#include <cmath>
+
+#include "lat_internal.h"
+
+namespace {
+
+constexpr int NB = 256;   // threads per workgroup of the vector kernels
+
+struct NGrid {
+    int dim, nel, nn, nloc;
+    int ncell[3];
+    int64_t gs[3];
+};
+
+NGrid make_ngrid(const lat_plan *P)
+{
+    NGrid g;
+    g.dim = P->dim; g.nel = P->nel; g.nn = P->nn; g.nloc = P->nloc;
+    for (int ax = 0; ax < 3; ++ax) {
+        g.ncell[ax] = P->ncell[ax];
+        g.gs[ax] = ax < P->dim ? (int64_t)P->ncell[ax] * P->nel + 1 : 1;
+    }
+    return g;
+}
+
+// Tables of the packed layout, for locating a cell's local node in a packed vector.
+struct PackMap {
+    const int32_t *lane;   // [N_s] canonical cell -> plan lane
+    const int32_t *uidx;   // [ngroups][nloc] packed index within the group, or -1
+    const int32_t *goff;   // [ngroups+1] packed-node offset of each group
+};
+
+// Calls f(cell, a) for every cell owning global node G (background id bg), in ascending
+// canonical cell id: the order in which the library's assembly sums.
+template <class F>
+__device__ __forceinline__ void for_owners(const NGrid &g, int64_t bg, const int32_t *__restrict__ l2g, F &&f)
+{
+    int gc[3] = {0, 0, 0};
+    for (int ax = 0; ax < g.dim; ++ax) { gc[ax] = (int)(bg % g.gs[ax]); bg /= g.gs[ax]; }
+    for (int kz = (g.dim == 3 ? 1 : 0); kz >= 0; --kz)
+        for (int ky = 1; ky >= 0; --ky)
+            for (int kx = 1; kx >= 0; --kx) {
+                const int kk[3] = {kx, ky, kz};
+                int cc[3] = {0, 0, 0}, ia[3] = {0, 0, 0};
+                bool ok = true;
+                for (int ax = 0; ax < g.dim; ++ax) {
+                    const int base = gc[ax] / g.nel;
+                    const int c = kk[ax] ? base - 1 : base;
+                    const int loc = gc[ax] - c * g.nel;
+                    ok = ok && c >= 0 && c < g.ncell[ax] && loc >= 0 && loc <= g.nel;
+                    cc[ax] = c; ia[ax] = loc;
+                }
+                if (!ok) continue;
+                const int64_t cell = cc[0] + (int64_t)g.ncell[0] * (cc[1] + (int64_t)g.ncell[1] * cc[2]);
+                const int a = ia[0] + g.nn * (ia[1] + g.nn * ia[2]);
+                if (l2g[cell * g.nloc + a] < 0) continue;
+                f(cell, a);
+            }
+}
+
+// Packed index of component 0 of (cell, local node a) with one right-hand side; component i is
+// at + i * 64.  -1 if the node is not in the union of the cell's group (never for an owned node).
+__device__ __forceinline__ int64_t packed_slot(const PackMap &pm, int nloc, int dim, int64_t cell, int a)
+{
+    const int p = pm.lane[cell];
+    const int g = p / LAT_WAVE, l = p % LAT_WAVE;
+    const int qi = pm.uidx[(int64_t)g * nloc + a];
+    if (qi < 0) return -1;
+    const int64_t q = (int64_t)pm.goff[g] + qi;
+    return q * dim * LAT_WAVE + l;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = NB / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// sum of part[0..n) in a fixed order by one workgroup
+__device__ __forceinline__ double sum_parts(const double *__restrict__ part, int n, double *sh)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += NB) acc += part[i];
+    return block_sum(acc, sh);
+}
+
+// Scalars of the MINRES recurrence (ESW-style indexing: step j uses gamma_j, gamma_{j-1},
+// c_j, c_{j-1}, s_j, s_{j-1}; eta tracks +-||r_j||_{D^-1}).
+struct MrCtl {
+    double gam, gam_prev, c, c_prev, s, s_prev, eta, eta0, tol_eta;
+    double cv1, cv2;                 // Lanczos coefficients delta_j / gamma_j, gamma_j / gamma_{j-1}
+    double a1, a2, a3, cx, inv_gam;  // step coefficients for the direction and solution updates
+    int32_t done, last, status, iters;
+};
+
+// |diag K~| on the free components, inverted (0 on prescribed ones, 1 where the diagonal vanishes)
+__global__ void __launch_bounds__(NB) k_jacobi(NGrid g, int64_t nglobal, const int64_t *__restrict__ g2bg,
+                                               const int32_t *__restrict__ l2g, const double *__restrict__ K,
+                                               const double *__restrict__ alpha, int cap, int n_r, int E,
+                                               const uint8_t *__restrict__ fixed, double *__restrict__ dinv)
+{
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (G >= nglobal) return;
+    const int d = g.dim;
+    const int oc = d == 2 ? 4 : 13;   // offset index of (0, 0[, 0])
+    double dg[3] = {0.0, 0.0, 0.0};
+    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
+        for (int i = 0; i < d; ++i) {
+            const double *kr = K + ((int64_t)a * E + (oc * d + i) * d + i) * cap;
+            const double *ar = alpha + cell * cap;
+            double s = 0.0;
+            for (int k = 0; k < n_r; ++k) s = fma(ar[k], kr[k], s);
+            dg[i] += s;
+        }
+    });
+    for (int i = 0; i < d; ++i) {
+        const int64_t j = G * d + i;
+        const double a = fabs(dg[i]);
+        dinv[j] = fixed[j] ? 0.0 : (a > 0.0 ? 1.0 / a : 1.0);
+    }
+}
+
+// v1 = b (free), z1 = D^-1 v1; x = w0 = w1 = v0 = 0; partial <z1, v1>
+__global__ void __launch_bounds__(NB) k_mr_init(int64_t n, const uint8_t *__restrict__ fixed,
+                                                const double *__restrict__ dinv, const double *__restrict__ b,
+                                                double *__restrict__ x, double *__restrict__ v0, double *__restrict__ v1,
+                                                double *__restrict__ z1, double *__restrict__ w0, double *__restrict__ w1,
+                                                double *__restrict__ part)
+{
+    __shared__ double sh[NB];
+    double zv = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) {
+        const double bj = fixed[j] ? 0.0 : b[j];
+        const double zj = dinv[j] * bj;
+        x[j] = 0.0; v0[j] = 0.0; w0[j] = 0.0; w1[j] = 0.0;
+        v1[j] = bj; z1[j] = zj;
+        zv = fma(zj, bj, zv);
+    }
+    zv = block_sum(zv, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = zv;
+}
+
+__global__ void __launch_bounds__(NB) k_mr_init_fin(int nb, const double *__restrict__ part, double tol, MrCtl *ctl)
+{
+    __shared__ double sh[NB];
+    const double zv = sum_parts(part, nb, sh);
+    if (threadIdx.x == 0) {
+        const double g1 = sqrt(fmax(zv, 0.0));
+        ctl->gam = g1; ctl->gam_prev = 1.0;
+        ctl->c = 1.0; ctl->c_prev = 1.0; ctl->s = 0.0; ctl->s_prev = 0.0;
+        ctl->eta = g1; ctl->eta0 = g1; ctl->tol_eta = tol * g1;
+        ctl->inv_gam = g1 > 0.0 ? 1.0 / g1 : 0.0;
+        ctl->iters = 0; ctl->status = LAT_OK; ctl->last = 0;
+        ctl->done = !(g1 > 0.0);   // b = 0 on the free components: x = 0
+    }
+}
+
+// z <- z / gamma (the normalised Lanczos vector), scattered into the packed apply input
+__global__ void __launch_bounds__(NB) k_mr_scale(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
+                                                 const int32_t *__restrict__ l2g, double *__restrict__ z,
+                                                 double *__restrict__ ppk, const MrCtl *__restrict__ ctl)
+{
+    if (ctl->done) return;
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (G >= nglobal) return;
+    const int d = g.dim;
+    const double ig = ctl->inv_gam;
+    double zv[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < d; ++i) {
+        zv[i] = z[G * d + i] * ig;
+        z[G * d + i] = zv[i];
+    }
+    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
+        const int64_t s0 = packed_slot(pm, g.nloc, d, cell, a);
+        if (s0 >= 0)
+            for (int i = 0; i < d; ++i) ppk[s0 + (int64_t)i * LAT_WAVE] = zv[i];
+    });
+}
+
+// y = assembled, masked K~ z from the packed apply output; partial <y, z>
+__global__ void __launch_bounds__(NB) k_mr_ap(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
+                                              const int32_t *__restrict__ l2g, const uint8_t *__restrict__ fixed,
+                                              const double *__restrict__ ypk, const double *__restrict__ z,
+                                              double *__restrict__ y, double *__restrict__ part,
+                                              const MrCtl *__restrict__ ctl)
+{
+    __shared__ double sh[NB];
+    if (ctl->done) return;
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    const int d = g.dim;
+    double dot = 0.0;
+    if (G < nglobal) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
+            const int64_t s0 = packed_slot(pm, g.nloc, d, cell, a);
+            if (s0 >= 0)
+                for (int i = 0; i < d; ++i) acc[i] += ypk[s0 + (int64_t)i * LAT_WAVE];
+        });
+        for (int i = 0; i < d; ++i) {
+            const int64_t j = G * d + i;
+            const double v = fixed[j] ? 0.0 : acc[i];
+            y[j] = v;
+            dot = fma(z[j], v, dot);
+        }
+    }
+    dot = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+}
+
+// delta_j = <K~ z_j, z_j> and the Lanczos coefficients; ends the solve one step after the
+// rotation kernel has flagged convergence (the solution update of that step has been applied)
+__global__ void __launch_bounds__(NB) k_mr_delta(int nb, const double *__restrict__ part, MrCtl *ctl)
+{
+    __shared__ double sh[NB];
+    if (ctl->done) return;
+    if (ctl->last) {
+        if (threadIdx.x == 0) ctl->done = 1;
+        return;
+    }
+    const double delta = sum_parts(part, nb, sh);
+    if (threadIdx.x == 0) {
+        ctl->a1 = delta;   // kept until the rotation kernel of this step
+        ctl->cv1 = delta / ctl->gam;
+        ctl->cv2 = ctl->gam / ctl->gam_prev;
+    }
+}
+
+// v_{j+1} = y - cv1 v_j - cv2 v_{j-1} (written over v_{j-1}); z_{j+1} = D^-1 v_{j+1};
+// partial <z_{j+1}, v_{j+1}>
+__global__ void __launch_bounds__(NB) k_mr_v(int64_t n, const double *__restrict__ y, const double *__restrict__ vj,
+                                             double *__restrict__ vprev_next, const double *__restrict__ dinv,
+                                             double *__restrict__ znext, double *__restrict__ part,
+                                             const MrCtl *__restrict__ ctl)
+{
+    __shared__ double sh[NB];
+    if (ctl->done) return;
+    const double c1 = ctl->cv1, c2 = ctl->cv2;
+    double zv = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) {
+        const double v = fma(-c2, vprev_next[j], fma(-c1, vj[j], y[j]));
+        const double z = dinv[j] * v;
+        vprev_next[j] = v;
+        znext[j] = z;
+        zv = fma(z, v, zv);
+    }
+    zv = block_sum(zv, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = zv;
+}
+
+// gamma_{j+1}, the Givens rotation of step j, the step coefficients and the residual estimate
+__global__ void __launch_bounds__(NB) k_mr_rot(int nb, const double *__restrict__ part, int it, MrCtl *ctl)
+{
+    __shared__ double sh[NB];
+    if (ctl->done) return;
+    const double zv = sum_parts(part, nb, sh);
+    if (threadIdx.x == 0) {
+        const double delta = ctl->a1;
+        const double gn = sqrt(fmax(zv, 0.0));
+        const double g = ctl->gam;
+        const double a0 = ctl->c * delta - ctl->c_prev * ctl->s * g;
+        const double a1 = sqrt(a0 * a0 + gn * gn);
+        const double a2 = ctl->s * delta + ctl->c_prev * ctl->c * g;
+        const double a3 = ctl->s_prev * g;
+        if (!(a1 > 0.0) || !isfinite(a1)) {   // K~ singular on the Krylov space (or non-finite)
+            ctl->status = LAT_E_SINGULAR;
+            ctl->done = 1;
+        } else {
+            const double cn = a0 / a1, sn = gn / a1;
+            ctl->a1 = a1; ctl->a2 = a2; ctl->a3 = a3;
+            ctl->cx = cn * ctl->eta;
+            ctl->inv_gam = gn > 0.0 ? 1.0 / gn : 0.0;
+            ctl->eta = -sn * ctl->eta;
+            ctl->c_prev = ctl->c; ctl->c = cn;
+            ctl->s_prev = ctl->s; ctl->s = sn;
+            ctl->gam_prev = g; ctl->gam = gn;
+            ctl->iters = it + 1;
+            if (fabs(ctl->eta) <= ctl->tol_eta || !(gn > 0.0)) ctl->last = 1;
+        }
+    }
+}
+
+// w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1 (written over w_{j-1}); x += cx w_{j+1}
+__global__ void __launch_bounds__(NB) k_mr_x(int64_t n, const double *__restrict__ zj, const double *__restrict__ wj,
+                                             double *__restrict__ wprev_next, double *__restrict__ x,
+                                             const MrCtl *__restrict__ ctl)
+{
+    if (ctl->done) return;
+    const double ia1 = 1.0 / ctl->a1, a2 = ctl->a2, a3 = ctl->a3, cx = ctl->cx;
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) {
+        const double w = (zj[j] - a3 * wprev_next[j] - a2 * wj[j]) * ia1;
+        wprev_next[j] = w;
+        x[j] = fma(cx, w, x[j]);
+    }
+}
+
+__global__ void __launch_bounds__(NB) k_fill(int64_t n, double v, double *__restrict__ y)
+{
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) y[j] = v;
+}
+
+// y = a + s b
+__global__ void __launch_bounds__(NB) k_axpy(int64_t n, const double *__restrict__ a, double s,
+                                             const double *__restrict__ b, double *__restrict__ y)
+{
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB)
+        y[j] = fma(s, b[j], a[j]);
+}
+
+// r = (assembled f_int - lf f_ext) on free components, 0 on prescribed ones; partial r.r
+__global__ void __launch_bounds__(NB) k_residual(int64_t n, const double *__restrict__ fasm,
+                                                 const double *__restrict__ fext, double lf,
+                                                 const uint8_t *__restrict__ fixed, double *__restrict__ r,
+                                                 double *__restrict__ part)
+{
+    __shared__ double sh[NB];
+    double rr = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) {
+        double v = fasm[j];
+        if (fext) v = fma(-lf, fext[j], v);
+        if (fixed[j]) v = 0.0;
+        r[j] = v;
+        rr = fma(v, v, rr);
+    }
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(NB) k_sum_fin(int nb, const double *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ double sh[NB];
+    const double s = sum_parts(part, nb, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// x = -y
+__global__ void __launch_bounds__(NB) k_neg(int64_t n, const double *__restrict__ y, double *__restrict__ x)
+{
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) x[j] = -y[j];
+}
+
+unsigned vec_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(lat_cdiv(n, NB), 2048)); }
+
+// Device buffers of one call, released on every return path.
+struct Arena {
+    std::vector<void *> ptrs;
+    ~Arena() { for (void *p : ptrs) (void)hipFree(p); }
+    template <class T>
+    lat_status get(T **p, int64_t n)
+    {
+        if (hipMalloc((void **)p, (size_t)std::max<int64_t>(n, 1) * sizeof(T)) != hipSuccess) {
+            *p = nullptr;
+            return LAT_E_NOMEM;
+        }
+        ptrs.push_back((void *)*p);
+        return LAT_OK;
+    }
+};
+
+#define NCHK(expr) do { lat_status st_ = (expr); if (st_ != LAT_OK) return st_; } while (0)
+
+struct MrWork {
+    double *v[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
+    double *y = nullptr, *dinv = nullptr, *ppk = nullptr, *ypk = nullptr, *part = nullptr;
+    MrCtl *ctl = nullptr;
+    unsigned nbn = 1, nbv = 1;   // blocks over nodes, over components
+};
+
+lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w)
+{
+    const int64_t n = P->nglobal * P->dim;
+    const int64_t npk = std::max<int64_t>(P->npacked, 1) * P->dim * LAT_WAVE;
+    w.nbn = (unsigned)std::max<int64_t>(1, lat_cdiv(P->nglobal, NB));
+    w.nbv = vec_blocks(n);
+    for (auto &p : w.v) NCHK(ar.get(&p, n));
+    for (auto &p : w.z) NCHK(ar.get(&p, n));
+    for (auto &p : w.w) NCHK(ar.get(&p, n));
+    NCHK(ar.get(&w.y, n)); NCHK(ar.get(&w.dinv, n));
+    NCHK(ar.get(&w.ppk, npk)); NCHK(ar.get(&w.ypk, npk));
+    NCHK(ar.get(&w.part, (int64_t)std::max(w.nbn, w.nbv))); NCHK(ar.get(&w.ctl, 1));
+    return LAT_OK;
+}
+
+// Preconditioned MINRES on K~ from x = 0.  Synchronises the stream.  *relres = ||r||_{D^-1} /
+// ||b||_{D^-1} as tracked by the rotations.
+lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const double *alpha, const uint8_t *fixed,
+                  const double *b, double *x, double tol, int maxit, int check, int *iters, double *relres,
+                  hipStream_t s)
+{
+    const NGrid g = make_ngrid(P);
+    const PackMap pm{P->lane, P->uidx, P->goff};
+    const int64_t n = P->nglobal * P->dim;
+    const int64_t npk = std::max<int64_t>(P->npacked, 1) * P->dim * LAT_WAVE;
+    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(npk)), dim3(NB), 0, s, npk, 0.0, w.ppk);
+    hipLaunchKernelGGL(k_jacobi, dim3(w.nbn), dim3(NB), 0, s, g, P->nglobal, P->g2bg, P->l2g, K, alpha, P->cap, n_r,
+                       P->E, fixed, w.dinv);
+    // v_0 = v[0], v_1 = v[1], z_1 = z[1], w_0 = w[0], w_1 = w[1]
+    hipLaunchKernelGGL(k_mr_init, dim3(w.nbv), dim3(NB), 0, s, n, fixed, w.dinv, b, x, w.v[0], w.v[1], w.z[1], w.w[0],
+                       w.w[1], w.part);
+    hipLaunchKernelGGL(k_mr_init_fin, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, tol, w.ctl);
+    LAT_LAUNCH_CHECK();
+    MrCtl h{};
+    int it = 0;
+    for (;;) {
+        LAT_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(MrCtl), hipMemcpyDeviceToHost, s));
+        LAT_HIP(hipStreamSynchronize(s));
+        if (h.done || h.last || it >= maxit) break;
+        const int nb = std::min(check, maxit - it);
+        for (int k = 0; k < nb; ++k, ++it) {
+            const int j = it + 1;                      // Lanczos step
+            double *vj = w.v[j % 2], *vjm1 = w.v[(j + 1) % 2];   // v_{j+1} is written over v_{j-1}
+            double *zj = w.z[j % 2], *zj1 = w.z[(j + 1) % 2];
+            double *wj = w.w[j % 2], *wjm1 = w.w[(j + 1) % 2];   // w_{j+1} is written over w_{j-1}
+            hipLaunchKernelGGL(k_mr_scale, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, zj, w.ppk,
+                               w.ctl);
+            LAT_LAUNCH_CHECK();
+            NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, s));
+            hipLaunchKernelGGL(k_mr_ap, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, fixed, w.ypk,
+                               zj, w.y, w.part, w.ctl);
+            hipLaunchKernelGGL(k_mr_delta, dim3(1), dim3(NB), 0, s, (int)w.nbn, w.part, w.ctl);
+            hipLaunchKernelGGL(k_mr_v, dim3(w.nbv), dim3(NB), 0, s, n, w.y, vj, vjm1, w.dinv, zj1, w.part, w.ctl);
+            hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, it, w.ctl);
+            hipLaunchKernelGGL(k_mr_x, dim3(w.nbv), dim3(NB), 0, s, n, zj, wj, wjm1, x, w.ctl);
+            LAT_LAUNCH_CHECK();
+        }
+    }
+    if (iters) *iters = h.iters;
+    if (relres) *relres = h.eta0 > 0.0 ? std::fabs(h.eta) / h.eta0 : 0.0;
+    if (h.status == LAT_E_SINGULAR) return LAT_E_SINGULAR;
+    return (h.done || h.last) ? LAT_OK : LAT_E_NOCONV;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const double *alpha, const uint8_t *fixed,
+                         const double *b, double *x, double tol, int32_t maxit, int32_t check, int32_t *iters,
+                         double *relres, hipStream_t stream)
+{
+    if (!P || !K || !alpha || !fixed || !b || !x) return LAT_E_ARG;
+    if (n_r < 0 || n_r > P->cap || !(tol > 0.0) || maxit < 0 || check < 1) return LAT_E_ARG;
+    if (P->nglobal == 0) {
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return LAT_OK;
+    }
+    Arena ar;
+    MrWork w;
+    NCHK(mr_alloc(P, ar, w));
+    int it = 0;
+    double rr = 0.0;
+    const lat_status st = mr_run(P, w, K, n_r, alpha, fixed, b, x, tol, maxit, check, &it, &rr, stream);
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    LAT_HIP(hipStreamSynchronize(stream));
+    return st;
+}
+
+lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *lam, const uint8_t *fixed,
+                            const double *ubar, const double *f_ext, const lat_newton_opts *o, double *u,
+                            lat_newton_record *records, int32_t max_records, int32_t *n_records, hipStream_t s)
+{
+    if (n_records) *n_records = 0;
+    if (!P || !mu || !lam || !fixed || !ubar || !o || !u) return LAT_E_ARG;
+    if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
+        o->cg_maxit < 1 || o->cg_check < 1 || (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
+        !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
+        !(o->armijo_c >= 0.0 && o->armijo_c < 1.0) || !(o->cg_tol > 0.0) || max_records < 0 ||
+        (max_records > 0 && !records))
+        return LAT_E_ARG;
+    if (P->nglobal == 0) return LAT_OK;
+    const int d = P->dim;
+    const int64_t n = P->nglobal * d;
+    Arena ar;
+    MrWork w;
+    NCHK(mr_alloc(P, ar, w));
+    double *u_try, *du, *rhs, *r, *r_try, *fasm, *f_cil, *snap, *K, *alpha, *R, *scal;
+    int32_t *S, *nr_d, *st_d, *gst_d;
+    NCHK(ar.get(&u_try, n)); NCHK(ar.get(&du, n)); NCHK(ar.get(&rhs, n)); NCHK(ar.get(&r, n));
+    NCHK(ar.get(&r_try, n)); NCHK(ar.get(&fasm, n));
+    NCHK(ar.get(&f_cil, (int64_t)P->nloc * d * P->ld));
+    NCHK(ar.get(&snap, P->nsnap * P->ld));
+    NCHK(ar.get(&K, (int64_t)P->nloc * P->E * P->cap));
+    NCHK(ar.get(&alpha, P->ncells * P->cap));
+    NCHK(ar.get(&R, (int64_t)P->cap * P->cap));
+    NCHK(ar.get(&scal, 2));
+    NCHK(ar.get(&S, P->cap)); NCHK(ar.get(&nr_d, 1)); NCHK(ar.get(&st_d, 2)); NCHK(ar.get(&gst_d, 2));
+    const unsigned nbv = w.nbv;
+    const lat_rule rule = (lat_rule)o->snap_rule;
+
+    // residual (and snapshots) at `at` into `res`; returns the HOST norm (inf if not admissible)
+    auto evaluate = [&](const double *at, double lf, double *res, double *norm, int32_t *code) -> lat_status {
+        NCHK(lat_status_reset(st_d, s));
+        NCHK(lat_residual_tangent(P, at, mu, lam, rule, f_cil, nullptr, snap, nullptr, st_d, s));
+        NCHK(lat_assemble(P, f_cil, d, fasm, s));
+        hipLaunchKernelGGL(k_residual, dim3(nbv), dim3(NB), 0, s, n, fasm, f_ext, lf, fixed, res, w.part);
+        hipLaunchKernelGGL(k_sum_fin, dim3(1), dim3(NB), 0, s, (int)nbv, w.part, scal);
+        LAT_LAUNCH_CHECK();
+        double rr = 0.0;
+        int32_t hst[2] = {0, 0};
+        LAT_HIP(hipMemcpyAsync(&rr, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        LAT_HIP(hipMemcpyAsync(hst, st_d, sizeof(hst), hipMemcpyDeviceToHost, s));
+        LAT_HIP(hipStreamSynchronize(s));
+        *code = hst[0];
+        *norm = (hst[0] == LAT_OK && std::isfinite(rr)) ? std::sqrt(rr) : INFINITY;
+        return LAT_OK;
+    };
+
+    int nrec = 0;
+    lat_status result = LAT_OK;
+    for (int t = 1; t <= o->n_inc && result == LAT_OK; ++t) {
+        const double lf = (double)t / o->n_inc;
+        auto t0 = std::chrono::steady_clock::now();
+        hipLaunchKernelGGL(k_axpy, dim3(nbv), dim3(NB), 0, s, n, u, 1.0 / o->n_inc, ubar, u);
+        LAT_LAUNCH_CHECK();
+        double rn = 0.0;
+        int32_t code = 0;
+        NCHK(evaluate(u, lf, r, &rn, &code));
+        if (code != LAT_OK) return (lat_status)code;
+        double t_eval = ms_since(t0);
+        const double r0 = rn;
+        if (r0 == 0.0) continue;
+        bool conv = false;
+        for (int it = 0; it < o->max_newton; ++it) {
+            lat_newton_record rec{};
+            rec.increment = t; rec.iteration = it; rec.res_before = rn; rec.res0 = r0;
+            // reduced basis at u and the principal tangents
+            t0 = std::chrono::steady_clock::now();
+            NCHK(lat_status_reset(gst_d, s));
+            NCHK(lat_select_principal(P, snap, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R, nullptr, scal + 1,
+                                      gst_d, s));
+            int32_t hnr = 0, hg[2] = {0, 0};
+            double ach = 0.0;
+            LAT_HIP(hipMemcpyAsync(&hnr, nr_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LAT_HIP(hipMemcpyAsync(hg, gst_d, sizeof(hg), hipMemcpyDeviceToHost, s));
+            LAT_HIP(hipMemcpyAsync(&ach, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            LAT_HIP(hipStreamSynchronize(s));
+            NCHK(lat_status_reset(st_d, s));
+            NCHK(lat_principal_ops(P, u, mu, lam, S, hnr, K, nullptr, nullptr, st_d, s));
+            LAT_HIP(hipStreamSynchronize(s));
+            rec.n_r = hnr; rec.rb_achieved = ach; rec.greedy_status = hg[0];
+            rec.t_init_ms = ms_since(t0);
+            // tangent solve K~ du = -r
+            t0 = std::chrono::steady_clock::now();
+            hipLaunchKernelGGL(k_neg, dim3(nbv), dim3(NB), 0, s, n, r, rhs);
+            LAT_LAUNCH_CHECK();
+            int cgit = 0;
+            double cgrel = 0.0;
+            const lat_status cst = mr_run(P, w, K, hnr, alpha, fixed, rhs, du, o->cg_tol, o->cg_maxit, o->cg_check,
+                                          &cgit, &cgrel, s);
+            if (cst != LAT_OK && cst != LAT_E_NOCONV && cst != LAT_E_SINGULAR) return cst;
+            rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst;
+            rec.t_solve_ms = ms_since(t0);
+            // Armijo backtracking on ||r||
+            t0 = std::chrono::steady_clock::now();
+            int m = 0;
+            double step = 1.0, rt = INFINITY;
+            bool ok = false;
+            for (; m <= o->max_backtrack; ++m, step *= o->armijo_beta) {
+                hipLaunchKernelGGL(k_axpy, dim3(nbv), dim3(NB), 0, s, n, u, step, du, u_try);
+                LAT_LAUNCH_CHECK();
+                NCHK(evaluate(u_try, lf, r_try, &rt, &code));
+                if (std::isfinite(rt) && rt <= (1.0 - o->armijo_c * step) * rn) { ok = true; break; }
+            }
+            rec.t_eval_ms = t_eval + ms_since(t0);
+            t_eval = 0.0;
+            rec.backtracks = m; rec.step = ok ? step : 0.0; rec.res_after = ok ? rt : rn;
+            if (records && nrec < max_records) records[nrec] = rec;
+            ++nrec;
+            if (!ok) { result = LAT_E_NOCONV; break; }
+            LAT_HIP(hipMemcpyAsync(u, u_try, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            std::swap(r_try, r);   // the snapshots in `snap` belong to the accepted state already
+            rn = rt;
+            if (rn <= o->newton_tol * r0) { conv = true; break; }
+        }
+        if (!conv && result == LAT_OK) result = LAT_E_NOCONV;
+    }
+    LAT_HIP(hipStreamSynchronize(s));
+    if (n_records) *n_records = nrec;
+    return result;
+}
+
+}  // extern "C"

@@ -377,6 +377,8 @@ const char *lat_status_string(lat_status s)
     case LAT_E_INVERTED: return "inverted element (J <= 0)";
     case LAT_E_NONFINITE: return "non-finite value";
     case LAT_W_CAP: return "principal-cell cap reached above tolerance";
+    case LAT_E_NOCONV: return "iteration limit reached before convergence";
+    case LAT_E_SINGULAR: return "singular operator in the tangent solve";
     }
     return "unknown status";
 }
