@@ -97,10 +97,24 @@ def main():
                     help="workload index (default: the 32x32 graded-hole lattice; the others are parity cases)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
+    ap.add_argument("--newton", action="store_true",
+                    help="time one load-stepped Newton-Raphson solve instead of the hot-path step")
+    ap.add_argument("--strain", type=float, default=0.04, help="--newton: total compression")
+    ap.add_argument("--shear", type=float, default=0.01, help="--newton: total shear of the top face")
+    ap.add_argument("--n-inc", type=int, default=4, help="--newton: load increments")
+    ap.add_argument("--rb-tol", type=float, default=3e-4, help="--newton: greedy tolerance")
+    ap.add_argument("--cap", type=int, default=64, help="--newton: principal-cell cap")
+    ap.add_argument("--max-newton", type=int, default=30, help="--newton: iterations per increment")
+    ap.add_argument("--solve-tol", type=float, default=1e-8, help="--newton: tangent-solve tolerance")
+    ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
+                    help="--newton: ROM tangent, or every cell's own tangent (the standard method)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.newton:
+        newton_main(args)
+        return
 
     import numpy as np
     import torch
@@ -273,6 +287,106 @@ def main():
         "rom_vs_plain_operator_rel_diff": rom_vs_plain,
         "stage_ms": {k: round(v, 4) for k, v in ms_stage.items()},
         "device_status": {"code": code, "first_cell": cell},
+    }
+    print(json.dumps(out))
+
+
+def newton_cpu_baseline(cfg, case, args, budget_s=12.0):
+    """The oracle's Newton iteration (snapshots + residual, greedy, sparse-LU tangent solve, one
+    line-search evaluation) on the 8 x 8-cell corner of the lattice, repeated within the budget."""
+    import numpy as np
+
+    import lattice as L
+    from oracle import newton as ON
+    sub = tuple(min(8, c) for c in cfg.ncell)
+    c2 = cfg.with_sub(sub)
+    bvp = L.make_bvp(c2, case)
+    mu, lam = L.make_material(c2)
+    P = ON.Problem(c2.dim, c2.ncell_eff, c2.nel, L.make_keep(c2), mu, lam, bvp["fixed"], bvp["ubar"])
+    u = P.ubar / case.n_inc
+    lf = 1.0 / case.n_inc
+    r, T, _, _ = P.evaluate(u, lf)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        du, g = P.tangent_solve(u, T, -r, args.rb_tol, args.cap)
+        r2, T2, _, _ = P.evaluate(u + du, lf)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 8:
+            break
+        u, r, T = u + du, r2, T2
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(el / n, 4), "unit": "s per Newton iteration", "cores": threads, "kind": "oracle",
+            "sample": f"{n} Newton iteration(s) of the first increment on the {sub[0]} x {sub[1]}-cell corner of the "
+                      f"workload ({P.ng * c2.dim} DOFs; the full lattice is {int(np.prod(cfg.ncell))} cells), "
+                      f"SuperLU (one thread) tangent solve, element loops on the OpenMP threads"}
+
+
+def newton_main(args):
+    """One load-stepped Newton-Raphson solve (compression + shear of the top face, bottom face
+    clamped) on the GPU; prints one JSON line with the time to solution and the per-iteration
+    split into reduced-basis set-up, tangent solve and residual/snapshot evaluations."""
+    import numpy as np
+    import torch
+
+    import lattice as L
+    from paper_2603_10741_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = L.config(args.workload)
+    case = L.LoadCase("compress_shear", args.strain, args.shear, args.n_inc)
+    log("newton workload", cfg.name, case)
+    keep = L.make_keep(cfg)
+    mu, lam = L.make_material(cfg)
+    bvp = L.make_bvp(cfg, case)
+    P = B.Plan(cfg.dim, cfg.ncell, cfg.nel, keep, cap=args.cap)
+    _, nact, g2bg, _ = P.dofmap()
+    g2bg = g2bg.cpu().numpy()
+    fixed = torch.from_numpy(np.ascontiguousarray(bvp["fixed"][g2bg])).to(dev)
+    ubar = torch.from_numpy(np.ascontiguousarray(bvp["ubar"][g2bg])).to(dev)
+    mu_t, lam_t = torch.from_numpy(mu).to(dev), torch.from_numpy(lam).to(dev)
+    u = torch.zeros(P.nglobal, cfg.dim, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, recs = P.newton_solve(mu_t, lam_t, fixed, ubar, u, n_inc=args.n_inc, max_newton=args.max_newton,
+                              cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=200000,
+                              cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = {k: float(sum(r[k] for r in recs)) for k in ("t_init_ms", "t_solve_ms", "t_eval_ms")}
+    its = int(sum(r["cg_iters"] for r in recs))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle Newton iterations on an 8 x 8-cell sample) ...")
+        cpu = newton_cpu_baseline(cfg, case, args, budget_s=args.cpu_budget)
+    out = {
+        "metric": "time to solution of the load-stepped Newton-Raphson solve on the ROM tangent",
+        "value": round(wall, 4),
+        "unit": "s",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "dtype": "f64",
+        "data": "synthetic",
+        "status": int(st),
+        "config": {"workload": cfg.name, "cells": P.ncells, "global_dofs": P.nglobal * cfg.dim,
+                   "load": {"kind": case.kind, "strain": case.strain, "shear": case.shear, "increments": case.n_inc},
+                   "tangent": args.tangent, "rb_tol": args.rb_tol, "cap": args.cap, "newton_tol": 1e-6,
+                   "armijo": [0.5, 1e-4],
+                   "tangent_solve": {"method": "MINRES, |diag| preconditioner", "tol": args.solve_tol}},
+        "cpu_baseline": cpu,
+        "newton_iterations": len(recs),
+        "tangent_solve_iterations": its,
+        "ms_per_tangent_solve_iteration": round(tot["t_solve_ms"] / max(its, 1), 5),
+        "split_ms": {k[2:-3]: round(v, 2) for k, v in tot.items()},
+        "iterations": [{"inc": r["increment"], "it": r["iteration"], "n_r": r["n_r"],
+                        "rb_achieved": float("%.3g" % r["rb_achieved"]), "m": r["backtracks"],
+                        "solve_its": r["cg_iters"], "solve_status": r["cg_status"],
+                        "rel_res": float("%.3g" % (r["res_after"] / r["res0"])),
+                        "ms": [round(r["t_init_ms"], 2), round(r["t_solve_ms"], 2), round(r["t_eval_ms"], 2)]}
+                       for r in recs],
     }
     print(json.dumps(out))
 

@@ -242,8 +242,11 @@ lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, doubl
  * eq. romstiffnessmatrix, K~ = sum_s A^s M_s (sum_k alpha_sk K_k) M_s A^{sT}) by MINRES
  * preconditioned with D = |diag K~|: K~ is symmetric but may be indefinite (a pre-stressed lattice
  * near buckling), and MINRES minimises ||b - K~ x||_{D^-1} over the Krylov space for any
- * symmetric non-singular K~.  Matrix-free: every product is one ROM apply (one right-hand side)
- * followed by an owner-ordered assembly.  K, n_r (HOST), alpha as for lat_apply_combo.
+ * symmetric non-singular K~.  Every product is a per-cell apply (one right-hand side) followed by an
+ * owner-ordered assembly.  materialize != 0: the combined stencils sum_k alpha_sk K_k of all cells
+ * are formed once (device memory n_packed E 64 doubles, the lat_apply_plain layout) and every
+ * product reads them; materialize == 0: every product is a ROM apply that forms them on the fly
+ * (no per-cell storage).  K, n_r (HOST), alpha as for lat_apply_combo.
  * b [n_global][d] (prescribed components ignored), x [n_global][d] out (prescribed components 0;
  * x starts from 0).  Stops when the residual estimate of the rotations satisfies
  * ||r||_{D^-1} <= tol ||b||_{D^-1} (tol > 0), after at most maxit iterations, checking on the host
@@ -252,7 +255,7 @@ lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, doubl
  * iterate), LAT_E_SINGULAR when K~ is singular on the Krylov space (x holds the last iterate). */
 lat_status lat_rom_solve(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
                          const uint8_t *fixed, const double *b, double *x, double tol, int32_t maxit,
-                         int32_t check, int32_t *iters, double *relres, hipStream_t stream);
+                         int32_t check, int32_t materialize, int32_t *iters, double *relres, hipStream_t stream);
 
 /* Options of lat_newton_solve (HOST struct). */
 typedef struct {
@@ -263,7 +266,11 @@ typedef struct {
     int32_t cg_maxit;       /* MINRES iterations per tangent solve, >= 1 */
     int32_t cg_check;       /* iterations between host convergence reads, >= 1 */
     int32_t snap_rule;      /* lat_rule of the snapshots fed to the greedy */
-    int32_t reserved;       /* 0 */
+    int32_t verbose;        /* nonzero: one progress line per Newton iteration on stderr */
+    int32_t matvec;         /* ROM tangent products: 0 = combined stencils formed once per iteration,
+                               1 = ROM apply forming them on the fly (see lat_rom_solve) */
+    int32_t tangent;        /* 0 = ROM tangent (the method), 1 = every cell's own full-rule tangent
+                               (the standard method, for comparison; no greedy) */
     double rb_tol;          /* greedy tolerance (Algorithm 1), > 0 */
     double newton_tol;      /* stop an increment at ||r|| / ||r(u_0)|| <= newton_tol, > 0 */
     double armijo_beta;     /* step reduction factor, in (0, 1) */
@@ -275,7 +282,7 @@ typedef struct {
 typedef struct {
     int32_t increment;      /* 1..n_inc */
     int32_t iteration;      /* 0-based within the increment */
-    int32_t n_r;            /* principal cells of this iteration's reduced basis */
+    int32_t n_r;            /* principal cells of this iteration's reduced basis (0: standard method) */
     int32_t backtracks;     /* Armijo exponent m of the accepted step beta^m */
     int32_t cg_iters;       /* MINRES iterations of the tangent solve */
     int32_t greedy_status;  /* LAT_OK or LAT_W_CAP */

@@ -7,9 +7,9 @@ What it computes (Sec. 2.2.5, Newton-Raphson method; Sec. 3.2, fast assembly):
   * residual r(u) = sum_s A^s f^{int,s}(A^{sT} u) - lf f_ext (eq. residualvector), zero on the
     prescribed components;
   * at every Newton iteration the reduced basis is rebuilt from the snapshots at the current
-    state (Algorithm 1, Sec. 3.2.3) and the tangent of eq. linsys is replaced by the ROM operator
-    K~ = sum_s A^s M_s (sum_k alpha_sk K_k) M_s A^{sT} (eq. romstiffnessmatrix), K_k the full-rule
-    tangents of the principal cells;
+    state (Algorithm 1, Sec. 3.2.3; full or reduced quadrature, eq. snapshots) and the tangent of
+    eq. linsys is replaced by the ROM operator K~ = sum_s A^s M_s (sum_k alpha_sk K_k) M_s A^{sT}
+    (eq. romstiffnessmatrix), K_k the full-rule tangents of the principal cells;
   * the tangent system K~ du = -r is solved exactly on the free components (sparse LU);
   * Armijo's rule: the smallest m >= 0 with ||r(u + beta^m du)|| <= (1 - c beta^m) ||r(u)||,
     beta = 1/2, c = 1e-4; an inverted element (J <= 0) at a trial counts as a failed trial;
@@ -107,13 +107,30 @@ class Problem:
         self.free = ~self.fixed.ravel()
 
     def evaluate(self, u, lf, want_T=True, want_energy=False):
-        """(r masked [n_global][d], T [N_s][n_snap] or None, status, energy per cell or None)."""
+        """(r masked [n_global][d], T [N_s][n_snap] or None, status, energy per cell or None).
+
+        The residual and energy always use the full rule (the residual is not reduced, Sec. 4);
+        the snapshots T use the problem's snapshot rule."""
         ul = gather_local(u, self.l2g)
-        ev = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=self.rule, want_f=True,
-                        want_energy=want_energy, want_T=want_T)
+        full = self.rule == RULE_FULL
+        ev = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=RULE_FULL, want_f=True,
+                        want_energy=want_energy, want_T=want_T and full)
+        T = ev["T"]
+        if want_T and not full:
+            T = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=self.rule, want_f=False,
+                           want_energy=False, want_T=True)["T"]
         r = assemble(ev["f"], self.l2g, self.ng) - lf * self.fext
         r[self.fixed] = 0.0
-        return r, ev["T"], ev["status"], ev["energy"]
+        return r, T, ev["status"], ev["energy"]
+
+    def principal_tangents(self, u, S, T):
+        """Full-rule tangents K_k of the principal cells S (eq. reducedbasis); these are the
+        snapshots themselves when the snapshots use the full rule."""
+        if self.rule == RULE_FULL:
+            return T[S]
+        ul = gather_local(u, self.l2g)[S]
+        return cells_eval(self.dim, self.nel, self.keep[S], ul, self.mu[S], self.lam[S], rule=RULE_FULL,
+                          want_f=False, want_energy=False, want_T=True)["T"]
 
     def total_energy(self, u, lf):
         """Pi(u) = sum_s W_s(u^s) - lf f_ext . u (the potential whose gradient is r)."""
@@ -122,11 +139,12 @@ class Problem:
             return np.inf
         return float(np.sum(en) - lf * np.sum(self.fext * u))
 
-    def tangent_solve(self, T, rhs, rb_tol, cap, exact=False):
-        """Greedy on T, then K~ du = rhs on the free components.  Returns (du, greedy dict)."""
+    def tangent_solve(self, u, T, rhs, rb_tol, cap):
+        """Greedy on the snapshots T at u, then K~ du = rhs on the free components.
+        Returns (du, greedy dict)."""
         g = greedy(T, rb_tol, cap, keep_Z=False)
         S = g["S"][:g["n_r"]]
-        K = rom_matrix(self.dim, self.nel, T[S], g["alpha"], self.l2g, self.ng)
+        K = rom_matrix(self.dim, self.nel, self.principal_tangents(u, S, T), g["alpha"], self.l2g, self.ng)
         f = self.free
         du = np.zeros(self.ng * self.dim)
         if f.any():
@@ -156,7 +174,7 @@ def newton_solve(prob: Problem, n_inc=4, rb_tol=3e-4, cap=64, newton_tol=1e-6, m
             continue
         done = False
         for it in range(max_newton):
-            du, g = prob.tangent_solve(T, -r, rb_tol, cap)
+            du, g = prob.tangent_solve(u, T, -r, rb_tol, cap)
 
             def phi(s, u=u, du=du):
                 rt, Tt, stt, _ = prob.evaluate(u + s * du, lf)

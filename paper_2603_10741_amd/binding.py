@@ -27,7 +27,8 @@ class NewtonOpts(ctypes.Structure):
     """lat_newton_opts"""
     _fields_ = [("n_inc", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
                 ("cap", ctypes.c_int32), ("cg_maxit", ctypes.c_int32), ("cg_check", ctypes.c_int32),
-                ("snap_rule", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rb_tol", ctypes.c_double),
+                ("snap_rule", ctypes.c_int32), ("verbose", ctypes.c_int32), ("matvec", ctypes.c_int32),
+                ("tangent", ctypes.c_int32), ("rb_tol", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("armijo_beta", ctypes.c_double), ("armijo_c", ctypes.c_double),
                 ("cg_tol", ctypes.c_double)]
 
@@ -85,7 +86,7 @@ def _lib():
             "lat_cil_to_canon": (ctypes.c_int, [P, P, I64, P, P]),
             "lat_canon_to_cil": (ctypes.c_int, [P, P, I64, P, P]),
             "lat_plain_ops_to_canon": (ctypes.c_int, [P, P, P, P]),
-            "lat_rom_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, F, I32, I32, P, P, P]),
+            "lat_rom_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, F, I32, I32, I32, P, P, P]),
             "lat_newton_solve": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, I32, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -304,26 +305,29 @@ class Plan:
         return out
 
     # ------------------------------------------------------------------ nonlinear solve
-    def rom_solve(self, K, n_r, alpha, fixed, b, tol=1e-10, maxit=20000, check=32, x=None):
+    def rom_solve(self, K, n_r, alpha, fixed, b, tol=1e-10, maxit=20000, check=32, materialize=True, x=None):
         """K~ x = b on the free components (lat_rom_solve).  Returns (x, status, iters, relres);
         status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other codes raise."""
         x = self._f64(max(self.nglobal, 1) * self.dim) if x is None else x
         it = ctypes.c_int32(0)
         rel = ctypes.c_double(0.0)
         st = _lib().lat_rom_solve(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(fixed), _ptr(b), _ptr(x), float(tol),
-                                  int(maxit), int(check), ctypes.byref(it), ctypes.byref(rel), _stream())
+                                  int(maxit), int(check), int(bool(materialize)), ctypes.byref(it), ctypes.byref(rel),
+                                  _stream())
         if st not in (LAT_OK, LAT_E_NOCONV, LAT_E_SINGULAR):
             raise LatError(st, "rom_solve")
         return x, st, it.value, rel.value
 
     def newton_solve(self, mu, lam, fixed, ubar, u, f_ext=None, n_inc=4, max_newton=30, max_backtrack=30, cap=None,
                      rb_tol=3e-4, newton_tol=1e-6, armijo_beta=0.5, armijo_c=1e-4, cg_tol=1e-10, cg_maxit=20000,
-                     cg_check=32, snap_rule=RULE_FULL, max_records=1024):
+                     cg_check=32, snap_rule=RULE_FULL, max_records=1024, verbose=False, matvec=0,
+                     tangent=0):
         """Load-stepped Newton-Raphson with Armijo backtracking (lat_newton_solve); u is updated in
         place.  Returns (status, records); status is LAT_OK, LAT_E_NOCONV, LAT_E_INVERTED or
         LAT_E_NONFINITE, other codes raise."""
         o = NewtonOpts(int(n_inc), int(max_newton), int(max_backtrack), int(cap if cap is not None else self.cap),
-                       int(cg_maxit), int(cg_check), int(snap_rule), 0, float(rb_tol), float(newton_tol),
+                       int(cg_maxit), int(cg_check), int(snap_rule), int(bool(verbose)), int(matvec), int(tangent), float(rb_tol),
+                       float(newton_tol),
                        float(armijo_beta), float(armijo_c), float(cg_tol))
         recs = (NewtonRecord * max(int(max_records), 1))()
         nrec = ctypes.c_int32(0)

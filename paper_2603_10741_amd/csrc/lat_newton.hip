@@ -87,6 +87,18 @@ __device__ __forceinline__ int64_t packed_slot(const PackMap &pm, int nloc, int 
     return q * dim * LAT_WAVE + l;
 }
 
+// Packed node q and lane l of (cell, local node a); false if the node is not in the union of the
+// cell's group (never for an owned node).
+__device__ __forceinline__ bool packed_ql(const PackMap &pm, int nloc, int64_t cell, int a, int64_t *q, int *l)
+{
+    const int p = pm.lane[cell];
+    const int g = p / LAT_WAVE;
+    const int qi = pm.uidx[(int64_t)g * nloc + a];
+    *q = (int64_t)pm.goff[g] + qi;
+    *l = p % LAT_WAVE;
+    return qi >= 0;
+}
+
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
     const int t = threadIdx.x;
@@ -145,6 +157,29 @@ __global__ void __launch_bounds__(NB) k_jacobi(NGrid g, int64_t nglobal, const i
     }
 }
 
+// The same from per-cell stencils in the packed layout of lat_apply_plain
+__global__ void __launch_bounds__(NB) k_jacobi_ops(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
+                                                   const int32_t *__restrict__ l2g, const double *__restrict__ ops,
+                                                   int E, const uint8_t *__restrict__ fixed, double *__restrict__ dinv)
+{
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (G >= nglobal) return;
+    const int d = g.dim;
+    const int oc = d == 2 ? 4 : 13;
+    double dg[3] = {0.0, 0.0, 0.0};
+    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
+        int64_t q;
+        int l;
+        if (!packed_ql(pm, g.nloc, cell, a, &q, &l)) return;
+        for (int i = 0; i < d; ++i) dg[i] += ops[(q * E + (oc * d + i) * d + i) * LAT_WAVE + l];
+    });
+    for (int i = 0; i < d; ++i) {
+        const int64_t j = G * d + i;
+        const double a = fabs(dg[i]);
+        dinv[j] = fixed[j] ? 0.0 : (a > 0.0 ? 1.0 / a : 1.0);
+    }
+}
+
 // v1 = b (free), z1 = D^-1 v1; x = w0 = w1 = v0 = 0; partial <z1, v1>
 __global__ void __launch_bounds__(NB) k_mr_init(int64_t n, const uint8_t *__restrict__ fixed,
                                                 const double *__restrict__ dinv, const double *__restrict__ b,
@@ -180,7 +215,7 @@ __global__ void __launch_bounds__(NB) k_mr_init_fin(int nb, const double *__rest
     }
 }
 
-// z <- z / gamma (the normalised Lanczos vector), scattered into the packed apply input
+// z <- z / gamma (the first normalised Lanczos vector), scattered into the packed apply input
 __global__ void __launch_bounds__(NB) k_mr_scale(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
                                                  const int32_t *__restrict__ l2g, double *__restrict__ z,
                                                  double *__restrict__ ppk, const MrCtl *__restrict__ ctl)
@@ -304,18 +339,83 @@ __global__ void __launch_bounds__(NB) k_mr_rot(int nb, const double *__restrict_
     }
 }
 
-// w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1 (written over w_{j-1}); x += cx w_{j+1}
-__global__ void __launch_bounds__(NB) k_mr_x(int64_t n, const double *__restrict__ zj, const double *__restrict__ wj,
-                                             double *__restrict__ wprev_next, double *__restrict__ x,
-                                             const MrCtl *__restrict__ ctl)
+// End of step j, per node: w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1 (written over w_{j-1}),
+// x += cx w_{j+1}; then the next Lanczos vector z_{j+1} <- z_{j+1} / gamma_{j+1}, scattered into
+// the packed input of the next product.
+__global__ void __launch_bounds__(NB) k_mr_x(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
+                                             const int32_t *__restrict__ l2g, const double *__restrict__ zj,
+                                             const double *__restrict__ wj, double *__restrict__ wprev_next,
+                                             double *__restrict__ x, double *__restrict__ znext,
+                                             double *__restrict__ ppk, const MrCtl *__restrict__ ctl)
 {
     if (ctl->done) return;
-    const double ia1 = 1.0 / ctl->a1, a2 = ctl->a2, a3 = ctl->a3, cx = ctl->cx;
-    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) {
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (G >= nglobal) return;
+    const int d = g.dim;
+    const double ia1 = 1.0 / ctl->a1, a2 = ctl->a2, a3 = ctl->a3, cx = ctl->cx, ig = ctl->inv_gam;
+    double zv[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < d; ++i) {
+        const int64_t j = G * d + i;
         const double w = (zj[j] - a3 * wprev_next[j] - a2 * wj[j]) * ia1;
         wprev_next[j] = w;
         x[j] = fma(cx, w, x[j]);
+        zv[i] = znext[j] * ig;
+        znext[j] = zv[i];
     }
+    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
+        const int64_t s0 = packed_slot(pm, g.nloc, d, cell, a);
+        if (s0 >= 0)
+            for (int i = 0; i < d; ++i) ppk[s0 + (int64_t)i * LAT_WAVE] = zv[i];
+    });
+}
+
+// Combined stencil of every cell, K~_s = sum_k alpha_sk K_k (eq. romstiffnessmatrix), in the
+// packed per-cell operator layout of lat_apply_plain: ops[(q E + e) 64 + l] for packed node q of
+// group g and lane l (cell perm[64 g + l]; padding lanes get 0).  One thread per (q, l) keeps its
+// cell's coefficients in registers and walks the E stencil entries of node unode[q]; the
+// principal entries it reads are the same for the 64 lanes of a wave.
+template <int NR>
+__global__ void __launch_bounds__(NB) k_combine_ops(int64_t npk, int E, int cap, int n_r,
+                                                    const int32_t *__restrict__ qgroup,
+                                                    const int32_t *__restrict__ unode, const int32_t *__restrict__ perm,
+                                                    const double *__restrict__ K, const double *__restrict__ alpha,
+                                                    double *__restrict__ ops)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= npk * LAT_WAVE) return;
+    const int l = (int)(t % LAT_WAVE);
+    const int64_t q = t / LAT_WAVE;
+    const int cell = perm[(int64_t)qgroup[q] * LAT_WAVE + l];
+    double al[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) al[k] = (cell >= 0 && k < n_r) ? alpha[(int64_t)cell * cap + k] : 0.0;
+    const double *kq = K + (int64_t)unode[q] * E * cap;
+    double *oq = ops + q * E * LAT_WAVE + l;
+    for (int e = 0; e < E; ++e) {
+        const double *kr = kq + (int64_t)e * cap;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            if (k < n_r) s = fma(al[k], kr[k], s);
+        oq[(int64_t)e * LAT_WAVE] = s;
+    }
+}
+
+lat_status combine_ops(const lat_plan *P, const double *K, int n_r, const double *alpha, double *ops, hipStream_t s)
+{
+    if (P->npacked == 0) return LAT_OK;
+    const int64_t nt = P->npacked * LAT_WAVE;
+    const dim3 grid((unsigned)lat_cdiv(nt, NB));
+    const int32_t *qgroup = P->goff + P->ngroups + 1;
+#define CO(NRV) hipLaunchKernelGGL((k_combine_ops<NRV>), grid, dim3(NB), 0, s, (int64_t)P->npacked, P->E, P->cap, n_r, \
+                                   qgroup, P->unode, P->perm, K, alpha, ops)
+    if (n_r <= 8) CO(8);
+    else if (n_r <= 16) CO(16);
+    else if (n_r <= 32) CO(32);
+    else CO(64);
+#undef CO
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
 }
 
 __global__ void __launch_bounds__(NB) k_fill(int64_t n, double v, double *__restrict__ y)
@@ -386,11 +486,12 @@ struct Arena {
 struct MrWork {
     double *v[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
     double *y = nullptr, *dinv = nullptr, *ppk = nullptr, *ypk = nullptr, *part = nullptr;
+    double *ops = nullptr;       // combined per-cell stencils (packed), when materialised
     MrCtl *ctl = nullptr;
     unsigned nbn = 1, nbv = 1;   // blocks over nodes, over components
 };
 
-lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w)
+lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize)
 {
     const int64_t n = P->nglobal * P->dim;
     const int64_t npk = std::max<int64_t>(P->npacked, 1) * P->dim * LAT_WAVE;
@@ -402,26 +503,36 @@ lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w)
     NCHK(ar.get(&w.y, n)); NCHK(ar.get(&w.dinv, n));
     NCHK(ar.get(&w.ppk, npk)); NCHK(ar.get(&w.ypk, npk));
     NCHK(ar.get(&w.part, (int64_t)std::max(w.nbn, w.nbv))); NCHK(ar.get(&w.ctl, 1));
+    if (materialize) NCHK(ar.get(&w.ops, std::max<int64_t>(P->npacked, 1) * P->E * LAT_WAVE));
     return LAT_OK;
 }
 
-// Preconditioned MINRES on K~ from x = 0.  Synchronises the stream.  *relres = ||r||_{D^-1} /
+// Preconditioned MINRES from x = 0 on the operator given by per-cell stencils `ops` (packed
+// layout of lat_apply_plain), or, when ops is null, by the principal stack K and coefficients
+// alpha (every product a ROM apply).  Synchronises the stream.  *relres = ||r||_{D^-1} /
 // ||b||_{D^-1} as tracked by the rotations.
-lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const double *alpha, const uint8_t *fixed,
-                  const double *b, double *x, double tol, int maxit, int check, int *iters, double *relres,
-                  hipStream_t s)
+lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const double *alpha, const double *ops,
+                  const uint8_t *fixed, const double *b, double *x, double tol, int maxit, int check, int *iters,
+                  double *relres, hipStream_t s)
 {
     const NGrid g = make_ngrid(P);
     const PackMap pm{P->lane, P->uidx, P->goff};
     const int64_t n = P->nglobal * P->dim;
     const int64_t npk = std::max<int64_t>(P->npacked, 1) * P->dim * LAT_WAVE;
     hipLaunchKernelGGL(k_fill, dim3(vec_blocks(npk)), dim3(NB), 0, s, npk, 0.0, w.ppk);
-    hipLaunchKernelGGL(k_jacobi, dim3(w.nbn), dim3(NB), 0, s, g, P->nglobal, P->g2bg, P->l2g, K, alpha, P->cap, n_r,
-                       P->E, fixed, w.dinv);
+    if (ops)
+        hipLaunchKernelGGL(k_jacobi_ops, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, ops, P->E,
+                           fixed, w.dinv);
+    else
+        hipLaunchKernelGGL(k_jacobi, dim3(w.nbn), dim3(NB), 0, s, g, P->nglobal, P->g2bg, P->l2g, K, alpha, P->cap,
+                           n_r, P->E, fixed, w.dinv);
     // v_0 = v[0], v_1 = v[1], z_1 = z[1], w_0 = w[0], w_1 = w[1]
     hipLaunchKernelGGL(k_mr_init, dim3(w.nbv), dim3(NB), 0, s, n, fixed, w.dinv, b, x, w.v[0], w.v[1], w.z[1], w.w[0],
                        w.w[1], w.part);
     hipLaunchKernelGGL(k_mr_init_fin, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, tol, w.ctl);
+    // z_1 / gamma_1 into the packed input of the first product
+    hipLaunchKernelGGL(k_mr_scale, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, w.z[1], w.ppk,
+                       w.ctl);
     LAT_LAUNCH_CHECK();
     MrCtl h{};
     int it = 0;
@@ -435,16 +546,15 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
             double *vj = w.v[j % 2], *vjm1 = w.v[(j + 1) % 2];   // v_{j+1} is written over v_{j-1}
             double *zj = w.z[j % 2], *zj1 = w.z[(j + 1) % 2];
             double *wj = w.w[j % 2], *wjm1 = w.w[(j + 1) % 2];   // w_{j+1} is written over w_{j-1}
-            hipLaunchKernelGGL(k_mr_scale, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, zj, w.ppk,
-                               w.ctl);
-            LAT_LAUNCH_CHECK();
-            NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, s));
+            if (ops) NCHK(lat_apply_plain(P, ops, w.ppk, w.ypk, 1, s));
+            else NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, s));
             hipLaunchKernelGGL(k_mr_ap, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, fixed, w.ypk,
                                zj, w.y, w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_delta, dim3(1), dim3(NB), 0, s, (int)w.nbn, w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_v, dim3(w.nbv), dim3(NB), 0, s, n, w.y, vj, vjm1, w.dinv, zj1, w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, it, w.ctl);
-            hipLaunchKernelGGL(k_mr_x, dim3(w.nbv), dim3(NB), 0, s, n, zj, wj, wjm1, x, w.ctl);
+            hipLaunchKernelGGL(k_mr_x, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, zj, wj, wjm1, x,
+                               zj1, w.ppk, w.ctl);
             LAT_LAUNCH_CHECK();
         }
     }
@@ -464,8 +574,8 @@ double ms_since(std::chrono::steady_clock::time_point t0)
 extern "C" {
 
 lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const double *alpha, const uint8_t *fixed,
-                         const double *b, double *x, double tol, int32_t maxit, int32_t check, int32_t *iters,
-                         double *relres, hipStream_t stream)
+                         const double *b, double *x, double tol, int32_t maxit, int32_t check, int32_t materialize,
+                         int32_t *iters, double *relres, hipStream_t stream)
 {
     if (!P || !K || !alpha || !fixed || !b || !x) return LAT_E_ARG;
     if (n_r < 0 || n_r > P->cap || !(tol > 0.0) || maxit < 0 || check < 1) return LAT_E_ARG;
@@ -476,10 +586,11 @@ lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const 
     }
     Arena ar;
     MrWork w;
-    NCHK(mr_alloc(P, ar, w));
+    NCHK(mr_alloc(P, ar, w, materialize != 0));
     int it = 0;
     double rr = 0.0;
-    const lat_status st = mr_run(P, w, K, n_r, alpha, fixed, b, x, tol, maxit, check, &it, &rr, stream);
+    if (w.ops) NCHK(combine_ops(P, K, n_r, alpha, w.ops, stream));
+    const lat_status st = mr_run(P, w, K, n_r, alpha, w.ops, fixed, b, x, tol, maxit, check, &it, &rr, stream);
     if (iters) *iters = it;
     if (relres) *relres = rr;
     LAT_HIP(hipStreamSynchronize(stream));
@@ -493,7 +604,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     if (n_records) *n_records = 0;
     if (!P || !mu || !lam || !fixed || !ubar || !o || !u) return LAT_E_ARG;
     if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
-        o->cg_maxit < 1 || o->cg_check < 1 || (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
+        o->cg_maxit < 1 || o->cg_check < 1 || (o->matvec != 0 && o->matvec != 1) ||
+        (o->tangent != 0 && o->tangent != 1) || (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
         !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
         !(o->armijo_c >= 0.0 && o->armijo_c < 1.0) || !(o->cg_tol > 0.0) || max_records < 0 ||
         (max_records > 0 && !records))
@@ -503,7 +615,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     const int64_t n = P->nglobal * d;
     Arena ar;
     MrWork w;
-    NCHK(mr_alloc(P, ar, w));
+    const bool full = o->tangent == 1;   // each cell's own tangent (the standard method)
+    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0));
     double *u_try, *du, *rhs, *r, *r_try, *fasm, *f_cil, *snap, *K, *alpha, *R, *scal;
     int32_t *S, *nr_d, *st_d, *gst_d;
     NCHK(ar.get(&u_try, n)); NCHK(ar.get(&du, n)); NCHK(ar.get(&rhs, n)); NCHK(ar.get(&r, n));
@@ -521,7 +634,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     // residual (and snapshots) at `at` into `res`; returns the HOST norm (inf if not admissible)
     auto evaluate = [&](const double *at, double lf, double *res, double *norm, int32_t *code) -> lat_status {
         NCHK(lat_status_reset(st_d, s));
-        NCHK(lat_residual_tangent(P, at, mu, lam, rule, f_cil, nullptr, snap, nullptr, st_d, s));
+        NCHK(lat_residual_tangent(P, at, mu, lam, rule, f_cil, nullptr, full ? nullptr : snap, full ? w.ops : nullptr,
+                                  st_d, s));
         NCHK(lat_assemble(P, f_cil, d, fasm, s));
         hipLaunchKernelGGL(k_residual, dim3(nbv), dim3(NB), 0, s, n, fasm, f_ext, lf, fixed, res, w.part);
         hipLaunchKernelGGL(k_sum_fin, dim3(1), dim3(NB), 0, s, (int)nbv, w.part, scal);
@@ -554,21 +668,27 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
         for (int it = 0; it < o->max_newton; ++it) {
             lat_newton_record rec{};
             rec.increment = t; rec.iteration = it; rec.res_before = rn; rec.res0 = r0;
-            // reduced basis at u and the principal tangents
+            // reduced basis at u and the principal tangents (the standard method uses the cells' own
+            // tangents, already formed with the residual)
             t0 = std::chrono::steady_clock::now();
-            NCHK(lat_status_reset(gst_d, s));
-            NCHK(lat_select_principal(P, snap, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R, nullptr, scal + 1,
-                                      gst_d, s));
-            int32_t hnr = 0, hg[2] = {0, 0};
-            double ach = 0.0;
-            LAT_HIP(hipMemcpyAsync(&hnr, nr_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            LAT_HIP(hipMemcpyAsync(hg, gst_d, sizeof(hg), hipMemcpyDeviceToHost, s));
-            LAT_HIP(hipMemcpyAsync(&ach, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-            LAT_HIP(hipStreamSynchronize(s));
-            NCHK(lat_status_reset(st_d, s));
-            NCHK(lat_principal_ops(P, u, mu, lam, S, hnr, K, nullptr, nullptr, st_d, s));
-            LAT_HIP(hipStreamSynchronize(s));
-            rec.n_r = hnr; rec.rb_achieved = ach; rec.greedy_status = hg[0];
+            int32_t hnr = 0;
+            if (!full) {
+                NCHK(lat_status_reset(gst_d, s));
+                NCHK(lat_select_principal(P, snap, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R, nullptr,
+                                          scal + 1, gst_d, s));
+                int32_t hg[2] = {0, 0};
+                double ach = 0.0;
+                LAT_HIP(hipMemcpyAsync(&hnr, nr_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                LAT_HIP(hipMemcpyAsync(hg, gst_d, sizeof(hg), hipMemcpyDeviceToHost, s));
+                LAT_HIP(hipMemcpyAsync(&ach, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+                LAT_HIP(hipStreamSynchronize(s));
+                NCHK(lat_status_reset(st_d, s));
+                NCHK(lat_principal_ops(P, u, mu, lam, S, hnr, K, nullptr, nullptr, st_d, s));
+                if (w.ops) NCHK(combine_ops(P, K, hnr, alpha, w.ops, s));
+                LAT_HIP(hipStreamSynchronize(s));
+                rec.rb_achieved = ach; rec.greedy_status = hg[0];
+            }
+            rec.n_r = hnr;
             rec.t_init_ms = ms_since(t0);
             // tangent solve K~ du = -r
             t0 = std::chrono::steady_clock::now();
@@ -576,8 +696,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             LAT_LAUNCH_CHECK();
             int cgit = 0;
             double cgrel = 0.0;
-            const lat_status cst = mr_run(P, w, K, hnr, alpha, fixed, rhs, du, o->cg_tol, o->cg_maxit, o->cg_check,
-                                          &cgit, &cgrel, s);
+            const lat_status cst = mr_run(P, w, K, hnr, alpha, w.ops, fixed, rhs, du, o->cg_tol, o->cg_maxit,
+                                          o->cg_check, &cgit, &cgrel, s);
             if (cst != LAT_OK && cst != LAT_E_NOCONV && cst != LAT_E_SINGULAR) return cst;
             rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst;
             rec.t_solve_ms = ms_since(t0);
@@ -597,6 +717,12 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             rec.backtracks = m; rec.step = ok ? step : 0.0; rec.res_after = ok ? rt : rn;
             if (records && nrec < max_records) records[nrec] = rec;
             ++nrec;
+            if (o->verbose) {
+                std::fprintf(stderr, "newton inc %d it %d: n_r %d, solve %d its (status %d), m %d, |r|/|r0| %.3e, "
+                             "ms init %.1f solve %.1f eval %.1f\n", t, it, rec.n_r, rec.cg_iters, rec.cg_status,
+                             rec.backtracks, (ok ? rt : rn) / r0, rec.t_init_ms, rec.t_solve_ms, rec.t_eval_ms);
+                std::fflush(stderr);
+            }
             if (!ok) { result = LAT_E_NOCONV; break; }
             LAT_HIP(hipMemcpyAsync(u, u_try, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             std::swap(r_try, r);   // the snapshots in `snap` belong to the accepted state already

@@ -100,6 +100,11 @@ def test_rom_solve_matches_direct_solve(graded):
     # the same solve again is bit-identical (fixed-order reductions)
     x2, _, its2, _ = nc.P.rom_solve(K, n_r, alpha, nc.fixed_t, b_t, tol=1e-12, maxit=50000, check=64)
     assert its2 == its and np.array_equal(x2.reshape(-1, cfg.dim).cpu().numpy(), x)
+    # products formed on the fly by the ROM apply instead of from the combined stencils
+    x3, st3, _, rr3 = nc.P.rom_solve(K, n_r, alpha, nc.fixed_t, b_t, tol=1e-12, maxit=50000, check=64,
+                                     materialize=False)
+    assert st3 == nc.B.LAT_OK and rr3 <= 1e-12
+    assert rel(x3.reshape(-1, cfg.dim).cpu().numpy().ravel(), xo) <= 1e-6
 
 
 def test_rom_solve_edge_cases(graded):
@@ -153,13 +158,16 @@ def test_rom_solve_indefinite_matches_direct_solve(graded):
     assert rel(x, xo) <= 1e-5
 
 
-def test_newton_matches_oracle(graded):
+@pytest.mark.parametrize("rule", [O.RULE_FULL, O.RULE_REDUCED])
+def test_newton_matches_oracle(graded, rule):
     nc = graded
     u = nc.zeros_u()
     st, recs = nc.P.newton_solve(nc.mu_t, nc.lam_t, nc.fixed_t, nc.ubar_t, u, n_inc=4, rb_tol=1e-4, cap=16,
-                                 cg_tol=1e-12, cg_maxit=50000)
+                                 cg_tol=1e-12, cg_maxit=50000, snap_rule=rule)
     assert st == nc.B.LAT_OK
-    out = ON.newton_solve(nc.orc, n_inc=4, rb_tol=1e-4, cap=16)
+    orc = nc.orc if rule == O.RULE_FULL else ON.Problem(
+        nc.cfg.dim, nc.cfg.ncell_eff, nc.cfg.nel, nc.keep, nc.mu, nc.lam, nc.bvp["fixed"], nc.bvp["ubar"], rule=rule)
+    out = ON.newton_solve(orc, n_inc=4, rb_tol=1e-4, cap=16)
     assert out["status"] == O.OK
     ro = out["records"]
     assert len(recs) == len(ro)
@@ -183,6 +191,7 @@ def test_newton_matches_oracle(graded):
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_newton_uniaxial_closed_form(dim):
+    # 2D: products from the combined stencils; 3D: ROM applies forming them on the fly
     if dim == 2:
         cfg = L.config(0).with_(ncell=(3, 2), nel=8, radius=(0.0, 0.0))
         lam = 10.0
@@ -194,7 +203,7 @@ def test_newton_uniaxial_closed_form(dim):
     assert nc.keep.all()
     u = nc.zeros_u()
     st, recs = nc.P.newton_solve(nc.mu_t, nc.lam_t, nc.fixed_t, nc.ubar_t, u, n_inc=4, rb_tol=1e-8, cap=8,
-                                 newton_tol=1e-11, cg_tol=1e-13, cg_maxit=50000)
+                                 newton_tol=1e-11, cg_tol=1e-13, cg_maxit=50000, matvec=dim - 2)
     summary = [(r["increment"], r["iteration"], r["n_r"], r["rb_achieved"], r["backtracks"], r["cg_iters"],
                 r["cg_status"], r["res_after"] / r["res0"]) for r in recs]
     assert st == nc.B.LAT_OK, summary
@@ -232,3 +241,51 @@ def test_newton_degenerate_loads(graded):
         nc.P.newton_solve(nc.mu_t, nc.lam_t, nc.fixed_t, nc.ubar_t, u, armijo_beta=1.0)
     with pytest.raises(B.LatError):
         nc.P.newton_solve(nc.mu_t, nc.lam_t, nc.fixed_t, nc.ubar_t, u, cap=nc.P.cap + 1)
+
+
+@pytest.fixture(scope="module")
+def two_groups():
+    # 12 x 8 = 96 cells: two 64-lane groups, so the packed layout spans group offsets
+    cfg = L.config(0).with_(ncell=(12, 8), radius=(0.25, 0.35))
+    return NCase(cfg, L.LoadCase("compress_shear", 0.02, 0.005, 2), cap=64)
+
+
+def test_rom_solve_two_groups(two_groups):
+    nc = two_groups
+    cfg = nc.cfg
+    assert nc.P.ngroups == 2
+    u = L.make_displacement(cfg.with_(strain=0.005, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, alpha, Ko = _rom_at(nc, u, 1e-4, 64)
+    rng = np.random.default_rng(24)
+    xs = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    xs[nc.orc.fixed] = 0.0
+    b = (Ko @ xs.ravel()).reshape(-1, cfg.dim)
+    b[nc.orc.fixed] = 0.0
+    for mat in (True, False):
+        x, st, its, rr = nc.P.rom_solve(K, n_r, alpha, nc.fixed_t, torch.from_numpy(b).to(nc.dev), tol=1e-12,
+                                        maxit=100000, check=128, materialize=mat)
+        assert st == nc.B.LAT_OK and rr <= 1e-12
+        f = nc.orc.free
+        xg = x.reshape(-1, cfg.dim).cpu().numpy().ravel()
+        assert np.linalg.norm(Ko[f][:, f] @ xg[f] - b.ravel()[f]) <= 1e-10 * np.linalg.norm(b)
+        assert rel(xg, xs.ravel()) <= 1e-5
+
+
+def test_newton_two_groups_matches_oracle(two_groups):
+    nc = two_groups
+    # ROM at a tolerance where it keeps the exact Newton's iteration count on this lattice (N_r 47-58
+    # of 96), then the standard method (every cell's own tangent: the ROM with all cells principal)
+    for tangent, tol in ((0, 3e-5), (1, None)):
+        u = nc.zeros_u()
+        st, recs = nc.P.newton_solve(nc.mu_t, nc.lam_t, nc.fixed_t, nc.ubar_t, u, n_inc=2, rb_tol=tol or 1e-4, cap=64,
+                                     cg_tol=1e-12, cg_maxit=100000, tangent=tangent)
+        assert st == nc.B.LAT_OK
+        out = ON.newton_solve(nc.orc, n_inc=2, rb_tol=tol if tol else 1e-14, cap=64 if tol else 96)
+        assert out["status"] == O.OK
+        ro = out["records"]
+        assert len(recs) == len(ro)
+        for g, o in zip(recs, ro):
+            assert (g["increment"], g["iteration"], g["backtracks"]) == (o["increment"], o["iteration"], o["backtracks"])
+            assert g["n_r"] == (o["n_r"] if tangent == 0 else 0)
+            assert abs(g["res_after"] - o["res_after"]) <= 1e-6 * o["res_before"]
+        assert np.abs(u.cpu().numpy() - out["u"]).max() <= 1e-7 * np.abs(out["u"]).max()
