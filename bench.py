@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--cap", type=int, default=64, help="--newton: principal-cell cap")
     ap.add_argument("--max-newton", type=int, default=30, help="--newton: iterations per increment")
     ap.add_argument("--solve-tol", type=float, default=1e-8, help="--newton: tangent-solve tolerance")
+    ap.add_argument("--solve-maxit", type=int, default=200000, help="--newton: tangent-solve iteration limit")
     ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
                     help="--newton: ROM tangent, or every cell's own tangent (the standard method)")
     args = ap.parse_args()
@@ -352,7 +353,7 @@ def newton_main(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, recs = P.newton_solve(mu_t, lam_t, fixed, ubar, u, n_inc=args.n_inc, max_newton=args.max_newton,
-                              cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=200000,
+                              cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=args.solve_maxit,
                               cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
