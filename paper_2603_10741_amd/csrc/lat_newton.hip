@@ -99,6 +99,26 @@ __device__ __forceinline__ bool packed_ql(const PackMap &pm, int nloc, int64_t c
     return qi >= 0;
 }
 
+constexpr int MAXOWN = 8;   // cells owning a node: at most 2^d
+
+// Packed slots (component 0) of the owners of every global node in ascending cell id, -1 padded:
+// own[G * 2^d + k].  Built once per solve so that the per-iteration assembly and scatter read
+// 4 or 8 indices instead of re-deriving the owners from the node's background coordinates.
+__global__ void __launch_bounds__(NB) k_owner_table(NGrid g, PackMap pm, int64_t nglobal,
+                                                    const int64_t *__restrict__ g2bg, const int32_t *__restrict__ l2g,
+                                                    int32_t *__restrict__ own)
+{
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (G >= nglobal) return;
+    const int no = 1 << g.dim;
+    int k = 0;
+    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
+        const int64_t s0 = packed_slot(pm, g.nloc, g.dim, cell, a);
+        if (s0 >= 0 && k < no) own[G * no + k++] = (int32_t)s0;
+    });
+    for (; k < no; ++k) own[G * no + k] = -1;
+}
+
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
     const int t = threadIdx.x;
@@ -216,48 +236,56 @@ __global__ void __launch_bounds__(NB) k_mr_init_fin(int nb, const double *__rest
 }
 
 // z <- z / gamma (the first normalised Lanczos vector), scattered into the packed apply input
-__global__ void __launch_bounds__(NB) k_mr_scale(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
-                                                 const int32_t *__restrict__ l2g, double *__restrict__ z,
-                                                 double *__restrict__ ppk, const MrCtl *__restrict__ ctl)
+template <int D>
+__global__ void __launch_bounds__(NB) k_mr_scale(int64_t nglobal, const int32_t *__restrict__ own,
+                                                 double *__restrict__ z, double *__restrict__ ppk,
+                                                 const MrCtl *__restrict__ ctl)
 {
     if (ctl->done) return;
     const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
     if (G >= nglobal) return;
-    const int d = g.dim;
     const double ig = ctl->inv_gam;
-    double zv[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < d; ++i) {
-        zv[i] = z[G * d + i] * ig;
-        z[G * d + i] = zv[i];
+    double zv[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        zv[i] = z[G * D + i] * ig;
+        z[G * D + i] = zv[i];
     }
-    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
-        const int64_t s0 = packed_slot(pm, g.nloc, d, cell, a);
+#pragma unroll
+    for (int k = 0; k < (1 << D); ++k) {
+        const int32_t s0 = own[G * (1 << D) + k];
         if (s0 >= 0)
-            for (int i = 0; i < d; ++i) ppk[s0 + (int64_t)i * LAT_WAVE] = zv[i];
-    });
+#pragma unroll
+            for (int i = 0; i < D; ++i) ppk[s0 + i * LAT_WAVE] = zv[i];
+    }
 }
 
-// y = assembled, masked K~ z from the packed apply output; partial <y, z>
-__global__ void __launch_bounds__(NB) k_mr_ap(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
-                                              const int32_t *__restrict__ l2g, const uint8_t *__restrict__ fixed,
-                                              const double *__restrict__ ypk, const double *__restrict__ z,
-                                              double *__restrict__ y, double *__restrict__ part,
-                                              const MrCtl *__restrict__ ctl)
+// y = assembled, masked K~ z from the packed apply output (owners summed in ascending cell id);
+// partial <y, z>
+template <int D>
+__global__ void __launch_bounds__(NB) k_mr_ap(int64_t nglobal, const int32_t *__restrict__ own,
+                                              const uint8_t *__restrict__ fixed, const double *__restrict__ ypk,
+                                              const double *__restrict__ z, double *__restrict__ y,
+                                              double *__restrict__ part, const MrCtl *__restrict__ ctl)
 {
     __shared__ double sh[NB];
     if (ctl->done) return;
     const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
-    const int d = g.dim;
     double dot = 0.0;
     if (G < nglobal) {
-        double acc[3] = {0.0, 0.0, 0.0};
-        for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
-            const int64_t s0 = packed_slot(pm, g.nloc, d, cell, a);
+        double acc[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < (1 << D); ++k) {
+            const int32_t s0 = own[G * (1 << D) + k];
             if (s0 >= 0)
-                for (int i = 0; i < d; ++i) acc[i] += ypk[s0 + (int64_t)i * LAT_WAVE];
-        });
-        for (int i = 0; i < d; ++i) {
-            const int64_t j = G * d + i;
+#pragma unroll
+                for (int i = 0; i < D; ++i) acc[i] += ypk[s0 + i * LAT_WAVE];
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int64_t j = G * D + i;
             const double v = fixed[j] ? 0.0 : acc[i];
             y[j] = v;
             dot = fma(z[j], v, dot);
@@ -342,31 +370,34 @@ __global__ void __launch_bounds__(NB) k_mr_rot(int nb, const double *__restrict_
 // End of step j, per node: w_{j+1} = (z_j - a3 w_{j-1} - a2 w_j) / a1 (written over w_{j-1}),
 // x += cx w_{j+1}; then the next Lanczos vector z_{j+1} <- z_{j+1} / gamma_{j+1}, scattered into
 // the packed input of the next product.
-__global__ void __launch_bounds__(NB) k_mr_x(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
-                                             const int32_t *__restrict__ l2g, const double *__restrict__ zj,
-                                             const double *__restrict__ wj, double *__restrict__ wprev_next,
-                                             double *__restrict__ x, double *__restrict__ znext,
-                                             double *__restrict__ ppk, const MrCtl *__restrict__ ctl)
+template <int D>
+__global__ void __launch_bounds__(NB) k_mr_x(int64_t nglobal, const int32_t *__restrict__ own,
+                                             const double *__restrict__ zj, const double *__restrict__ wj,
+                                             double *__restrict__ wprev_next, double *__restrict__ x,
+                                             double *__restrict__ znext, double *__restrict__ ppk,
+                                             const MrCtl *__restrict__ ctl)
 {
     if (ctl->done) return;
     const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
     if (G >= nglobal) return;
-    const int d = g.dim;
     const double ia1 = 1.0 / ctl->a1, a2 = ctl->a2, a3 = ctl->a3, cx = ctl->cx, ig = ctl->inv_gam;
-    double zv[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < d; ++i) {
-        const int64_t j = G * d + i;
+    double zv[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const int64_t j = G * D + i;
         const double w = (zj[j] - a3 * wprev_next[j] - a2 * wj[j]) * ia1;
         wprev_next[j] = w;
         x[j] = fma(cx, w, x[j]);
         zv[i] = znext[j] * ig;
         znext[j] = zv[i];
     }
-    for_owners(g, g2bg[G], l2g, [&](int64_t cell, int a) {
-        const int64_t s0 = packed_slot(pm, g.nloc, d, cell, a);
+#pragma unroll
+    for (int k = 0; k < (1 << D); ++k) {
+        const int32_t s0 = own[G * (1 << D) + k];
         if (s0 >= 0)
-            for (int i = 0; i < d; ++i) ppk[s0 + (int64_t)i * LAT_WAVE] = zv[i];
-    });
+#pragma unroll
+            for (int i = 0; i < D; ++i) ppk[s0 + i * LAT_WAVE] = zv[i];
+    }
 }
 
 // Combined stencil of every cell, K~_s = sum_k alpha_sk K_k (eq. romstiffnessmatrix), in the
@@ -487,11 +518,12 @@ struct MrWork {
     double *v[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
     double *y = nullptr, *dinv = nullptr, *ppk = nullptr, *ypk = nullptr, *part = nullptr;
     double *ops = nullptr;       // combined per-cell stencils (packed), when materialised
+    int32_t *own = nullptr;      // [n_global][2^d] packed slots of each node's owners
     MrCtl *ctl = nullptr;
     unsigned nbn = 1, nbv = 1;   // blocks over nodes, over components
 };
 
-lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize)
+lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize, hipStream_t s)
 {
     const int64_t n = P->nglobal * P->dim;
     const int64_t npk = std::max<int64_t>(P->npacked, 1) * P->dim * LAT_WAVE;
@@ -503,6 +535,11 @@ lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize)
     NCHK(ar.get(&w.y, n)); NCHK(ar.get(&w.dinv, n));
     NCHK(ar.get(&w.ppk, npk)); NCHK(ar.get(&w.ypk, npk));
     NCHK(ar.get(&w.part, (int64_t)std::max(w.nbn, w.nbv))); NCHK(ar.get(&w.ctl, 1));
+    if (npk >= INT32_MAX) return LAT_E_SHAPE;   // packed slots are held as int32
+    NCHK(ar.get(&w.own, P->nglobal << P->dim));
+    hipLaunchKernelGGL(k_owner_table, dim3(w.nbn), dim3(NB), 0, s, make_ngrid(P), PackMap{P->lane, P->uidx, P->goff},
+                       P->nglobal, P->g2bg, P->l2g, w.own);
+    LAT_LAUNCH_CHECK();
     if (materialize) NCHK(ar.get(&w.ops, std::max<int64_t>(P->npacked, 1) * P->E * LAT_WAVE));
     return LAT_OK;
 }
@@ -531,8 +568,10 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
                        w.w[1], w.part);
     hipLaunchKernelGGL(k_mr_init_fin, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, tol, w.ctl);
     // z_1 / gamma_1 into the packed input of the first product
-    hipLaunchKernelGGL(k_mr_scale, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, w.z[1], w.ppk,
-                       w.ctl);
+    if (P->dim == 2)
+        hipLaunchKernelGGL(k_mr_scale<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, w.z[1], w.ppk, w.ctl);
+    else
+        hipLaunchKernelGGL(k_mr_scale<3>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, w.z[1], w.ppk, w.ctl);
     LAT_LAUNCH_CHECK();
     MrCtl h{};
     int it = 0;
@@ -548,13 +587,21 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
             double *wj = w.w[j % 2], *wjm1 = w.w[(j + 1) % 2];   // w_{j+1} is written over w_{j-1}
             if (ops) NCHK(lat_apply_plain(P, ops, w.ppk, w.ypk, 1, s));
             else NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, s));
-            hipLaunchKernelGGL(k_mr_ap, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, fixed, w.ypk,
-                               zj, w.y, w.part, w.ctl);
+            if (P->dim == 2)
+                hipLaunchKernelGGL(k_mr_ap<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, fixed, w.ypk, zj, w.y,
+                                   w.part, w.ctl);
+            else
+                hipLaunchKernelGGL(k_mr_ap<3>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, fixed, w.ypk, zj, w.y,
+                                   w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_delta, dim3(1), dim3(NB), 0, s, (int)w.nbn, w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_v, dim3(w.nbv), dim3(NB), 0, s, n, w.y, vj, vjm1, w.dinv, zj1, w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, it, w.ctl);
-            hipLaunchKernelGGL(k_mr_x, dim3(w.nbn), dim3(NB), 0, s, g, pm, P->nglobal, P->g2bg, P->l2g, zj, wj, wjm1, x,
-                               zj1, w.ppk, w.ctl);
+            if (P->dim == 2)
+                hipLaunchKernelGGL(k_mr_x<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, zj, wj, wjm1, x, zj1,
+                                   w.ppk, w.ctl);
+            else
+                hipLaunchKernelGGL(k_mr_x<3>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, zj, wj, wjm1, x, zj1,
+                                   w.ppk, w.ctl);
             LAT_LAUNCH_CHECK();
         }
     }
@@ -586,7 +633,7 @@ lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const 
     }
     Arena ar;
     MrWork w;
-    NCHK(mr_alloc(P, ar, w, materialize != 0));
+    NCHK(mr_alloc(P, ar, w, materialize != 0, stream));
     int it = 0;
     double rr = 0.0;
     if (w.ops) NCHK(combine_ops(P, K, n_r, alpha, w.ops, stream));
@@ -616,7 +663,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     Arena ar;
     MrWork w;
     const bool full = o->tangent == 1;   // each cell's own tangent (the standard method)
-    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0));
+    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0, s));
     double *u_try, *du, *rhs, *r, *r_try, *fasm, *f_cil, *snap, *K, *alpha, *R, *scal;
     int32_t *S, *nr_d, *st_d, *gst_d;
     NCHK(ar.get(&u_try, n)); NCHK(ar.get(&du, n)); NCHK(ar.get(&rhs, n)); NCHK(ar.get(&r, n));
