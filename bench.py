@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--max-newton", type=int, default=30, help="--newton: iterations per increment")
     ap.add_argument("--solve-tol", type=float, default=1e-8, help="--newton: tangent-solve tolerance")
     ap.add_argument("--solve-maxit", type=int, default=200000, help="--newton: tangent-solve iteration limit")
+    ap.add_argument("--snap-rule", choices=["full", "reduced"], default="full", help="--newton: snapshot quadrature")
     ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
                     help="--newton: ROM tangent, or every cell's own tangent (the standard method)")
     args = ap.parse_args()
@@ -250,6 +251,31 @@ def main():
     t_lp = ms_stage["rom_apply_bf16"] * 1e-3
     rom_vs_plain = float(np.linalg.norm(Y - Yp) / np.linalg.norm(Yp))
 
+    def snapshot_variant(rule, tol):
+        """Snapshots with one quadrature rule, the greedy on them, then the ROM apply with the
+        full-rule principal tangents: time of the snapshot pass and of the greedy, N_r, and the
+        ROM operator's distance to every cell's own tangent (outside the timed steps)."""
+        buf = {"snap": P._f64(P.nsnap * P.ld)}
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        cs = torch.cuda.current_stream()
+        e[0].record(cs)
+        P.residual_tangent(ug, mu_t, lam_t, snap_rule=rule, f=False, energy=False, snap=True, out=buf)
+        e[1].record(cs)
+        g = P.select_principal(buf["snap"], tol, keep_Z=False)
+        e[2].record(cs)
+        torch.cuda.synchronize()
+        nr = int(g["n_r"].item())
+        K = P.principal_ops(ug, mu_t, lam_t, g["S"], nr)["K"]
+        Yv = P.unpack(P.apply_combo(K, nr, g["alpha"], Xp, m), m).cpu().numpy()
+        ach = float(g["achieved"].item())
+        return {"snap_ms": round(e[0].elapsed_time(e[1]), 4), "greedy_ms": round(e[1].elapsed_time(e[2]), 4),
+                "n_r": nr, "capped": bool(ach > tol), "rom_vs_plain_rel": float(np.linalg.norm(Yv - Yp) /
+                                                                                np.linalg.norm(Yp))}
+
+    snap_variants = {f"{name}_tol_{tol:g}": snapshot_variant(rule, tol)
+                     for tol in (1e-3, 1e-4) for name, rule in (("full", B.RULE_FULL), ("reduced", B.RULE_REDUCED))}
+    P.reset_status()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -287,6 +313,7 @@ def main():
         "rel_err_plain_apply_vs_fp64_oracle": err_plain,
         "rom_vs_plain_operator_rel_diff": rom_vs_plain,
         "stage_ms": {k: round(v, 4) for k, v in ms_stage.items()},
+        "snapshot_variants": snap_variants,
         "device_status": {"code": code, "first_cell": cell},
     }
     print(json.dumps(out))
@@ -354,11 +381,37 @@ def newton_main(args):
     t0 = time.perf_counter()
     st, recs = P.newton_solve(mu_t, lam_t, fixed, ubar, u, n_inc=args.n_inc, max_newton=args.max_newton,
                               cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=args.solve_maxit,
-                              cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0)
+                              cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0,
+                              snap_rule=B.RULE_REDUCED if args.snap_rule == "reduced" else B.RULE_FULL)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tot = {k: float(sum(r[k] for r in recs)) for k in ("t_init_ms", "t_solve_ms", "t_eval_ms")}
     its = int(sum(r["cg_iters"] for r in recs))
+    # the tangent solve's dominant kernel: the per-cell stencil apply with one right-hand side,
+    # timed on the cells' own stencils at the final state (HIP events, current stream)
+    ops = P.residual_tangent(u, mu_t, lam_t, f=False, energy=False, snap=False, plain=True)["plain"]
+    x1 = torch.randn(P.ncells, P.nloc, cfg.dim, 1, dtype=torch.float64, device=dev,
+                     generator=torch.Generator(dev).manual_seed(7))
+    xp = P.pack(x1, 1)
+    yp = P._f64(P.packed_size(1))
+    for _ in range(3):
+        P.apply_plain(ops, xp, 1, out=yp)
+    # each timed launch starts with cold caches, as inside the solve (a 1 GiB fill between launches
+    # evicts the 256 MB last-level cache, which would otherwise hold most of the stencils)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    reps = 20
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        flush.fill_(0.0)
+        a.record()
+        P.apply_plain(ops, xp, 1, out=yp)
+        b.record()
+    torch.cuda.synchronize()
+    t_mv = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+    del flush
+    lane_nodes = int(nact.sum().item())
+    mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
+    del ops
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle Newton iterations on an 8 x 8-cell sample) ...")
@@ -374,9 +427,14 @@ def newton_main(args):
         "status": int(st),
         "config": {"workload": cfg.name, "cells": P.ncells, "global_dofs": P.nglobal * cfg.dim,
                    "load": {"kind": case.kind, "strain": case.strain, "shear": case.shear, "increments": case.n_inc},
-                   "tangent": args.tangent, "rb_tol": args.rb_tol, "cap": args.cap, "newton_tol": 1e-6,
+                   "tangent": args.tangent, "snap_rule": args.snap_rule, "rb_tol": args.rb_tol, "cap": args.cap,
+                   "newton_tol": 1e-6,
                    "armijo": [0.5, 1e-4],
                    "tangent_solve": {"method": "MINRES, |diag| preconditioner", "tol": args.solve_tol}},
+        "roofline": {"bound": "hbm", "achieved": round(mv_bytes / t_mv / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(mv_bytes / t_mv / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_apply (per-cell stencil apply, one right-hand side) in every MINRES iteration",
+                     "algorithmic_bytes_per_launch": int(mv_bytes), "us_per_launch": round(t_mv * 1e6, 2)},
         "cpu_baseline": cpu,
         "newton_iterations": len(recs),
         "tangent_solve_iterations": its,
