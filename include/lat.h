@@ -297,6 +297,9 @@ typedef struct {
     double t_init_ms;       /* greedy + principal tangents + preconditioner */
     double t_solve_ms;      /* tangent solve */
     double t_eval_ms;       /* residual + snapshot evaluations (predictor and line-search trials) */
+    double t_product_us;    /* mean duration of one tangent product (the per-cell or ROM apply),
+                               HIP events around up to 64 products of the solve, taken from the
+                               9th product of each host batch on (0 when none was timed) */
 } lat_newton_record;
 
 /* Load-stepped Newton-Raphson with Armijo backtracking (Sec. 2.2.5) on the ROM tangent.

@@ -40,7 +40,7 @@ class NewtonRecord(ctypes.Structure):
                 ("cg_status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("step", ctypes.c_double),
                 ("res_before", ctypes.c_double), ("res_after", ctypes.c_double), ("res0", ctypes.c_double),
                 ("rb_achieved", ctypes.c_double), ("cg_relres", ctypes.c_double), ("t_init_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double), ("t_eval_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("t_eval_ms", ctypes.c_double), ("t_product_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

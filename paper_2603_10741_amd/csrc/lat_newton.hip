@@ -499,7 +499,18 @@ unsigned vec_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<
 // Device buffers of one call, released on every return path.
 struct Arena {
     std::vector<void *> ptrs;
-    ~Arena() { for (void *p : ptrs) (void)hipFree(p); }
+    std::vector<hipEvent_t> evs;
+    ~Arena()
+    {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    lat_status event(hipEvent_t *e)
+    {
+        if (hipEventCreate(e) != hipSuccess) return LAT_E_DEVICE;
+        evs.push_back(*e);
+        return LAT_OK;
+    }
     template <class T>
     lat_status get(T **p, int64_t n)
     {
@@ -520,6 +531,8 @@ struct MrWork {
     double *ops = nullptr;       // combined per-cell stencils (packed), when materialised
     int32_t *own = nullptr;      // [n_global][2^d] packed slots of each node's owners
     MrCtl *ctl = nullptr;
+    static constexpr int NT = 64;            // products timed per solve (the first NT)
+    hipEvent_t tev[2 * NT] = {};
     unsigned nbn = 1, nbv = 1;   // blocks over nodes, over components
 };
 
@@ -535,6 +548,7 @@ lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize, h
     NCHK(ar.get(&w.y, n)); NCHK(ar.get(&w.dinv, n));
     NCHK(ar.get(&w.ppk, npk)); NCHK(ar.get(&w.ypk, npk));
     NCHK(ar.get(&w.part, (int64_t)std::max(w.nbn, w.nbv))); NCHK(ar.get(&w.ctl, 1));
+    for (auto &e : w.tev) NCHK(ar.event(&e));
     if (npk >= INT32_MAX) return LAT_E_SHAPE;   // packed slots are held as int32
     NCHK(ar.get(&w.own, P->nglobal << P->dim));
     hipLaunchKernelGGL(k_owner_table, dim3(w.nbn), dim3(NB), 0, s, make_ngrid(P), PackMap{P->lane, P->uidx, P->goff},
@@ -550,7 +564,7 @@ lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize, h
 // ||b||_{D^-1} as tracked by the rotations.
 lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const double *alpha, const double *ops,
                   const uint8_t *fixed, const double *b, double *x, double tol, int maxit, int check, int *iters,
-                  double *relres, hipStream_t s)
+                  double *relres, hipStream_t s, double *t_product_us = nullptr)
 {
     const NGrid g = make_ngrid(P);
     const PackMap pm{P->lane, P->uidx, P->goff};
@@ -574,7 +588,10 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
         hipLaunchKernelGGL(k_mr_scale<3>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, w.z[1], w.ppk, w.ctl);
     LAT_LAUNCH_CHECK();
     MrCtl h{};
-    int it = 0;
+    int it = 0, ntimed = 0;
+    // products timed: from the 9th of a batch on (the host has run ahead by then, so the events
+    // bracket the kernel and not a launch gap), at most NT per solve
+    const int tskip = std::min(8, check - 1);
     for (;;) {
         LAT_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(MrCtl), hipMemcpyDeviceToHost, s));
         LAT_HIP(hipStreamSynchronize(s));
@@ -585,8 +602,11 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
             double *vj = w.v[j % 2], *vjm1 = w.v[(j + 1) % 2];   // v_{j+1} is written over v_{j-1}
             double *zj = w.z[j % 2], *zj1 = w.z[(j + 1) % 2];
             double *wj = w.w[j % 2], *wjm1 = w.w[(j + 1) % 2];   // w_{j+1} is written over w_{j-1}
+            const bool timed = t_product_us && k >= tskip && ntimed < MrWork::NT;
+            if (timed) LAT_HIP(hipEventRecord(w.tev[2 * ntimed], s));
             if (ops) NCHK(lat_apply_plain(P, ops, w.ppk, w.ypk, 1, s));
             else NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, s));
+            if (timed) LAT_HIP(hipEventRecord(w.tev[2 * ntimed++ + 1], s));
             if (P->dim == 2)
                 hipLaunchKernelGGL(k_mr_ap<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, fixed, w.ypk, zj, w.y,
                                    w.part, w.ctl);
@@ -604,6 +624,16 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
                                    w.ppk, w.ctl);
             LAT_LAUNCH_CHECK();
         }
+    }
+    if (t_product_us) {   // mean duration of the timed products (events on the launch stream)
+        const int nt = ntimed;
+        double tot = 0.0;
+        for (int k = 0; k < nt; ++k) {
+            float ms = 0.0f;
+            LAT_HIP(hipEventElapsedTime(&ms, w.tev[2 * k], w.tev[2 * k + 1]));
+            tot += ms;
+        }
+        *t_product_us = nt > 0 ? 1e3 * tot / nt : 0.0;
     }
     if (iters) *iters = h.iters;
     if (relres) *relres = h.eta0 > 0.0 ? std::fabs(h.eta) / h.eta0 : 0.0;
@@ -744,7 +774,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             int cgit = 0;
             double cgrel = 0.0;
             const lat_status cst = mr_run(P, w, K, hnr, alpha, w.ops, fixed, rhs, du, o->cg_tol, o->cg_maxit,
-                                          o->cg_check, &cgit, &cgrel, s);
+                                          o->cg_check, &cgit, &cgrel, s, &rec.t_product_us);
             if (cst != LAT_OK && cst != LAT_E_NOCONV && cst != LAT_E_SINGULAR) return cst;
             rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst;
             rec.t_solve_ms = ms_since(t0);
