@@ -246,7 +246,11 @@ lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, doubl
  * owner-ordered assembly.  materialize != 0: the combined stencils sum_k alpha_sk K_k of all cells
  * are formed once (device memory n_packed E 64 doubles, the lat_apply_plain layout) and every
  * product reads them; materialize == 0: every product is a ROM apply that forms them on the fly
- * (no per-cell storage).  K, n_r (HOST), alpha as for lat_apply_combo.
+ * (no per-cell storage).  precond = 0: D = |diag K~|; precond = 1: two levels,
+ * M^-1 = D^-1 + P K0^-1 P^T with the coarse operator of lat_coarse_operator, factorised per call
+ * (rocSOLVER Cholesky and inverse, FP64); a K0 that is not positive definite or larger than the
+ * limit leaves D alone, and *coarse_used (HOST, may be NULL) says which ran.  The stop test then
+ * uses ||.||_{M^-1} in place of ||.||_{D^-1}.  K, n_r (HOST), alpha as for lat_apply_combo.
  * b [n_global][d] (prescribed components ignored), x [n_global][d] out (prescribed components 0;
  * x starts from 0).  Stops when the residual estimate of the rotations satisfies
  * ||r||_{D^-1} <= tol ||b||_{D^-1} (tol > 0), after at most maxit iterations, checking on the host
@@ -255,7 +259,18 @@ lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, doubl
  * iterate), LAT_E_SINGULAR when K~ is singular on the Krylov space (x holds the last iterate). */
 lat_status lat_rom_solve(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
                          const uint8_t *fixed, const double *b, double *x, double tol, int32_t maxit,
-                         int32_t check, int32_t materialize, int32_t *iters, double *relres, hipStream_t stream);
+                         int32_t check, int32_t materialize, int32_t precond, int32_t *iters, double *relres,
+                         int32_t *coarse_used, hipStream_t stream);
+
+/* The coarse operator of the two-level preconditioner: K0 = P^T K~ P, P the Q1 interpolation from
+ * the cell-corner nodes (coarse node C = cx + (C_x+1)(cy + (C_y+1) cz), coarse DOF C d + i, the
+ * corners being the primal nodes of the coarse problem of Sec. 3.3) to the global nodes with
+ * the prescribed components' rows removed.  Formed with one ROM apply of the cells' 2^d d corner
+ * functions (materialize as in lat_rom_solve), per-cell products and an owner-ordered assembly;
+ * a coarse DOF with no free fine support gets a unit diagonal.  K0: device [n_c d][n_c d],
+ * row-major, n_c = prod (C_x+1).  LAT_E_SHAPE when n_c d > 16384 (the dense factor's limit). */
+lat_status lat_coarse_operator(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
+                               const uint8_t *fixed, int32_t materialize, double *K0, hipStream_t stream);
 
 /* Options of lat_newton_solve (HOST struct). */
 typedef struct {
@@ -271,6 +286,8 @@ typedef struct {
                                1 = ROM apply forming them on the fly (see lat_rom_solve) */
     int32_t tangent;        /* 0 = ROM tangent (the method), 1 = every cell's own full-rule tangent
                                (the standard method, for comparison; no greedy) */
+    int32_t precond;        /* tangent-solve preconditioner, as lat_rom_solve's precond */
+    int32_t reserved;       /* 0 */
     double rb_tol;          /* greedy tolerance (Algorithm 1), > 0 */
     double newton_tol;      /* stop an increment at ||r|| / ||r(u_0)|| <= newton_tol, > 0 */
     double armijo_beta;     /* step reduction factor, in (0, 1) */
@@ -287,7 +304,7 @@ typedef struct {
     int32_t cg_iters;       /* MINRES iterations of the tangent solve */
     int32_t greedy_status;  /* LAT_OK or LAT_W_CAP */
     int32_t cg_status;      /* LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR */
-    int32_t reserved;
+    int32_t coarse;         /* 1 if the two-level preconditioner's coarse correction ran */
     double step;            /* beta^m */
     double res_before;      /* ||r(u_k)||_2 */
     double res_after;       /* ||r(u_k + beta^m du)||_2 */

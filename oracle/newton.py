@@ -197,3 +197,52 @@ def newton_solve(prob: Problem, n_inc=4, rb_tol=3e-4, cap=64, newton_tol=1e-6, m
         if not done:
             return {"u": u, "records": recs, "status": NOCONV}
     return {"u": u, "records": recs, "status": status}
+
+
+# ----------------------------------------------------------------------------- coarse space (cell corners)
+def coarse_prolongation(dim, ncell, nel, g2bg, fixed=None):
+    """Prolongation P [n_global d][n_coarse d] from the cell-corner nodes: the Q1 (bi/trilinear)
+    interpolation on the grid of cell corners, evaluated at every global fine node; rows of
+    prescribed components are zero.  Coarse node C = cx + (C_x+1)(cy + (C_y+1) cz)."""
+    ncell = list(ncell)
+    gs = [c * nel + 1 for c in ncell]
+    cs = [c + 1 for c in ncell]
+    ng = g2bg.size
+    gc = np.zeros((ng, dim), np.int64)
+    r = g2bg.astype(np.int64).copy()
+    for ax in range(dim):
+        gc[:, ax] = r % gs[ax]
+        r //= gs[ax]
+    base = np.minimum(gc // nel, np.array(ncell[:dim]) - 1)          # enclosing coarse cell
+    t = (gc - base * nel) / nel                                       # local coordinate in [0, 1]
+    rows, cols, vals = [], [], []
+    for corner in range(2 ** dim):
+        bits = [(corner >> ax) & 1 for ax in range(dim)]
+        w = np.ones(ng)
+        C = np.zeros(ng, np.int64)
+        stride = 1
+        for ax in range(dim):
+            w *= t[:, ax] if bits[ax] else 1.0 - t[:, ax]
+            C += (base[:, ax] + bits[ax]) * stride
+            stride *= cs[ax]
+        for i in range(dim):
+            rows.append(np.arange(ng) * dim + i)
+            cols.append(C * dim + i)
+            vals.append(w)
+    nc = int(np.prod(cs[:dim]))
+    P = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(ng * dim, nc * dim)).tocsr()
+    P.eliminate_zeros()
+    if fixed is not None:
+        keep = sp.diags((~np.asarray(fixed, bool).ravel()).astype(np.float64))
+        P = (keep @ P).tocsr()
+    return P
+
+
+def coarse_operator(K, P):
+    """Galerkin coarse operator K_0 = P^T K P (dense); rows and columns of coarse components with
+    no free fine support get a unit diagonal."""
+    K0 = np.asarray((P.T @ (K @ P)).todense())
+    empty = np.asarray(abs(P).sum(axis=0)).ravel() == 0.0
+    K0[empty, empty] = 1.0
+    return K0

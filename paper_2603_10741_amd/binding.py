@@ -28,7 +28,8 @@ class NewtonOpts(ctypes.Structure):
     _fields_ = [("n_inc", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
                 ("cap", ctypes.c_int32), ("cg_maxit", ctypes.c_int32), ("cg_check", ctypes.c_int32),
                 ("snap_rule", ctypes.c_int32), ("verbose", ctypes.c_int32), ("matvec", ctypes.c_int32),
-                ("tangent", ctypes.c_int32), ("rb_tol", ctypes.c_double),
+                ("tangent", ctypes.c_int32), ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rb_tol", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("armijo_beta", ctypes.c_double), ("armijo_c", ctypes.c_double),
                 ("cg_tol", ctypes.c_double)]
 
@@ -37,13 +38,13 @@ class NewtonRecord(ctypes.Structure):
     """lat_newton_record"""
     _fields_ = [("increment", ctypes.c_int32), ("iteration", ctypes.c_int32), ("n_r", ctypes.c_int32),
                 ("backtracks", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("greedy_status", ctypes.c_int32),
-                ("cg_status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("step", ctypes.c_double),
+                ("cg_status", ctypes.c_int32), ("coarse", ctypes.c_int32), ("step", ctypes.c_double),
                 ("res_before", ctypes.c_double), ("res_after", ctypes.c_double), ("res0", ctypes.c_double),
                 ("rb_achieved", ctypes.c_double), ("cg_relres", ctypes.c_double), ("t_init_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_eval_ms", ctypes.c_double), ("t_product_us", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class LatError(RuntimeError):
@@ -86,7 +87,8 @@ def _lib():
             "lat_cil_to_canon": (ctypes.c_int, [P, P, I64, P, P]),
             "lat_canon_to_cil": (ctypes.c_int, [P, P, I64, P, P]),
             "lat_plain_ops_to_canon": (ctypes.c_int, [P, P, P, P]),
-            "lat_rom_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, F, I32, I32, I32, P, P, P]),
+            "lat_rom_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, F, I32, I32, I32, I32, P, P, P, P]),
+            "lat_coarse_operator": (ctypes.c_int, [P, P, I32, P, P, I32, P, P]),
             "lat_newton_solve": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, I32, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -103,7 +105,7 @@ def exported_symbols():
             "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_apply_combo", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
-            "lat_plain_ops_to_canon", "lat_rom_solve", "lat_newton_solve"]
+            "lat_plain_ops_to_canon", "lat_rom_solve", "lat_coarse_operator", "lat_newton_solve"]
 
 
 def _ptr(t):
@@ -127,6 +129,7 @@ class Plan:
 
     def __init__(self, dim, ncell, nel, keep, cap=64, device="cuda"):
         self.device = torch.device(device)
+        self.ncell = tuple(int(c) for c in ncell)
         keep = np.ascontiguousarray(keep, dtype=np.uint8)
         nc = (ctypes.c_int32 * 3)(*(list(ncell) + [1] * (3 - len(ncell))))
         out = ctypes.c_void_p()
@@ -305,30 +308,45 @@ class Plan:
         return out
 
     # ------------------------------------------------------------------ nonlinear solve
-    def rom_solve(self, K, n_r, alpha, fixed, b, tol=1e-10, maxit=20000, check=32, materialize=True, x=None):
+    def rom_solve(self, K, n_r, alpha, fixed, b, tol=1e-10, maxit=20000, check=32, materialize=True, precond=1,
+                  x=None, info=None):
         """K~ x = b on the free components (lat_rom_solve).  Returns (x, status, iters, relres);
-        status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other codes raise."""
+        status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other codes raise.  `info` (a dict)
+        receives whether the coarse correction ran."""
         x = self._f64(max(self.nglobal, 1) * self.dim) if x is None else x
         it = ctypes.c_int32(0)
         rel = ctypes.c_double(0.0)
+        cu = ctypes.c_int32(0)
         st = _lib().lat_rom_solve(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(fixed), _ptr(b), _ptr(x), float(tol),
-                                  int(maxit), int(check), int(bool(materialize)), ctypes.byref(it), ctypes.byref(rel),
-                                  _stream())
+                                  int(maxit), int(check), int(bool(materialize)), int(precond), ctypes.byref(it),
+                                  ctypes.byref(rel), ctypes.byref(cu), _stream())
         if st not in (LAT_OK, LAT_E_NOCONV, LAT_E_SINGULAR):
             raise LatError(st, "rom_solve")
+        if info is not None:
+            info["coarse_used"] = bool(cu.value)
         return x, st, it.value, rel.value
+
+    def coarse_operator(self, K, n_r, alpha, fixed, materialize=True):
+        """Dense K0 = P^T K~ P over the cell-corner nodes (lat_coarse_operator)."""
+        nc = 1
+        for c in self.ncell[:self.dim]:
+            nc *= c + 1
+        K0 = self._f64(nc * self.dim, nc * self.dim)
+        _ok(_lib().lat_coarse_operator(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(fixed), int(bool(materialize)),
+                                       _ptr(K0), _stream()), "coarse_operator")
+        return K0
 
     def newton_solve(self, mu, lam, fixed, ubar, u, f_ext=None, n_inc=4, max_newton=30, max_backtrack=30, cap=None,
                      rb_tol=3e-4, newton_tol=1e-6, armijo_beta=0.5, armijo_c=1e-4, cg_tol=1e-10, cg_maxit=20000,
                      cg_check=32, snap_rule=RULE_FULL, max_records=1024, verbose=False, matvec=0,
-                     tangent=0):
+                     tangent=0, precond=1):
         """Load-stepped Newton-Raphson with Armijo backtracking (lat_newton_solve); u is updated in
         place.  Returns (status, records); status is LAT_OK, LAT_E_NOCONV, LAT_E_INVERTED or
         LAT_E_NONFINITE, other codes raise."""
         o = NewtonOpts(int(n_inc), int(max_newton), int(max_backtrack), int(cap if cap is not None else self.cap),
-                       int(cg_maxit), int(cg_check), int(snap_rule), int(bool(verbose)), int(matvec), int(tangent), float(rb_tol),
-                       float(newton_tol),
-                       float(armijo_beta), float(armijo_c), float(cg_tol))
+                       int(cg_maxit), int(cg_check), int(snap_rule), int(bool(verbose)), int(matvec), int(tangent),
+                       int(precond), 0, float(rb_tol), float(newton_tol), float(armijo_beta), float(armijo_c),
+                       float(cg_tol))
         recs = (NewtonRecord * max(int(max_records), 1))()
         nrec = ctypes.c_int32(0)
         st = _lib().lat_newton_solve(self._p, _ptr(mu), _ptr(lam), _ptr(fixed), _ptr(ubar), _ptr(f_ext), ctypes.byref(o),

@@ -16,6 +16,10 @@
 // partials in index order): a solve is reproducible bit for bit on a given plan.
 #include <chrono>
 #include <cmath>
+#include <mutex>
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include "lat_internal.h"
 
@@ -220,6 +224,12 @@ __global__ void __launch_bounds__(NB) k_mr_init(int64_t n, const uint8_t *__rest
     if (threadIdx.x == 0) part[blockIdx.x] = zv;
 }
 
+__global__ void k_ctl_clear(MrCtl *ctl)
+{
+    ctl->done = 0;
+    ctl->last = 0;
+}
+
 __global__ void __launch_bounds__(NB) k_mr_init_fin(int nb, const double *__restrict__ part, double tol, MrCtl *ctl)
 {
     __shared__ double sh[NB];
@@ -400,6 +410,289 @@ __global__ void __launch_bounds__(NB) k_mr_x(int64_t nglobal, const int32_t *__r
     }
 }
 
+// ---------------------------------------------------------------------- two-level preconditioner
+// Coarse space: the cell-corner nodes of the lattice (the primal corners of the FETI-DP coarse
+// problem, Sec. 3.3) with Q1 interpolation on the grid of corners, P.  The preconditioner is
+// M^-1 = D^-1 + P K0^-1 P^T with the Galerkin coarse operator K0 = P^T K~ P (prescribed
+// components removed from P's rows), factorised once per tangent solve.  Coarse node
+// C = cx + (C_x+1)(cy + (C_y+1) cz); coarse DOF C d + i.
+
+// Per fine node: the enclosing coarse cell's low corner and the local grid coordinates.
+__global__ void __launch_bounds__(NB) k_coarse_tables(NGrid g, int64_t nglobal, const int64_t *__restrict__ g2bg,
+                                                      int32_t *__restrict__ cbase, uint32_t *__restrict__ cloc)
+{
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (G >= nglobal) return;
+    int64_t bg = g2bg[G];
+    int32_t base = 0, stride = 1;
+    uint32_t loc = 0;
+    for (int ax = 0; ax < g.dim; ++ax) {
+        const int gc = (int)(bg % g.gs[ax]);
+        bg /= g.gs[ax];
+        const int b = min(gc / g.nel, g.ncell[ax] - 1);
+        base += b * stride;
+        stride *= g.ncell[ax] + 1;
+        loc |= (uint32_t)(gc - b * g.nel) << (10 * ax);
+    }
+    cbase[G] = base;
+    cloc[G] = loc;
+}
+
+// prim[c][a] = 1 when cell c is the lowest-id owner of its active local node a (each fine node
+// enters the restriction once)
+__global__ void __launch_bounds__(NB) k_coarse_prim(NGrid g, int64_t ncells, const int64_t *__restrict__ g2bg,
+                                                    const int32_t *__restrict__ l2g, uint8_t *__restrict__ prim)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= ncells * g.nloc) return;
+    const int64_t c = t / g.nloc;
+    const int32_t G = l2g[t];
+    uint8_t v = 0;
+    if (G >= 0) {
+        int64_t first = -1;
+        for_owners(g, g2bg[G], l2g, [&](int64_t cell, int) {
+            if (first < 0) first = cell;
+        });
+        v = first == c;
+    }
+    prim[t] = v;
+}
+
+// Q1 corner function k of a cell at its local node with grid coordinates (ix, iy, iz)
+__device__ __forceinline__ double corner_phi(int k, int dim, int nel, const int (&ic)[3])
+{
+    double f = 1.0;
+    for (int ax = 0; ax < dim; ++ax) {
+        const double t = (double)ic[ax] / nel;
+        f *= ((k >> ax) & 1) ? t : 1.0 - t;
+    }
+    return f;
+}
+
+// The cells' corner functions on the packed layout, m = 2^d d right-hand sides (r = k d + i:
+// corner k, component i), zero on prescribed components and on DOFs a cell does not own.
+__global__ void __launch_bounds__(NB) k_coarse_X(NGrid g, int64_t npk, const int32_t *__restrict__ qgroup,
+                                                 const int32_t *__restrict__ unode, const int32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ l2g, const uint8_t *__restrict__ fixed,
+                                                 double *__restrict__ X)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= npk * LAT_WAVE) return;
+    const int d = g.dim, m = (1 << d) * d;
+    const int l = (int)(t % LAT_WAVE);
+    const int64_t q = t / LAT_WAVE;
+    const int cell = perm[(int64_t)qgroup[q] * LAT_WAVE + l];
+    const int a = unode[q];
+    const int32_t G = cell >= 0 ? l2g[(int64_t)cell * g.nloc + a] : -1;
+    const int ic[3] = {a % g.nn, (a / g.nn) % g.nn, a / (g.nn * g.nn)};
+    for (int j = 0; j < d; ++j) {
+        const bool free_j = G >= 0 && !fixed[(int64_t)G * d + j];
+        for (int r = 0; r < m; ++r) {
+            const double v = (free_j && r % d == j) ? corner_phi(r / d, d, g.nel, ic) : 0.0;
+            X[((q * d + j) * m + r) * LAT_WAVE + l] = v;
+        }
+    }
+}
+
+// Per-cell coarse matrices K0s[c][r1][r2] = sum over the cell's DOFs of X[., r1] (K~ X)[., r2]
+template <int MM>
+__global__ void __launch_bounds__(LAT_WAVE) k_coarse_cellmat(int dim, const int32_t *__restrict__ goff,
+                                                             const int32_t *__restrict__ perm,
+                                                             const double *__restrict__ X,
+                                                             const double *__restrict__ Y, double *__restrict__ K0s)
+{
+    const int g = blockIdx.x, r1 = blockIdx.y, l = threadIdx.x;
+    const int cell = perm[(int64_t)g * LAT_WAVE + l];
+    double acc[MM];
+#pragma unroll
+    for (int r = 0; r < MM; ++r) acc[r] = 0.0;
+    for (int64_t q = goff[g]; q < goff[g + 1]; ++q)
+        for (int j = 0; j < dim; ++j) {
+            const int64_t row = (q * dim + j) * MM;
+            const double x1 = X[(row + r1) * LAT_WAVE + l];
+            if (x1 != 0.0)
+#pragma unroll
+                for (int r = 0; r < MM; ++r) acc[r] = fma(x1, Y[(row + r) * LAT_WAVE + l], acc[r]);
+        }
+    if (cell >= 0)
+#pragma unroll
+        for (int r = 0; r < MM; ++r) K0s[((int64_t)cell * MM + r1) * MM + r] = acc[r];
+}
+
+// Dense K0 (row-major, pre-zeroed), one thread per coarse row: the cells around the row's corner
+// in ascending id; a row with no free fine support gets a unit diagonal.
+__global__ void __launch_bounds__(NB) k_coarse_assemble(NGrid g, int ncd, const double *__restrict__ K0s,
+                                                        double *__restrict__ K0)
+{
+    const int R = blockIdx.x * NB + threadIdx.x;
+    if (R >= ncd) return;
+    const int d = g.dim, nco = 1 << d, m = nco * d;
+    const int C1 = R / d, i1 = R % d;
+    const int cs0 = g.ncell[0] + 1, cs1 = g.ncell[1] + 1;
+    const int c1[3] = {C1 % cs0, (C1 / cs0) % cs1, C1 / (cs0 * cs1)};
+    double *row = K0 + (int64_t)R * ncd;
+    for (int kz = (d == 3 ? 1 : 0); kz >= 0; --kz)
+        for (int ky = 1; ky >= 0; --ky)
+            for (int kx = 1; kx >= 0; --kx) {
+                const int kk[3] = {kx, ky, kz};
+                int cc[3] = {0, 0, 0}, bits = 0;
+                bool ok = true;
+                for (int ax = 0; ax < d; ++ax) {
+                    cc[ax] = c1[ax] - kk[ax];
+                    ok = ok && cc[ax] >= 0 && cc[ax] < g.ncell[ax];
+                    bits |= kk[ax] << ax;
+                }
+                if (!ok) continue;
+                const int64_t cell = cc[0] + (int64_t)g.ncell[0] * (cc[1] + (int64_t)g.ncell[1] * cc[2]);
+                const double *ks = K0s + ((int64_t)cell * m + bits * d + i1) * m;
+                for (int k2 = 0; k2 < nco; ++k2) {
+                    const int C2 = (cc[0] + (k2 & 1)) + cs0 * ((cc[1] + ((k2 >> 1) & 1)) + cs1 * (cc[2] + ((k2 >> 2) & 1)));
+                    for (int i2 = 0; i2 < d; ++i2) row[C2 * d + i2] += ks[k2 * d + i2];
+                }
+            }
+    if (row[R] == 0.0) row[R] = 1.0;
+}
+
+// Copy the lower triangle (column-major, as factorised) of a symmetric matrix into the upper one.
+__global__ void __launch_bounds__(NB) k_symmetrize(int64_t n, double *__restrict__ A)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= n * n) return;
+    const int64_t i = t / n, j = t % n;
+    if (i > j) A[j + i * n] = A[i + j * n];
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, LAT_WAVE);
+    return v;
+}
+
+// Restriction, per cell (one wave each): cpart[c][k][i] = sum over the cell's primary nodes of
+// phi_k v_i
+template <int D>
+__global__ void __launch_bounds__(NB) k_cr_restrict(int nel, int nn, int64_t ncells, const int32_t *__restrict__ l2g,
+                                                    const uint8_t *__restrict__ prim, const double *__restrict__ v,
+                                                    double *__restrict__ cpart, const MrCtl *__restrict__ ctl)
+{
+    constexpr int NCO = 1 << D;
+    if (ctl->done) return;
+    const int64_t c = (int64_t)blockIdx.x * (NB / LAT_WAVE) + (threadIdx.x >> 6);
+    if (c >= ncells) return;
+    const int l = threadIdx.x & 63;
+    const int nloc = D == 2 ? nn * nn : nn * nn * nn;
+    double acc[NCO][D];
+#pragma unroll
+    for (int k = 0; k < NCO; ++k)
+#pragma unroll
+        for (int i = 0; i < D; ++i) acc[k][i] = 0.0;
+    for (int a = l; a < nloc; a += LAT_WAVE) {
+        if (!prim[c * nloc + a]) continue;
+        const int64_t G = l2g[c * nloc + a];
+        const int ic[3] = {a % nn, (a / nn) % nn, a / (nn * nn)};
+        double vi[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) vi[i] = v[G * D + i];
+#pragma unroll
+        for (int k = 0; k < NCO; ++k) {
+            const double f = corner_phi(k, D, nel, ic);
+#pragma unroll
+            for (int i = 0; i < D; ++i) acc[k][i] = fma(f, vi[i], acc[k][i]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NCO; ++k)
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double s = wave_sum(acc[k][i]);
+            if (l == 0) cpart[(c * NCO + k) * D + i] = s;
+        }
+}
+
+// rc[C d + i] = sum over the cells around corner C (ascending id) of their partials
+__global__ void __launch_bounds__(NB) k_cr_sum(NGrid g, int ncd, const double *__restrict__ cpart,
+                                               double *__restrict__ rc, const MrCtl *__restrict__ ctl)
+{
+    if (ctl->done) return;
+    const int R = blockIdx.x * NB + threadIdx.x;
+    if (R >= ncd) return;
+    const int d = g.dim, nco = 1 << d;
+    const int C = R / d, i = R % d;
+    const int cs0 = g.ncell[0] + 1, cs1 = g.ncell[1] + 1;
+    const int c1[3] = {C % cs0, (C / cs0) % cs1, C / (cs0 * cs1)};
+    double acc = 0.0;
+    for (int kz = (d == 3 ? 1 : 0); kz >= 0; --kz)
+        for (int ky = 1; ky >= 0; --ky)
+            for (int kx = 1; kx >= 0; --kx) {
+                const int kk[3] = {kx, ky, kz};
+                int cc[3] = {0, 0, 0}, bits = 0;
+                bool ok = true;
+                for (int ax = 0; ax < d; ++ax) {
+                    cc[ax] = c1[ax] - kk[ax];
+                    ok = ok && cc[ax] >= 0 && cc[ax] < g.ncell[ax];
+                    bits |= kk[ax] << ax;
+                }
+                if (!ok) continue;
+                const int64_t cell = cc[0] + (int64_t)g.ncell[0] * (cc[1] + (int64_t)g.ncell[1] * cc[2]);
+                acc += cpart[(cell * nco + bits) * d + i];
+            }
+    rc[R] = acc;
+}
+
+// ec = K0^-1 rc, one wave per row
+__global__ void __launch_bounds__(NB) k_cr_gemv(int ncd, const double *__restrict__ A, const double *__restrict__ x,
+                                                double *__restrict__ y, const MrCtl *__restrict__ ctl)
+{
+    if (ctl->done) return;
+    const int64_t R = (int64_t)blockIdx.x * (NB / LAT_WAVE) + (threadIdx.x >> 6);
+    if (R >= ncd) return;
+    const int l = threadIdx.x & 63;
+    const double *row = A + R * ncd;
+    double acc = 0.0;
+    for (int c = l; c < ncd; c += LAT_WAVE) acc = fma(row[c], x[c], acc);
+    acc = wave_sum(acc);
+    if (l == 0) y[R] = acc;
+}
+
+// z += P ec on the free components; partial <z, v>
+template <int D>
+__global__ void __launch_bounds__(NB) k_cr_prolong(int nel, int cs0, int cs1, int64_t nglobal,
+                                                   const int32_t *__restrict__ cbase, const uint32_t *__restrict__ cloc,
+                                                   const uint8_t *__restrict__ fixed, const double *__restrict__ ec,
+                                                   const double *__restrict__ v, double *__restrict__ z,
+                                                   double *__restrict__ part, const MrCtl *__restrict__ ctl)
+{
+    __shared__ double sh[NB];
+    if (ctl->done) return;
+    const int64_t G = (int64_t)blockIdx.x * NB + threadIdx.x;
+    double dot = 0.0;
+    if (G < nglobal) {
+        const int32_t base = cbase[G];
+        const uint32_t lc = cloc[G];
+        const int ic[3] = {(int)(lc & 1023u), (int)((lc >> 10) & 1023u), (int)((lc >> 20) & 1023u)};
+        double add[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) add[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < (1 << D); ++k) {
+            const double f = corner_phi(k, D, nel, ic);
+            const int C = base + (k & 1) + cs0 * (((k >> 1) & 1) + cs1 * ((k >> 2) & 1));
+#pragma unroll
+            for (int i = 0; i < D; ++i) add[i] = fma(f, ec[(int64_t)C * D + i], add[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int64_t j = G * D + i;
+            const double zj = fixed[j] ? z[j] : z[j] + add[i];
+            z[j] = zj;
+            dot = fma(zj, v[j], dot);
+        }
+    }
+    dot = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+}
+
 // Combined stencil of every cell, K~_s = sum_k alpha_sk K_k (eq. romstiffnessmatrix), in the
 // packed per-cell operator layout of lat_apply_plain: ops[(q E + e) 64 + l] for packed node q of
 // group g and lane l (cell perm[64 g + l]; padding lanes get 0).  One thread per (q, l) keeps its
@@ -534,9 +827,33 @@ struct MrWork {
     static constexpr int NT = 64;            // products timed per solve (the first NT)
     hipEvent_t tev[2 * NT] = {};
     unsigned nbn = 1, nbv = 1;   // blocks over nodes, over components
+    // two-level preconditioner (coarse space of cell corners)
+    bool coarse = false;         // requested and within the size limit
+    bool coarse_on = false;      // the current solve's coarse operator factorised
+    int ncd = 0, mc = 0;         // coarse DOFs, corner functions per cell
+    int32_t *cbase = nullptr;
+    uint32_t *cloc = nullptr;
+    uint8_t *prim = nullptr;
+    double *Xc = nullptr, *Yc = nullptr, *K0s = nullptr, *K0 = nullptr, *cpart = nullptr, *rc = nullptr, *ec = nullptr;
+    int32_t *info = nullptr;
 };
 
-lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize, hipStream_t s)
+constexpr int COARSE_MAX = 16384;   // coarse DOFs held as a dense factor
+
+// One rocBLAS handle per device for the coarse factorisation (created on first use, kept).
+rocblas_handle solver_handle()
+{
+    static std::mutex mu;
+    static rocblas_handle h[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!h[dev] && rocblas_create_handle(&h[dev]) != rocblas_status_success) h[dev] = nullptr;
+    return h[dev];
+}
+
+lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize, hipStream_t s, bool coarse = false,
+                    const uint8_t *fixed = nullptr)
 {
     const int64_t n = P->nglobal * P->dim;
     const int64_t npk = std::max<int64_t>(P->npacked, 1) * P->dim * LAT_WAVE;
@@ -555,6 +872,100 @@ lat_status mr_alloc(const lat_plan *P, Arena &ar, MrWork &w, bool materialize, h
                        P->nglobal, P->g2bg, P->l2g, w.own);
     LAT_LAUNCH_CHECK();
     if (materialize) NCHK(ar.get(&w.ops, std::max<int64_t>(P->npacked, 1) * P->E * LAT_WAVE));
+    int64_t nc = 1;
+    for (int ax = 0; ax < P->dim; ++ax) nc *= P->ncell[ax] + 1;
+    w.ncd = (int)std::min<int64_t>(nc * P->dim, INT32_MAX);
+    w.mc = (1 << P->dim) * P->dim;
+    w.coarse = coarse && fixed && nc * P->dim <= COARSE_MAX && P->npacked > 0;
+    if (w.coarse) {
+        const NGrid g = make_ngrid(P);
+        const int64_t npm = P->npacked * P->dim * w.mc * LAT_WAVE;
+        NCHK(ar.get(&w.cbase, P->nglobal)); NCHK(ar.get(&w.cloc, P->nglobal));
+        NCHK(ar.get(&w.prim, P->ncells * P->nloc));
+        NCHK(ar.get(&w.Xc, npm)); NCHK(ar.get(&w.Yc, npm));
+        NCHK(ar.get(&w.K0s, P->ncells * w.mc * w.mc));
+        NCHK(ar.get(&w.K0, (int64_t)w.ncd * w.ncd));
+        NCHK(ar.get(&w.cpart, P->ncells * (1 << P->dim) * P->dim));
+        NCHK(ar.get(&w.rc, w.ncd)); NCHK(ar.get(&w.ec, w.ncd)); NCHK(ar.get(&w.info, 1));
+        hipLaunchKernelGGL(k_coarse_tables, dim3(w.nbn), dim3(NB), 0, s, g, P->nglobal, P->g2bg, w.cbase, w.cloc);
+        hipLaunchKernelGGL(k_coarse_prim, dim3((unsigned)lat_cdiv(P->ncells * P->nloc, NB)), dim3(NB), 0, s, g,
+                           P->ncells, P->g2bg, P->l2g, w.prim);
+        hipLaunchKernelGGL(k_coarse_X, dim3((unsigned)lat_cdiv(P->npacked * LAT_WAVE, NB)), dim3(NB), 0, s, g,
+                           (int64_t)P->npacked, P->goff + P->ngroups + 1, P->unode, P->perm, P->l2g, fixed, w.Xc);
+        LAT_LAUNCH_CHECK();
+    }
+    return LAT_OK;
+}
+
+// K0 = P^T K~ P (dense, row-major) of the operator given by `ops` or (K, alpha): one apply of the
+// cells' corner functions, per-cell m x m products, owner-ordered assembly.
+lat_status coarse_operator(const lat_plan *P, MrWork &w, const double *K, int n_r, const double *alpha,
+                           const double *ops, hipStream_t s)
+{
+    if (ops) NCHK(lat_apply_plain(P, ops, w.Xc, w.Yc, w.mc, s));
+    else NCHK(lat_apply_combo(P, K, n_r, alpha, w.Xc, w.Yc, w.mc, LAT_F64, 0.0, 0, s));
+    const dim3 cg((unsigned)P->ngroups, (unsigned)w.mc);
+    if (w.mc == 8) hipLaunchKernelGGL(k_coarse_cellmat<8>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc, w.K0s);
+    else hipLaunchKernelGGL(k_coarse_cellmat<24>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc, w.K0s);
+    const int64_t nn2 = (int64_t)w.ncd * w.ncd;
+    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(nn2)), dim3(NB), 0, s, nn2, 0.0, w.K0);
+    hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)lat_cdiv(w.ncd, NB)), dim3(NB), 0, s, make_ngrid(P), w.ncd,
+                       w.K0s, w.K0);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
+// Form and invert K0 for this solve; a coarse operator that is not positive definite (an
+// indefinite tangent) leaves the solve with the diagonal preconditioner alone.
+lat_status coarse_setup(const lat_plan *P, MrWork &w, const double *K, int n_r, const double *alpha,
+                        const double *ops, hipStream_t s)
+{
+    w.coarse_on = false;
+    if (!w.coarse) return LAT_OK;
+    NCHK(coarse_operator(P, w, K, n_r, alpha, ops, s));
+    rocblas_handle h = solver_handle();
+    if (!h || rocblas_set_stream(h, s) != rocblas_status_success) return LAT_E_DEVICE;
+    int32_t info = 0;
+    if (rocsolver_dpotrf(h, rocblas_fill_lower, w.ncd, w.K0, w.ncd, w.info) != rocblas_status_success)
+        return LAT_E_DEVICE;
+    LAT_HIP(hipMemcpyAsync(&info, w.info, sizeof(info), hipMemcpyDeviceToHost, s));
+    LAT_HIP(hipStreamSynchronize(s));
+    if (info != 0) return LAT_OK;
+    if (rocsolver_dpotri(h, rocblas_fill_lower, w.ncd, w.K0, w.ncd, w.info) != rocblas_status_success)
+        return LAT_E_DEVICE;
+    LAT_HIP(hipMemcpyAsync(&info, w.info, sizeof(info), hipMemcpyDeviceToHost, s));
+    LAT_HIP(hipStreamSynchronize(s));
+    if (info != 0) return LAT_OK;
+    const int64_t nn2 = (int64_t)w.ncd * w.ncd;
+    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)lat_cdiv(nn2, NB)), dim3(NB), 0, s, (int64_t)w.ncd, w.K0);
+    LAT_LAUNCH_CHECK();
+    w.coarse_on = true;
+    return LAT_OK;
+}
+
+// z += P K0^-1 P^T v; partial <z, v> over the node blocks into w.part
+lat_status coarse_apply(const lat_plan *P, MrWork &w, const uint8_t *fixed, const double *v, double *z, hipStream_t s)
+{
+    const NGrid g = make_ngrid(P);
+    const unsigned nbc = (unsigned)lat_cdiv(P->ncells, NB / LAT_WAVE);
+    const unsigned nbr = (unsigned)lat_cdiv(w.ncd, NB);
+    const unsigned nbg = (unsigned)lat_cdiv(w.ncd, NB / LAT_WAVE);
+    const int cs0 = P->ncell[0] + 1, cs1 = P->ncell[1] + 1;
+    if (P->dim == 2)
+        hipLaunchKernelGGL(k_cr_restrict<2>, dim3(nbc), dim3(NB), 0, s, P->nel, P->nn, P->ncells, P->l2g, w.prim, v,
+                           w.cpart, w.ctl);
+    else
+        hipLaunchKernelGGL(k_cr_restrict<3>, dim3(nbc), dim3(NB), 0, s, P->nel, P->nn, P->ncells, P->l2g, w.prim, v,
+                           w.cpart, w.ctl);
+    hipLaunchKernelGGL(k_cr_sum, dim3(nbr), dim3(NB), 0, s, g, w.ncd, w.cpart, w.rc, w.ctl);
+    hipLaunchKernelGGL(k_cr_gemv, dim3(nbg), dim3(NB), 0, s, w.ncd, w.K0, w.rc, w.ec, w.ctl);
+    if (P->dim == 2)
+        hipLaunchKernelGGL(k_cr_prolong<2>, dim3(w.nbn), dim3(NB), 0, s, P->nel, cs0, cs1, P->nglobal, w.cbase, w.cloc,
+                           fixed, w.ec, v, z, w.part, w.ctl);
+    else
+        hipLaunchKernelGGL(k_cr_prolong<3>, dim3(w.nbn), dim3(NB), 0, s, P->nel, cs0, cs1, P->nglobal, w.cbase, w.cloc,
+                           fixed, w.ec, v, z, w.part, w.ctl);
+    LAT_LAUNCH_CHECK();
     return LAT_OK;
 }
 
@@ -577,10 +988,18 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
     else
         hipLaunchKernelGGL(k_jacobi, dim3(w.nbn), dim3(NB), 0, s, g, P->nglobal, P->g2bg, P->l2g, K, alpha, P->cap,
                            n_r, P->E, fixed, w.dinv);
+    NCHK(coarse_setup(P, w, K, n_r, alpha, ops, s));
+    const bool two = w.coarse_on;
+    const int nbz = two ? (int)w.nbn : (int)w.nbv;   // partial sums of <z, v>: node or component blocks
     // v_0 = v[0], v_1 = v[1], z_1 = z[1], w_0 = w[0], w_1 = w[1]
     hipLaunchKernelGGL(k_mr_init, dim3(w.nbv), dim3(NB), 0, s, n, fixed, w.dinv, b, x, w.v[0], w.v[1], w.z[1], w.w[0],
                        w.w[1], w.part);
-    hipLaunchKernelGGL(k_mr_init_fin, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, tol, w.ctl);
+    if (two) {
+        // the control block is not yet initialised: clear its stop flag for the coarse kernels
+        hipLaunchKernelGGL(k_ctl_clear, dim3(1), dim3(1), 0, s, w.ctl);
+        NCHK(coarse_apply(P, w, fixed, w.v[1], w.z[1], s));
+    }
+    hipLaunchKernelGGL(k_mr_init_fin, dim3(1), dim3(NB), 0, s, nbz, w.part, tol, w.ctl);
     // z_1 / gamma_1 into the packed input of the first product
     if (P->dim == 2)
         hipLaunchKernelGGL(k_mr_scale<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, w.z[1], w.ppk, w.ctl);
@@ -615,7 +1034,8 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
                                    w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_delta, dim3(1), dim3(NB), 0, s, (int)w.nbn, w.part, w.ctl);
             hipLaunchKernelGGL(k_mr_v, dim3(w.nbv), dim3(NB), 0, s, n, w.y, vj, vjm1, w.dinv, zj1, w.part, w.ctl);
-            hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(NB), 0, s, (int)w.nbv, w.part, it, w.ctl);
+            if (two) NCHK(coarse_apply(P, w, fixed, vjm1, zj1, s));   // v_{j+1} now lives in vjm1
+            hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(NB), 0, s, nbz, w.part, it, w.ctl);
             if (P->dim == 2)
                 hipLaunchKernelGGL(k_mr_x<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, zj, wj, wjm1, x, zj1,
                                    w.ppk, w.ctl);
@@ -652,10 +1072,12 @@ extern "C" {
 
 lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const double *alpha, const uint8_t *fixed,
                          const double *b, double *x, double tol, int32_t maxit, int32_t check, int32_t materialize,
-                         int32_t *iters, double *relres, hipStream_t stream)
+                         int32_t precond, int32_t *iters, double *relres, int32_t *coarse_used, hipStream_t stream)
 {
+    if (coarse_used) *coarse_used = 0;
     if (!P || !K || !alpha || !fixed || !b || !x) return LAT_E_ARG;
-    if (n_r < 0 || n_r > P->cap || !(tol > 0.0) || maxit < 0 || check < 1) return LAT_E_ARG;
+    if (n_r < 0 || n_r > P->cap || !(tol > 0.0) || maxit < 0 || check < 1 || (precond != 0 && precond != 1))
+        return LAT_E_ARG;
     if (P->nglobal == 0) {
         if (iters) *iters = 0;
         if (relres) *relres = 0.0;
@@ -663,15 +1085,33 @@ lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const 
     }
     Arena ar;
     MrWork w;
-    NCHK(mr_alloc(P, ar, w, materialize != 0, stream));
+    NCHK(mr_alloc(P, ar, w, materialize != 0, stream, precond == 1, fixed));
     int it = 0;
     double rr = 0.0;
     if (w.ops) NCHK(combine_ops(P, K, n_r, alpha, w.ops, stream));
     const lat_status st = mr_run(P, w, K, n_r, alpha, w.ops, fixed, b, x, tol, maxit, check, &it, &rr, stream);
     if (iters) *iters = it;
     if (relres) *relres = rr;
+    if (coarse_used) *coarse_used = w.coarse_on;
     LAT_HIP(hipStreamSynchronize(stream));
     return st;
+}
+
+lat_status lat_coarse_operator(const lat_plan *P, const double *K, int32_t n_r, const double *alpha,
+                               const uint8_t *fixed, int32_t materialize, double *K0, hipStream_t stream)
+{
+    if (!P || !K || !alpha || !fixed || !K0) return LAT_E_ARG;
+    if (n_r < 0 || n_r > P->cap) return LAT_E_ARG;
+    if (P->nglobal == 0 || P->npacked == 0) return LAT_E_SHAPE;
+    Arena ar;
+    MrWork w;
+    NCHK(mr_alloc(P, ar, w, materialize != 0, stream, true, fixed));
+    if (!w.coarse) return LAT_E_SHAPE;
+    if (w.ops) NCHK(combine_ops(P, K, n_r, alpha, w.ops, stream));
+    NCHK(coarse_operator(P, w, K, n_r, alpha, w.ops, stream));
+    LAT_HIP(hipMemcpyAsync(K0, w.K0, (size_t)w.ncd * w.ncd * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    LAT_HIP(hipStreamSynchronize(stream));
+    return LAT_OK;
 }
 
 lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *lam, const uint8_t *fixed,
@@ -682,7 +1122,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     if (!P || !mu || !lam || !fixed || !ubar || !o || !u) return LAT_E_ARG;
     if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
         o->cg_maxit < 1 || o->cg_check < 1 || (o->matvec != 0 && o->matvec != 1) ||
-        (o->tangent != 0 && o->tangent != 1) || (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
+        (o->tangent != 0 && o->tangent != 1) || (o->precond != 0 && o->precond != 1) || (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
         !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
         !(o->armijo_c >= 0.0 && o->armijo_c < 1.0) || !(o->cg_tol > 0.0) || max_records < 0 ||
         (max_records > 0 && !records))
@@ -693,7 +1133,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     Arena ar;
     MrWork w;
     const bool full = o->tangent == 1;   // each cell's own tangent (the standard method)
-    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0, s));
+    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0, s, o->precond == 1, fixed));
     double *u_try, *du, *rhs, *r, *r_try, *fasm, *f_cil, *snap, *K, *alpha, *R, *scal;
     int32_t *S, *nr_d, *st_d, *gst_d;
     NCHK(ar.get(&u_try, n)); NCHK(ar.get(&du, n)); NCHK(ar.get(&rhs, n)); NCHK(ar.get(&r, n));
@@ -776,7 +1216,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             const lat_status cst = mr_run(P, w, K, hnr, alpha, w.ops, fixed, rhs, du, o->cg_tol, o->cg_maxit,
                                           o->cg_check, &cgit, &cgrel, s, &rec.t_product_us);
             if (cst != LAT_OK && cst != LAT_E_NOCONV && cst != LAT_E_SINGULAR) return cst;
-            rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst;
+            rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst; rec.coarse = w.coarse_on;
             rec.t_solve_ms = ms_since(t0);
             // Armijo backtracking on ||r||
             t0 = std::chrono::steady_clock::now();
@@ -795,9 +1235,10 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             if (records && nrec < max_records) records[nrec] = rec;
             ++nrec;
             if (o->verbose) {
-                std::fprintf(stderr, "newton inc %d it %d: n_r %d, solve %d its (status %d), m %d, |r|/|r0| %.3e, "
-                             "ms init %.1f solve %.1f eval %.1f\n", t, it, rec.n_r, rec.cg_iters, rec.cg_status,
-                             rec.backtracks, (ok ? rt : rn) / r0, rec.t_init_ms, rec.t_solve_ms, rec.t_eval_ms);
+                std::fprintf(stderr, "newton inc %d it %d: n_r %d, solve %d its (status %d, coarse %d), m %d, "
+                             "|r|/|r0| %.3e, ms init %.1f solve %.1f eval %.1f\n", t, it, rec.n_r, rec.cg_iters,
+                             rec.cg_status, rec.coarse, rec.backtracks, (ok ? rt : rn) / r0, rec.t_init_ms,
+                             rec.t_solve_ms, rec.t_eval_ms);
                 std::fflush(stderr);
             }
             if (!ok) { result = LAT_E_NOCONV; break; }

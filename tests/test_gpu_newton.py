@@ -289,3 +289,46 @@ def test_newton_two_groups_matches_oracle(two_groups):
             assert g["n_r"] == (o["n_r"] if tangent == 0 else 0)
             assert abs(g["res_after"] - o["res_after"]) <= 1e-6 * o["res_before"]
         assert np.abs(u.cpu().numpy() - out["u"]).max() <= 1e-7 * np.abs(out["u"]).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_operator_matches_oracle(dim):
+    # K0 = P^T K~ P over the cell-corner nodes, against the oracle's sparse ROM matrix and Q1
+    # prolongation (prescribed rows removed)
+    if dim == 2:
+        cfg = L.config(0).with_(radius=(0.25, 0.35))
+        case = L.LoadCase("compress_shear", 0.04, 0.01, 4)
+    else:
+        cfg = L.config(2).with_(ncell=(2, 2, 2), nel=6)
+        case = L.LoadCase("compress_shear", 0.02, 0.005, 4)
+    nc = NCase(cfg, case, cap=16)
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, alpha, Ko = _rom_at(nc, u, 1e-4, 16)
+    Pc = ON.coarse_prolongation(dim, cfg.ncell_eff, cfg.nel, nc.orc.g2bg, nc.orc.fixed)
+    K0o = ON.coarse_operator(Ko, Pc)
+    for mat in (True, False):
+        K0 = nc.P.coarse_operator(K, n_r, alpha, nc.fixed_t, materialize=mat).cpu().numpy()
+        assert np.abs(K0 - K0o).max() <= 1e-11 * np.abs(K0o).max()
+
+
+def test_rom_solve_two_level(graded):
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, alpha, Ko = _rom_at(nc, u, 1e-4, 16)
+    rng = np.random.default_rng(25)
+    b = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    b_t = torch.from_numpy(b).to(nc.dev)
+    f = nc.orc.free
+    xo = np.zeros(b.size)
+    xo[f] = spla.spsolve(Ko[f][:, f].tocsc(), b.ravel()[f])
+    its = {}
+    for pc in (0, 1):
+        info = {}
+        x, st, it, rr = nc.P.rom_solve(K, n_r, alpha, nc.fixed_t, b_t, tol=1e-12, maxit=50000, check=64, precond=pc,
+                                       info=info)
+        assert st == nc.B.LAT_OK and rr <= 1e-12
+        assert info["coarse_used"] == (pc == 1)
+        assert rel(x.reshape(-1, cfg.dim).cpu().numpy().ravel(), xo) <= 1e-6
+        its[pc] = it
+    assert its[1] < its[0]

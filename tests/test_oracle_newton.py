@@ -161,3 +161,54 @@ def test_reduced_snapshots_reach_the_same_equilibrium(exact_graded):
     assert out["status"] == O.OK
     assert any(r["n_r"] < 16 for r in out["records"])
     assert np.abs(out["u"] - out_full["u"]).max() <= 1e-10 * np.abs(out_full["u"]).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_prolongation_is_q1_interpolation(dim):
+    # Q1 interpolation on the cell-corner grid: a partition of unity, exact on affine fields,
+    # and equal to the corner value at every corner node.
+    cfg = L.config(0 if dim == 2 else 2).with_(ncell=(3, 2) if dim == 2 else (2, 2, 2), nel=4)
+    keep = L.make_keep(cfg)
+    l2g, _, g2bg = O.dofmap(dim, cfg.ncell, cfg.nel, keep)
+    P = ON.coarse_prolongation(dim, cfg.ncell, cfg.nel, g2bg)
+    nc = P.shape[1] // dim
+    np.testing.assert_allclose(np.asarray(P.sum(axis=1)).ravel(), dim * 0 + 1.0, rtol=0, atol=1e-15)
+    cs = [c + 1 for c in cfg.ncell]
+    Xc = np.zeros((nc, dim))
+    r = np.arange(nc)
+    for ax in range(dim):
+        Xc[:, ax] = r % cs[ax]
+        r //= cs[ax]
+    gs = [c * cfg.nel + 1 for c in cfg.ncell]
+    Xf = np.zeros((g2bg.size, dim))
+    r = g2bg.copy()
+    for ax in range(dim):
+        Xf[:, ax] = (r % gs[ax]) / cfg.nel
+        r //= gs[ax]
+    A = np.arange(1, dim * dim + 1).reshape(dim, dim) / 7.0
+    b = np.arange(dim) - 0.5
+    uc = Xc @ A.T + b
+    uf = (P @ uc.ravel()).reshape(-1, dim)
+    np.testing.assert_allclose(uf, Xf @ A.T + b, rtol=0, atol=1e-13)
+
+
+def test_coarse_operator_kills_translations_and_is_galerkin():
+    # No prescribed components: rigid translations lie in the kernel of every cell tangent at
+    # u = 0, and P maps coarse translations to fine translations, so K_0 annihilates them.
+    cfg = L.config(0).with_(ncell=(3, 2), nel=8, radius=(0.25, 0.35))
+    keep = L.make_keep(cfg)
+    l2g, _, g2bg = O.dofmap(2, cfg.ncell, cfg.nel, keep)
+    ul = np.zeros((cfg.n_cells, (cfg.nel + 1) ** 2, 2))
+    T = O.cells_eval(2, cfg.nel, keep, ul, 1.0, 10.0, want_f=False, want_energy=False)["T"]
+    g = O.greedy(T, 1e-10, 6)
+    K = ON.rom_matrix(2, cfg.nel, T[g["S"][:g["n_r"]]], g["alpha"], l2g, g2bg.size)
+    P = ON.coarse_prolongation(2, cfg.ncell, cfg.nel, g2bg)
+    K0 = ON.coarse_operator(K, P)
+    assert np.abs(K0 - K0.T).max() <= 1e-12 * np.abs(K0).max()
+    nc = K0.shape[0] // 2
+    for i in range(2):
+        t = np.zeros((nc, 2)); t[:, i] = 1.0
+        assert np.abs(K0 @ t.ravel()).max() <= 1e-11 * np.abs(K0).max()
+    rng = np.random.default_rng(3)
+    a, c = rng.standard_normal(2 * nc), rng.standard_normal(2 * nc)
+    assert abs(a @ K0 @ c - (P @ a) @ (K @ (P @ c))) <= 1e-11 * np.abs(K0).max() * 2 * nc
