@@ -461,12 +461,32 @@ __global__ void __launch_bounds__(NB) k_coarse_prim(NGrid g, int64_t ncells, con
 // Q1 corner function k of a cell at its local node with grid coordinates (ix, iy, iz)
 __device__ __forceinline__ double corner_phi(int k, int dim, int nel, const int (&ic)[3])
 {
+    const double h = 1.0 / nel;
     double f = 1.0;
     for (int ax = 0; ax < dim; ++ax) {
-        const double t = (double)ic[ax] / nel;
+        const double t = ic[ax] * h;
         f *= ((k >> ax) & 1) ? t : 1.0 - t;
     }
     return f;
+}
+
+// All 2^D corner functions at once from the per-axis coordinates t = ic / n
+template <int D>
+__device__ __forceinline__ void corner_phis(double h, const int (&ic)[3], double (&phi)[1 << D])
+{
+    double t[3], u[3];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        t[ax] = ic[ax] * h;
+        u[ax] = 1.0 - t[ax];
+    }
+#pragma unroll
+    for (int k = 0; k < (1 << D); ++k) {
+        double f = (k & 1) ? t[0] : u[0];
+#pragma unroll
+        for (int ax = 1; ax < D; ++ax) f *= ((k >> ax) & 1) ? t[ax] : u[ax];
+        phi[k] = f;
+    }
 }
 
 // The cells' corner functions on the packed layout, m = 2^d d right-hand sides (r = k d + i:
@@ -569,45 +589,53 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Restriction, per cell (one wave each): cpart[c][k][i] = sum over the cell's primary nodes of
-// phi_k v_i
+// Restriction, one workgroup per cell: cpart[c][k][i] = sum over the cell's primary nodes of
+// phi_k v_i (per-thread sums, wave sums by a fixed shuffle tree, then the 4 waves in order)
 template <int D>
 __global__ void __launch_bounds__(NB) k_cr_restrict(int nel, int nn, int64_t ncells, const int32_t *__restrict__ l2g,
                                                     const uint8_t *__restrict__ prim, const double *__restrict__ v,
                                                     double *__restrict__ cpart, const MrCtl *__restrict__ ctl)
 {
-    constexpr int NCO = 1 << D;
+    constexpr int NCO = 1 << D, NA = NCO * D, NWV = NB / LAT_WAVE;
+    __shared__ double sh[NWV][NA];
     if (ctl->done) return;
-    const int64_t c = (int64_t)blockIdx.x * (NB / LAT_WAVE) + (threadIdx.x >> 6);
-    if (c >= ncells) return;
-    const int l = threadIdx.x & 63;
+    const int64_t c = blockIdx.x;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nloc = D == 2 ? nn * nn : nn * nn * nn;
+    const double h = 1.0 / nel;
     double acc[NCO][D];
 #pragma unroll
     for (int k = 0; k < NCO; ++k)
 #pragma unroll
         for (int i = 0; i < D; ++i) acc[k][i] = 0.0;
-    for (int a = l; a < nloc; a += LAT_WAVE) {
+    for (int a = threadIdx.x; a < nloc; a += NB) {
         if (!prim[c * nloc + a]) continue;
         const int64_t G = l2g[c * nloc + a];
         const int ic[3] = {a % nn, (a / nn) % nn, a / (nn * nn)};
+        double phi[NCO];
+        corner_phis<D>(h, ic, phi);
         double vi[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) vi[i] = v[G * D + i];
 #pragma unroll
-        for (int k = 0; k < NCO; ++k) {
-            const double f = corner_phi(k, D, nel, ic);
+        for (int k = 0; k < NCO; ++k)
 #pragma unroll
-            for (int i = 0; i < D; ++i) acc[k][i] = fma(f, vi[i], acc[k][i]);
-        }
+            for (int i = 0; i < D; ++i) acc[k][i] = fma(phi[k], vi[i], acc[k][i]);
     }
 #pragma unroll
     for (int k = 0; k < NCO; ++k)
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const double s = wave_sum(acc[k][i]);
-            if (l == 0) cpart[(c * NCO + k) * D + i] = s;
+            if (l == 0) sh[wv][k * D + i] = s;
         }
+    __syncthreads();
+    if (threadIdx.x < NA) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) s += sh[w][threadIdx.x];
+        cpart[c * NA + threadIdx.x] = s;
+    }
 }
 
 // rc[C d + i] = sum over the cells around corner C (ascending id) of their partials
@@ -640,19 +668,35 @@ __global__ void __launch_bounds__(NB) k_cr_sum(NGrid g, int ncd, const double *_
     rc[R] = acc;
 }
 
-// ec = K0^-1 rc, one wave per row
+// ec = K0^-1 rc, one workgroup per row (four independent partial sums per thread, wave sums by a
+// fixed shuffle tree, the waves combined in order)
 __global__ void __launch_bounds__(NB) k_cr_gemv(int ncd, const double *__restrict__ A, const double *__restrict__ x,
                                                 double *__restrict__ y, const MrCtl *__restrict__ ctl)
 {
+    constexpr int NWV = NB / LAT_WAVE;
+    __shared__ double sh[NWV];
     if (ctl->done) return;
-    const int64_t R = (int64_t)blockIdx.x * (NB / LAT_WAVE) + (threadIdx.x >> 6);
-    if (R >= ncd) return;
-    const int l = threadIdx.x & 63;
+    const int64_t R = blockIdx.x;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double *row = A + R * ncd;
-    double acc = 0.0;
-    for (int c = l; c < ncd; c += LAT_WAVE) acc = fma(row[c], x[c], acc);
-    acc = wave_sum(acc);
-    if (l == 0) y[R] = acc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int c = threadIdx.x;
+    for (; c + 3 * NB < ncd; c += 4 * NB) {
+        a0 = fma(row[c], x[c], a0);
+        a1 = fma(row[c + NB], x[c + NB], a1);
+        a2 = fma(row[c + 2 * NB], x[c + 2 * NB], a2);
+        a3 = fma(row[c + 3 * NB], x[c + 3 * NB], a3);
+    }
+    for (; c < ncd; c += NB) a0 = fma(row[c], x[c], a0);
+    const double s = wave_sum((a0 + a1) + (a2 + a3));
+    if (l == 0) sh[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) t += sh[w];
+        y[R] = t;
+    }
 }
 
 // z += P ec on the free components; partial <z, v>
@@ -671,12 +715,13 @@ __global__ void __launch_bounds__(NB) k_cr_prolong(int nel, int cs0, int cs1, in
         const int32_t base = cbase[G];
         const uint32_t lc = cloc[G];
         const int ic[3] = {(int)(lc & 1023u), (int)((lc >> 10) & 1023u), (int)((lc >> 20) & 1023u)};
-        double add[D];
+        double add[D], phi[1 << D];
+        corner_phis<D>(1.0 / nel, ic, phi);
 #pragma unroll
         for (int i = 0; i < D; ++i) add[i] = 0.0;
 #pragma unroll
         for (int k = 0; k < (1 << D); ++k) {
-            const double f = corner_phi(k, D, nel, ic);
+            const double f = phi[k];
             const int C = base + (k & 1) + cs0 * (((k >> 1) & 1) + cs1 * ((k >> 2) & 1));
 #pragma unroll
             for (int i = 0; i < D; ++i) add[i] = fma(f, ec[(int64_t)C * D + i], add[i]);
@@ -947,9 +992,9 @@ lat_status coarse_setup(const lat_plan *P, MrWork &w, const double *K, int n_r, 
 lat_status coarse_apply(const lat_plan *P, MrWork &w, const uint8_t *fixed, const double *v, double *z, hipStream_t s)
 {
     const NGrid g = make_ngrid(P);
-    const unsigned nbc = (unsigned)lat_cdiv(P->ncells, NB / LAT_WAVE);
+    const unsigned nbc = (unsigned)P->ncells;
     const unsigned nbr = (unsigned)lat_cdiv(w.ncd, NB);
-    const unsigned nbg = (unsigned)lat_cdiv(w.ncd, NB / LAT_WAVE);
+    const unsigned nbg = (unsigned)w.ncd;
     const int cs0 = P->ncell[0] + 1, cs1 = P->ncell[1] + 1;
     if (P->dim == 2)
         hipLaunchKernelGGL(k_cr_restrict<2>, dim3(nbc), dim3(NB), 0, s, P->nel, P->nn, P->ncells, P->l2g, w.prim, v,
