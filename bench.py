@@ -108,6 +108,10 @@ def main():
     ap.add_argument("--solve-tol", type=float, default=1e-8, help="--newton: tangent-solve tolerance")
     ap.add_argument("--solve-maxit", type=int, default=200000, help="--newton: tangent-solve iteration limit")
     ap.add_argument("--snap-rule", choices=["full", "reduced"], default="full", help="--newton: snapshot quadrature")
+    ap.add_argument("--radius", type=float, default=None, help="--newton: one hole radius for every cell")
+    ap.add_argument("--matvec", choices=["stencils", "rom"], default="stencils",
+                    help="--newton: ROM tangent products from stencils formed once per iteration, or ROM applies")
+    ap.add_argument("--precond", choices=["two-level", "diag"], default="two-level", help="--newton: preconditioner")
     ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
                     help="--newton: ROM tangent, or every cell's own tangent (the standard method)")
     args = ap.parse_args()
@@ -365,6 +369,8 @@ def newton_main(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cfg = L.config(args.workload)
+    if args.radius is not None:
+        cfg = cfg.with_(radius=(args.radius, args.radius), name=cfg.name + f"_r{args.radius:g}")
     case = L.LoadCase("compress_shear", args.strain, args.shear, args.n_inc)
     log("newton workload", cfg.name, case)
     keep = L.make_keep(cfg)
@@ -382,7 +388,8 @@ def newton_main(args):
     st, recs = P.newton_solve(mu_t, lam_t, fixed, ubar, u, n_inc=args.n_inc, max_newton=args.max_newton,
                               cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=args.solve_maxit,
                               cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0,
-                              snap_rule=B.RULE_REDUCED if args.snap_rule == "reduced" else B.RULE_FULL)
+                              snap_rule=B.RULE_REDUCED if args.snap_rule == "reduced" else B.RULE_FULL,
+                              matvec=1 if args.matvec == "rom" else 0, precond=0 if args.precond == "diag" else 1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tot = {k: float(sum(r[k] for r in recs)) for k in ("t_init_ms", "t_solve_ms", "t_eval_ms")}
@@ -392,9 +399,21 @@ def newton_main(args):
     tp = [r["t_product_us"] for r in recs if r["t_product_us"] > 0]
     t_mv = float(np.mean(tp)) * 1e-6 if tp else float("nan")
     lane_nodes = int(nact.sum().item())
-    mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
+    if args.matvec == "rom" and args.tangent == "rom":
+        # ROM apply: X read + Y written, the principal stack and the coefficients
+        nr_avg = float(np.mean([r["n_r"] for r in recs])) if recs else 0.0
+        mv_bytes = 16.0 * lane_nodes * cfg.dim + 8.0 * (P.nloc * P.E + P.ncells) * nr_avg
+    else:
+        # per-cell stencils (8 B x E per active lane-node) + X read + Y written
+        mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
     lane_nodes = int(nact.sum().item())
-    mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
+    if args.matvec == "rom" and args.tangent == "rom":
+        # ROM apply: X read + Y written, the principal stack and the coefficients
+        nr_avg = float(np.mean([r["n_r"] for r in recs])) if recs else 0.0
+        mv_bytes = 16.0 * lane_nodes * cfg.dim + 8.0 * (P.nloc * P.E + P.ncells) * nr_avg
+    else:
+        # per-cell stencils (8 B x E per active lane-node) + X read + Y written
+        mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle Newton iterations on an 8 x 8-cell sample) ...")
@@ -413,10 +432,13 @@ def newton_main(args):
                    "tangent": args.tangent, "snap_rule": args.snap_rule, "rb_tol": args.rb_tol, "cap": args.cap,
                    "newton_tol": 1e-6,
                    "armijo": [0.5, 1e-4],
-                   "tangent_solve": {"method": "MINRES, |diag| preconditioner", "tol": args.solve_tol}},
+                   "tangent_solve": {"method": "MINRES", "preconditioner": args.precond, "products": args.matvec,
+                                     "tol": args.solve_tol}},
         "roofline": {"bound": "hbm", "achieved": round(mv_bytes / t_mv / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mv_bytes / t_mv / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": ("k_apply (per-cell stencil apply, one right-hand side) in every MINRES iteration"
+                     "kernel": ("k_apply (ROM apply forming the stencils, one right-hand side) in every MINRES "
+                                "iteration" if args.matvec == "rom" and args.tangent == "rom" else
+                                "k_apply (per-cell stencil apply, one right-hand side) in every MINRES iteration"
                                 + (" (standard method: the cells' own stencils)" if args.tangent == "full" else
                                    " (combined ROM stencils)")),
                      "algorithmic_bytes_per_launch": int(mv_bytes), "us_per_launch": round(t_mv * 1e6, 2)},
