@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD_INDEX = 1
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TF = 78.6
 LOWP_REFINE = 2.0 ** -16       # bf16 slice products up to level 1 (two levels)
 
 
@@ -399,17 +400,23 @@ def newton_main(args):
     tp = [r["t_product_us"] for r in recs if r["t_product_us"] > 0]
     t_mv = float(np.mean(tp)) * 1e-6 if tp else float("nan")
     lane_nodes = int(nact.sum().item())
-    if args.matvec == "rom" and args.tangent == "rom":
-        # ROM apply: X read + Y written, the principal stack and the coefficients
+    rom_products = args.matvec == "rom" and args.tangent == "rom"
+    if rom_products:
+        # ROM apply forming the stencils on the matrix cores: 2 E N_r flops per packed lane-node
+        # (combination) + 2 E per active lane-node (apply), against the FP64 matrix-core peak
         nr_avg = float(np.mean([r["n_r"] for r in recs])) if recs else 0.0
+        mv_flops = 2.0 * P.E * nr_avg * P.npacked * 64 + 2.0 * P.E * lane_nodes
         mv_bytes = 16.0 * lane_nodes * cfg.dim + 8.0 * (P.nloc * P.E + P.ncells) * nr_avg
     else:
         # per-cell stencils (8 B x E per active lane-node) + X read + Y written
         mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
     lane_nodes = int(nact.sum().item())
-    if args.matvec == "rom" and args.tangent == "rom":
-        # ROM apply: X read + Y written, the principal stack and the coefficients
+    rom_products = args.matvec == "rom" and args.tangent == "rom"
+    if rom_products:
+        # ROM apply forming the stencils on the matrix cores: 2 E N_r flops per packed lane-node
+        # (combination) + 2 E per active lane-node (apply), against the FP64 matrix-core peak
         nr_avg = float(np.mean([r["n_r"] for r in recs])) if recs else 0.0
+        mv_flops = 2.0 * P.E * nr_avg * P.npacked * 64 + 2.0 * P.E * lane_nodes
         mv_bytes = 16.0 * lane_nodes * cfg.dim + 8.0 * (P.nloc * P.E + P.ncells) * nr_avg
     else:
         # per-cell stencils (8 B x E per active lane-node) + X read + Y written
@@ -434,11 +441,16 @@ def newton_main(args):
                    "armijo": [0.5, 1e-4],
                    "tangent_solve": {"method": "MINRES", "preconditioner": args.precond, "products": args.matvec,
                                      "tol": args.solve_tol}},
-        "roofline": {"bound": "hbm", "achieved": round(mv_bytes / t_mv / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(mv_bytes / t_mv / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": ("k_apply (ROM apply forming the stencils, one right-hand side) in every MINRES "
-                                "iteration" if args.matvec == "rom" and args.tangent == "rom" else
-                                "k_apply (per-cell stencil apply, one right-hand side) in every MINRES iteration"
+        "roofline": ({"bound": "mfma", "achieved": round(mv_flops / t_mv / 1e12, 2), "peak": FP64_MFMA_PEAK_TF,
+                      "unit": "TFLOP/s", "frac": round(mv_flops / t_mv / 1e12 / FP64_MFMA_PEAK_TF, 4),
+                      "algorithmic_flops_per_launch": int(mv_flops)} if rom_products else
+                     {"bound": "hbm", "achieved": round(mv_bytes / t_mv / 1e9, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(mv_bytes / t_mv / 1e9 / HBM_PEAK_GBS, 4)}) | {"traffic": None,
+                     "kernel": ((("k_apply2d_rw<1,NR,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
+                                 + " (ROM apply, one right-hand side, stencils formed on the matrix cores) in every "
+                                 "MINRES iteration") if rom_products else
+                                ("k_apply<2,1,8,2>" if cfg.dim == 2 else "k_apply<3,1,8,2>")
+                                + " (per-cell stencil apply, one right-hand side) in every MINRES iteration"
                                 + (" (standard method: the cells' own stencils)" if args.tangent == "full" else
                                    " (combined ROM stencils)")),
                      "algorithmic_bytes_per_launch": int(mv_bytes), "us_per_launch": round(t_mv * 1e6, 2)},

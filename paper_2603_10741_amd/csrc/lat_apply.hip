@@ -169,6 +169,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int64_t p = (int64_t)g * LAT_WAVE + l;
     const int r0 = w * MW;
+    const bool act = r0 < m;                             // false for the waves past m (m < 8)
     const int e0 = (w * E) / NW, e1 = ((w + 1) * E) / NW;   // this wave's share of the entries
     const int32_t *ui = uidx + (int64_t)g * nloc;
     const int gq = goff[g];
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     };
     double xw[4][3][2][MW];            // [slot][row y-1..y+1][dof][rhs]; column c lives in slot (c+1) % 4
     auto load_col = [&](double (&col)[3][2][MW], int xc) {
+        if (!act) return;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
             const int yy = y + dy - 1;
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
         load_col(xw[sf], x + 2);
         __syncthreads();
         // (3) apply
-        if (qi >= 0) {
+        if (qi >= 0 && act) {
             double acc[2][MW];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -1069,7 +1071,11 @@ lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, cons
         A.alpha_il = P->alpha_il;
     }
     const int nwaves = P->ngroups * A.chunks_per_group;
-    if (P->dim == 2 && (m == 8 || m == 16) && P->nn >= 3) return launch_rowwalk(P, A, mode, s);
+    // the row walk: m in {8, 16}; for the ROM modes also m in {1, 2, 4} (waves past m idle in the
+    // apply; the combination on the matrix cores is what the walk buys there), while the per-cell
+    // stencil apply with so few right-hand sides streams faster in the per-group kernel
+    if (P->dim == 2 && P->nn >= 3 && (m == 8 || m == 16 || (mode != 2 && (m == 1 || m == 2 || m == 4))))
+        return launch_rowwalk(P, A, mode, s);
     if (P->dim == 2) {
         if (mode == 0) return launch_apply<2, 0>(A, nwaves, s);
         if (mode == 1) return launch_apply<2, 1>(A, nwaves, s);

@@ -95,8 +95,10 @@ def test_empty_basis_gives_zero():
         assert torch.count_nonzero(Y).item() == 0
 
 
-@pytest.mark.parametrize("m", [1, 3, 5])
-def test_odd_rhs_counts(m):
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
+def test_small_and_odd_rhs_counts(m):
+    # m in {1, 2, 4}: the ROM applies run the 2D row walk with idle waves past m, the plain apply the
+    # per-group kernel; 3 and 5 the per-group kernels throughout
     cfg = _sub3()
     c = Case(cfg, m=m)
     P = c.P
