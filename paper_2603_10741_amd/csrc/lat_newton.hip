@@ -3,17 +3,19 @@
 //
 // K~ is symmetric (every principal tangent is the Hessian of a stored energy) but need not be
 // definite: the tangent of a pre-stressed lattice loses definiteness near buckling, and the
-// Newton step is still defined there.  MINRES (Lanczos on K~ with the preconditioner
-// D = |diag K~|, the tridiagonal factor reduced by Givens rotations) minimises ||b - K~ x||_{D^-1}
-// over the Krylov space for any symmetric non-singular K~, so the step equals that of a direct
-// solve up to the tolerance.
+// Newton step is still defined there.  MINRES (Lanczos on K~ with an SPD preconditioner M, the
+// tridiagonal factor reduced by Givens rotations) minimises ||b - K~ x||_{M^-1} over the Krylov
+// space for any symmetric non-singular K~, so the step equals that of a direct solve up to the
+// tolerance.  M^-1 is D^-1 (D = |diag K~|) or D^-1 + P K0^-1 P^T with a coarse space of the
+// cell-corner nodes (two levels).
 //
-// A product K~ z is one ROM apply with a single right-hand side on the packed layout, followed
-// by an owner-ordered assembly onto the global nodes that also forms the partial sums of z.K~z.
-// The Lanczos and rotation scalars live in a small device control block and are finalised by
-// single-workgroup kernels, so the host only reads the control block every `check` iterations.
-// Every reduction has a fixed order (per-block LDS trees, then one block summing the block
-// partials in index order): a solve is reproducible bit for bit on a given plan.
+// A product K~ z is one per-cell apply with a single right-hand side on the packed layout (the
+// combined stencils formed once, or the ROM apply forming them), followed by an owner-ordered
+// assembly onto the global nodes that also forms the partial sums of z.K~z.  The Lanczos and
+// rotation scalars live in a small device control block and are finalised by single-workgroup
+// kernels, so the host only reads the control block every `check` iterations.  Every reduction
+// has a fixed order (per-block LDS trees or shuffle trees, then the block partials in index
+// order): a solve is reproducible bit for bit on a given plan.
 #include <chrono>
 #include <cmath>
 #include <mutex>
@@ -182,7 +184,8 @@ __global__ void __launch_bounds__(NB) k_jacobi(NGrid g, int64_t nglobal, const i
 }
 
 // The same from per-cell stencils in the packed layout of lat_apply_plain
-__global__ void __launch_bounds__(NB) k_jacobi_ops(NGrid g, PackMap pm, int64_t nglobal, const int64_t *__restrict__ g2bg,
+__global__ void __launch_bounds__(NB) k_jacobi_ops(NGrid g, PackMap pm, int64_t nglobal,
+                                                   const int64_t *__restrict__ g2bg,
                                                    const int32_t *__restrict__ l2g, const double *__restrict__ ops,
                                                    int E, const uint8_t *__restrict__ fixed, double *__restrict__ dinv)
 {
@@ -207,8 +210,9 @@ __global__ void __launch_bounds__(NB) k_jacobi_ops(NGrid g, PackMap pm, int64_t 
 // v1 = b (free), z1 = D^-1 v1; x = w0 = w1 = v0 = 0; partial <z1, v1>
 __global__ void __launch_bounds__(NB) k_mr_init(int64_t n, const uint8_t *__restrict__ fixed,
                                                 const double *__restrict__ dinv, const double *__restrict__ b,
-                                                double *__restrict__ x, double *__restrict__ v0, double *__restrict__ v1,
-                                                double *__restrict__ z1, double *__restrict__ w0, double *__restrict__ w1,
+                                                double *__restrict__ x, double *__restrict__ v0,
+                                                double *__restrict__ v1, double *__restrict__ z1,
+                                                double *__restrict__ w0, double *__restrict__ w1,
                                                 double *__restrict__ part)
 {
     __shared__ double sh[NB];
@@ -566,7 +570,8 @@ __global__ void __launch_bounds__(NB) k_coarse_assemble(NGrid g, int ncd, const 
                 const int64_t cell = cc[0] + (int64_t)g.ncell[0] * (cc[1] + (int64_t)g.ncell[1] * cc[2]);
                 const double *ks = K0s + ((int64_t)cell * m + bits * d + i1) * m;
                 for (int k2 = 0; k2 < nco; ++k2) {
-                    const int C2 = (cc[0] + (k2 & 1)) + cs0 * ((cc[1] + ((k2 >> 1) & 1)) + cs1 * (cc[2] + ((k2 >> 2) & 1)));
+                    const int C2 = (cc[0] + (k2 & 1)) +
+                                   cs0 * ((cc[1] + ((k2 >> 1) & 1)) + cs1 * (cc[2] + ((k2 >> 2) & 1)));
                     for (int i2 = 0; i2 < d; ++i2) row[C2 * d + i2] += ks[k2 * d + i2];
                 }
             }
@@ -950,8 +955,11 @@ lat_status coarse_operator(const lat_plan *P, MrWork &w, const double *K, int n_
     if (ops) NCHK(lat_apply_plain(P, ops, w.Xc, w.Yc, w.mc, s));
     else NCHK(lat_apply_combo(P, K, n_r, alpha, w.Xc, w.Yc, w.mc, LAT_F64, 0.0, 0, s));
     const dim3 cg((unsigned)P->ngroups, (unsigned)w.mc);
-    if (w.mc == 8) hipLaunchKernelGGL(k_coarse_cellmat<8>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc, w.K0s);
-    else hipLaunchKernelGGL(k_coarse_cellmat<24>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc, w.K0s);
+    if (w.mc == 8)
+        hipLaunchKernelGGL(k_coarse_cellmat<8>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc, w.K0s);
+    else
+        hipLaunchKernelGGL(k_coarse_cellmat<24>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc,
+                           w.K0s);
     const int64_t nn2 = (int64_t)w.ncd * w.ncd;
     hipLaunchKernelGGL(k_fill, dim3(vec_blocks(nn2)), dim3(NB), 0, s, nn2, 0.0, w.K0);
     hipLaunchKernelGGL(k_coarse_assemble, dim3((unsigned)lat_cdiv(w.ncd, NB)), dim3(NB), 0, s, make_ngrid(P), w.ncd,
@@ -1167,7 +1175,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     if (!P || !mu || !lam || !fixed || !ubar || !o || !u) return LAT_E_ARG;
     if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
         o->cg_maxit < 1 || o->cg_check < 1 || (o->matvec != 0 && o->matvec != 1) ||
-        (o->tangent != 0 && o->tangent != 1) || (o->precond != 0 && o->precond != 1) || (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
+        (o->tangent != 0 && o->tangent != 1) || (o->precond != 0 && o->precond != 1) ||
+        (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
         !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
         !(o->armijo_c >= 0.0 && o->armijo_c < 1.0) || !(o->cg_tol > 0.0) || max_records < 0 ||
         (max_records > 0 && !records))
