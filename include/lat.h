@@ -70,7 +70,9 @@ typedef enum {
     LAT_E_SINGULAR = 9    /* the tangent solve met an operator singular on its Krylov space */
 } lat_status;
 
-typedef enum { LAT_RULE_FULL = 0, LAT_RULE_REDUCED = 1 } lat_rule;   /* 2^d Gauss points / 1 point */
+/* snapshot data: the assembled cell tangent with 2^d Gauss points / with 1 point per element, or the
+ * material tangent dP/dF at the centre of every kept element (see lat_residual_tangent) */
+typedef enum { LAT_RULE_FULL = 0, LAT_RULE_REDUCED = 1, LAT_RULE_MATERIAL = 2 } lat_rule;
 typedef enum { LAT_F64 = 0, LAT_F32 = 1, LAT_BF16 = 2 } lat_prec;
 
 typedef struct lat_plan lat_plan;
@@ -117,7 +119,11 @@ lat_status lat_dofmap(const lat_plan *plan, int32_t *l2g, int32_t *n_active, int
  *   f_int     CIL(d)   internal force f^{int,s} (eq. internalloadvec), cell-local, full rule
  *   energy    [N_s]    stored energy per cell (canonical order), full rule
  *   snap      CIL(E)   snapshot matrix T: the assembled cell tangent in stencil layout
- *                      (eq. snapshots), quadrature `snap_rule`
+ *                      (eq. snapshots), quadrature `snap_rule` (FULL or REDUCED); or, with
+ *                      LAT_RULE_MATERIAL, the material tangent A = dP/dF at the centre of every
+ *                      kept element (the Remark on snapshots of Sec. 3.2.2), A_iJkL of element e in
+ *                      row (e d^2 + i d + J) d^2 + k d + L, zeros for elements not kept and for the
+ *                      rows past n^d d^4
  *   plain_ops packed   every cell's full-rule tangent in stencil form (for lat_apply_plain)
  * Errors J <= 0 / non-finite go to dev_status. */
 lat_status lat_residual_tangent(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,

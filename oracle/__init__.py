@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "liblat_oracle.so")
 _lib = None
 
 OK, E_INVERTED, E_NONFINITE, W_CAP = 0, 5, 6, 7
-RULE_FULL, RULE_REDUCED = 0, 1
+RULE_FULL, RULE_REDUCED, RULE_MATERIAL = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -237,3 +237,39 @@ def alpha_ls_adjoint(T_S, T_all, alpha, alpha_bar):
     rho = T_all - alpha @ T_S.T                          # [N_s][n_snap]
     TbarS = rho.T @ V - (T_S @ V.T) @ alpha              # [n_snap][n_r]
     return tbar, TbarS
+
+
+# ----------------------------------------------------------------------------- f3: material snapshots
+def material_snapshots(dim, nel, keep, u_loc, mu, lam):
+    """Snapshots made of the material tangent A = dP/dF (the pulled-back fourth-order tensor of the
+    Remark on snapshots in Sec. 3.2.2) at the centre of every kept element, [N_s][n_snap]:
+    row (e d^2 + i d + J) d^2 + k d + L holds A_iJkL of element e; rows of elements that are not
+    kept, and rows past n^d d^4, are zero.  2D is plane strain (F_33 = 1).
+    Returns (T, status) with status E_INVERTED when J <= 0 at some kept centre."""
+    keep = np.asarray(keep, np.uint8)
+    Ns = keep.shape[0]
+    nn = nel + 1
+    h = 1.0 / nel
+    d4 = dim ** 4
+    T = np.zeros((Ns, n_snap(dim, nel)))
+    status = OK
+    corners = [[(c >> ax) & 1 for ax in range(dim)] for c in range(2 ** dim)]
+    for s in range(Ns):
+        mu_s = float(np.broadcast_to(mu, (Ns,))[s]); lam_s = float(np.broadcast_to(lam, (Ns,))[s])
+        for e in range(nel ** dim):
+            if not keep[s, e]:
+                continue
+            ec = [(e // nel ** ax) % nel for ax in range(dim)]
+            F = np.eye(3)
+            for cb in corners:
+                a = sum((ec[ax] + cb[ax]) * nn ** ax for ax in range(dim))
+                # gradient of the Q1 shape function of corner cb at the element centre
+                g = np.array([(1.0 if cb[ax] else -1.0) / h * 0.5 ** (dim - 1) for ax in range(dim)])
+                F[:dim, :dim] += np.outer(u_loc[s, a, :dim], g)
+            try:
+                _, _, A = neo_hooke(F, mu_s, lam_s)
+            except ValueError:
+                status = E_INVERTED
+                continue
+            T[s, e * d4:(e + 1) * d4] = A[:dim, :dim, :dim, :dim].reshape(-1)
+    return T, status

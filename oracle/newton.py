@@ -23,7 +23,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import OK, RULE_FULL, assemble, cells_eval, dofmap, gather_local, greedy
+from . import OK, RULE_FULL, RULE_MATERIAL, assemble, cells_eval, dofmap, gather_local, greedy, material_snapshots
 
 NOCONV = 8
 
@@ -110,13 +110,16 @@ class Problem:
         """(r masked [n_global][d], T [N_s][n_snap] or None, status, energy per cell or None).
 
         The residual and energy always use the full rule (the residual is not reduced, Sec. 4);
-        the snapshots T use the problem's snapshot rule."""
+        the snapshots T use the problem's snapshot rule (full, one-point, or the material tangent
+        at the kept elements' centres)."""
         ul = gather_local(u, self.l2g)
         full = self.rule == RULE_FULL
         ev = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=RULE_FULL, want_f=True,
                         want_energy=want_energy, want_T=want_T and full)
         T = ev["T"]
-        if want_T and not full:
+        if want_T and self.rule == RULE_MATERIAL:
+            T, _ = material_snapshots(self.dim, self.nel, self.keep, ul, self.mu, self.lam)
+        elif want_T and not full:
             T = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=self.rule, want_f=False,
                            want_energy=False, want_T=True)["T"]
         r = assemble(ev["f"], self.l2g, self.ng) - lf * self.fext

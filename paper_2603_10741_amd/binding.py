@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("LAT_LIBRARY") or os.path.join(_HERE, "liblat.so")
 
 (LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP, LAT_E_NOCONV,
  LAT_E_SINGULAR) = range(10)
-RULE_FULL, RULE_REDUCED = 0, 1
+RULE_FULL, RULE_REDUCED, RULE_MATERIAL = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 INFO_KEYS = ["dim", "nel", "ncells", "nloc", "nelem", "E", "nsnap", "ld", "ngroups", "npacked", "nglobal", "cap"]
 

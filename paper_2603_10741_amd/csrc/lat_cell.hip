@@ -519,6 +519,95 @@ CellArgs base_args(const lat_plan *P)
     return A;
 }
 
+// Material-tangent snapshots (the Remark on snapshots of Sec. 3.2.2: the cell-to-cell differences
+// of the tangent sit in the pulled-back constitutive tensor): A = dP/dF at the centre of every kept
+// element, A_iJkL = mu d_ik d_JL + (mu - lam ln J) F^-1_Li F^-1_Jk + lam F^-1_Ji F^-1_Lk (plane strain
+// in 2D), in rows (e d^2 + i d + J) d^2 + k d + L of CIL(E); elements that are not kept give zeros.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_material_snap(int nel, int64_t ld, const uint8_t *__restrict__ keep_il,
+                                                       const int32_t *__restrict__ perm,
+                                                       const double *__restrict__ u_cil, const double *__restrict__ mu,
+                                                       const double *__restrict__ lam, double *__restrict__ T,
+                                                       int32_t *st)
+{
+    constexpr int D4 = DIM * DIM * DIM * DIM;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int e = blockIdx.y;
+    if (p >= ld) return;
+    const int c = perm[p];
+    double out[D4];
+#pragma unroll
+    for (int t = 0; t < D4; ++t) out[t] = 0.0;
+    if (c >= 0 && keep_il[(int64_t)e * ld + p]) {
+        const int nn = nel + 1;
+        const int ec[3] = {e % nel, (e / nel) % nel, e / (nel * nel)};
+        const double g0 = nel * (DIM == 2 ? 0.5 : 0.25);   // |dN/dX| of a corner function at the centre
+        double F[DIM][DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int J = 0; J < DIM; ++J) F[i][J] = i == J ? 1.0 : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < (1 << DIM); ++cb) {
+            int a = 0, str = 1;
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                a += (ec[ax] + ((cb >> ax) & 1)) * str;
+                str *= nn;
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                const double ua = u_cil[((int64_t)a * DIM + i) * ld + p];
+#pragma unroll
+                for (int J = 0; J < DIM; ++J) F[i][J] = fma(ua, ((cb >> J) & 1) ? g0 : -g0, F[i][J]);
+            }
+        }
+        double Fi[DIM][DIM], det;
+        if (DIM == 2) {
+            det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+            Fi[0][0] = F[1][1] / det; Fi[0][1] = -F[0][1] / det;
+            Fi[1][0] = -F[1][0] / det; Fi[1][1] = F[0][0] / det;
+        } else {
+            const double c00 = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+            const double c01 = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+            const double c02 = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+            det = F[0][0] * c00 + F[0][1] * c01 + F[0][2] * c02;
+            const double id = 1.0 / det;
+            Fi[0][0] = c00 * id; Fi[1][0] = c01 * id; Fi[2][0] = c02 * id;
+            Fi[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) * id;
+            Fi[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) * id;
+            Fi[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) * id;
+            Fi[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) * id;
+            Fi[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) * id;
+            Fi[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) * id;
+        }
+        if (!(det > 0.0) || !isfinite(det)) {
+            lat_flag(st, isfinite(det) ? LAT_E_INVERTED : LAT_E_NONFINITE, c);
+        } else {
+            const double m = mu[c], l = lam[c], ml = m - l * log(det);
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                for (int J = 0; J < DIM; ++J)
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+                        for (int L = 0; L < DIM; ++L)
+                            out[((i * DIM + J) * DIM + k) * DIM + L] = (i == k && J == L ? m : 0.0) +
+                                                                       ml * Fi[L][i] * Fi[J][k] +
+                                                                       l * Fi[J][i] * Fi[L][k];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < D4; ++t) T[((int64_t)e * D4 + t) * ld + p] = out[t];
+}
+
+__global__ void k_zero_rows(int64_t n, double *__restrict__ y)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        y[j] = 0.0;
+}
+
 lat_status gather_u(const lat_plan *P, const double *u_global, int32_t *st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gather_u, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc), dim3(256), 0, s, P->dim,
@@ -536,7 +625,7 @@ lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const
                                 int32_t *dev_status, hipStream_t stream)
 {
     if (!P || !u_global || !mu || !lam) return LAT_E_ARG;
-    if (snap_rule != LAT_RULE_FULL && snap_rule != LAT_RULE_REDUCED) return LAT_E_ARG;
+    if (snap_rule != LAT_RULE_FULL && snap_rule != LAT_RULE_REDUCED && snap_rule != LAT_RULE_MATERIAL) return LAT_E_ARG;
     lat_status st = gather_u(P, u_global, dev_status, stream);
     if (st != LAT_OK) return st;
     CellArgs A = base_args(P);
@@ -553,6 +642,22 @@ lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const
         CellArgs B = base_args(P);
         B.mu = mu; B.lam = lam; B.matmode = 0; B.st = dev_status; B.T = snap;
         if ((st = dispatch_cell<false>(P, LAT_RULE_REDUCED, B, stream)) != LAT_OK) return st;
+    }
+    if (snap && snap_rule == LAT_RULE_MATERIAL) {
+        const int d4 = P->dim * P->dim * P->dim * P->dim;
+        const int64_t rows = (int64_t)P->nelem * d4;
+        const dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nelem);
+        if (P->dim == 2)
+            hipLaunchKernelGGL(k_material_snap<2>, grid, dim3(256), 0, stream, P->nel, P->ld, P->keep_il, P->perm,
+                               P->u_cil, mu, lam, snap, dev_status);
+        else
+            hipLaunchKernelGGL(k_material_snap<3>, grid, dim3(256), 0, stream, P->nel, P->ld, P->keep_il, P->perm,
+                               P->u_cil, mu, lam, snap, dev_status);
+        const int64_t rest = (P->nsnap - rows) * P->ld;
+        if (rest > 0)
+            hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)std::min<int64_t>(lat_cdiv(rest, 256), 4096)), dim3(256), 0,
+                               stream, rest, snap + rows * P->ld);
+        LAT_LAUNCH_CHECK();
     }
     if (energy) {
         if ((st = lat_tree_reduce(P->w_part, P->nloc, P->ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;

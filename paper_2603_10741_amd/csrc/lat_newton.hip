@@ -1176,7 +1176,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
         o->cg_maxit < 1 || o->cg_check < 1 || (o->matvec != 0 && o->matvec != 1) ||
         (o->tangent != 0 && o->tangent != 1) || (o->precond != 0 && o->precond != 1) ||
-        (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED) ||
+        (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED && o->snap_rule != LAT_RULE_MATERIAL) ||
         !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
         !(o->armijo_c >= 0.0 && o->armijo_c < 1.0) || !(o->cg_tol > 0.0) || max_records < 0 ||
         (max_records > 0 && !records))

@@ -158,7 +158,7 @@ def test_rom_solve_indefinite_matches_direct_solve(graded):
     assert rel(x, xo) <= 1e-5
 
 
-@pytest.mark.parametrize("rule", [O.RULE_FULL, O.RULE_REDUCED])
+@pytest.mark.parametrize("rule", [O.RULE_FULL, O.RULE_REDUCED, O.RULE_MATERIAL])
 def test_newton_matches_oracle(graded, rule):
     nc = graded
     u = nc.zeros_u()
@@ -332,3 +332,23 @@ def test_rom_solve_two_level(graded):
         assert rel(x.reshape(-1, cfg.dim).cpu().numpy().ravel(), xo) <= 1e-6
         its[pc] = it
     assert its[1] < its[0]
+
+
+@pytest.mark.parametrize("which", ["hole", "bcc"])
+def test_material_snapshots_match_oracle(which):
+    # the material-tangent snapshots (snap_rule MATERIAL) and the greedy on them
+    from gpu_common import Case
+    cfg = L.config(0).with_(radius=(0.25, 0.35)) if which == "hole" else L.config(2).with_sub((2, 2, 2))
+    c = Case(cfg, m=1)
+    P = c.P
+    out = P.residual_tangent(c.ug, c.mu_t, c.lam_t, snap_rule=c.B.RULE_MATERIAL, f=False, energy=False, snap=True)
+    T = c.canon_T(out["snap"])
+    To, st = O.material_snapshots(cfg.dim, cfg.nel, c.keep, c.uloc, c.mu, c.lam)
+    assert st == O.OK
+    assert rel(T, To) <= 1e-13
+    code, _ = P.check_status(allow_cap=True)
+    assert code == c.B.LAT_OK
+    for tol in (1e-2, 1e-3):
+        g = P.select_principal(out["snap"] if tol == 1e-2 else c.to_cil_T(To), tol, keep_Z=False)
+        go = O.greedy(To, tol, cfg.cap, keep_Z=False)
+        assert int(g["n_r"].item()) == go["n_r"]

@@ -212,3 +212,41 @@ def test_coarse_operator_kills_translations_and_is_galerkin():
     rng = np.random.default_rng(3)
     a, c = rng.standard_normal(2 * nc), rng.standard_normal(2 * nc)
     assert abs(a @ K0 @ c - (P @ a) @ (K @ (P @ c))) <= 1e-11 * np.abs(K0).max() * 2 * nc
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_material_snapshots_at_rest_are_the_elasticity_tensor(dim):
+    # At u = 0 every kept element carries the isotropic tensor
+    # C_iJkL = lam d_iJ d_kL + mu (d_ik d_JL + d_iL d_Jk); elements that are not kept carry zeros.
+    cfg = L.config(0 if dim == 2 else 2).with_(ncell=(2, 1) if dim == 2 else (1, 1, 1), nel=4 if dim == 2 else 3)
+    keep = L.make_keep(cfg)
+    keep[0, 0] = 0
+    Ns = keep.shape[0]
+    mu, lam = 1.3, 7.0
+    T, st = O.material_snapshots(dim, cfg.nel, keep, np.zeros((Ns, (cfg.nel + 1) ** dim, dim)), mu, lam)
+    assert st == O.OK
+    I = np.eye(dim)
+    C = (lam * np.einsum("ij,kl->ijkl", I, I) + mu * (np.einsum("ik,jl->ijkl", I, I) + np.einsum("il,jk->ijkl", I, I)))
+    d4 = dim ** 4
+    for s in range(Ns):
+        for e in range(cfg.nel ** dim):
+            blk = T[s, e * d4:(e + 1) * d4]
+            np.testing.assert_allclose(blk, C.reshape(-1) if keep[s, e] else 0.0, rtol=0, atol=1e-13)
+    assert not T[:, cfg.nel ** dim * d4:].any()
+
+
+def test_material_snapshots_follow_a_homogeneous_stretch():
+    # An affine displacement gives the same F in every element: the snapshot block is the oracle's
+    # tangent at that F, and a cell with every element kept has N_s identical blocks.
+    cfg = L.config(0).with_(ncell=(1, 1), nel=4, radius=(0.0, 0.0))
+    keep = L.make_keep(cfg)
+    F = np.array([[1.05, 0.02], [-0.01, 0.93]])
+    nn = cfg.nel + 1
+    a = np.arange(nn * nn)
+    X = np.stack([a % nn, a // nn], 1) / cfg.nel
+    u = (X @ (F - np.eye(2)).T)[None]
+    T, st = O.material_snapshots(2, cfg.nel, keep, u, 1.0, 10.0)
+    F3 = np.eye(3); F3[:2, :2] = F
+    A = O.neo_hooke(F3, 1.0, 10.0)[2][:2, :2, :2, :2].reshape(-1)
+    for e in range(cfg.nel ** 2):
+        np.testing.assert_allclose(T[0, e * 16:(e + 1) * 16], A, rtol=1e-13, atol=1e-13)
