@@ -108,7 +108,8 @@ def main():
     ap.add_argument("--max-newton", type=int, default=30, help="--newton: iterations per increment")
     ap.add_argument("--solve-tol", type=float, default=1e-8, help="--newton: tangent-solve tolerance")
     ap.add_argument("--solve-maxit", type=int, default=200000, help="--newton: tangent-solve iteration limit")
-    ap.add_argument("--snap-rule", choices=["full", "reduced"], default="full", help="--newton: snapshot quadrature")
+    ap.add_argument("--snap-rule", choices=["full", "reduced", "material"], default="full",
+                    help="--newton: snapshot data")
     ap.add_argument("--radius", type=float, default=None, help="--newton: one hole radius for every cell")
     ap.add_argument("--matvec", choices=["stencils", "rom"], default="stencils",
                     help="--newton: ROM tangent products from stencils formed once per iteration, or ROM applies")
@@ -278,7 +279,8 @@ def main():
                                                                                 np.linalg.norm(Yp))}
 
     snap_variants = {f"{name}_tol_{tol:g}": snapshot_variant(rule, tol)
-                     for tol in (1e-3, 1e-4) for name, rule in (("full", B.RULE_FULL), ("reduced", B.RULE_REDUCED))}
+                     for tol in (1e-3, 1e-4) for name, rule in (("full", B.RULE_FULL), ("reduced", B.RULE_REDUCED),
+                                                                ("material", B.RULE_MATERIAL))}
     P.reset_status()
 
     cpu = None
@@ -389,7 +391,8 @@ def newton_main(args):
     st, recs = P.newton_solve(mu_t, lam_t, fixed, ubar, u, n_inc=args.n_inc, max_newton=args.max_newton,
                               cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=args.solve_maxit,
                               cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0,
-                              snap_rule=B.RULE_REDUCED if args.snap_rule == "reduced" else B.RULE_FULL,
+                              snap_rule={"full": B.RULE_FULL, "reduced": B.RULE_REDUCED,
+                                         "material": B.RULE_MATERIAL}[args.snap_rule],
                               matvec=1 if args.matvec == "rom" else 0, precond=0 if args.precond == "diag" else 1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
