@@ -157,6 +157,15 @@ lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, 
                                 int32_t *n_r, double *alpha, double *beta, double *nu, double *R, double *Z,
                                 double *achieved, int32_t *dev_status, hipStream_t stream);
 
+/* lat_select_principal on the first `rows` snapshot rows only (1 <= rows <= n_snap): for snapshots
+ * whose rows past `rows` are zero (LAT_RULE_MATERIAL fills n^d d^4 of them) the outputs equal those
+ * of lat_select_principal bit for bit (the chunk sums and pairwise trees take a zero chunk
+ * exactly), at the cost of the rows read.  Rows past `rows` are neither read nor written; Z keeps
+ * its [cap][n_snap] layout with zeros there. */
+lat_status lat_select_principal_rows(const lat_plan *plan, double *snap, int64_t rows, double tol, int32_t cap,
+                                     int32_t *S, int32_t *n_r, double *alpha, double *beta, double *nu, double *R,
+                                     double *Z, double *achieved, int32_t *dev_status, hipStream_t stream);
+
 /* ROM apply (eq. romstiffnessmatrix): Y_i = M_i (sum_k alpha_ik K_k) M_i X_i for every cell at
  * once, M_i the active-DOF mask of cell i.  K: a stack of n_r stencils in the principal stack
  * layout (cap slots) -- the principal tangents from lat_principal_ops with alpha the RB

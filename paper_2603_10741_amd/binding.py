@@ -74,6 +74,7 @@ def _lib():
             "lat_residual_tangent": (ctypes.c_int, [P, P, P, P, ctypes.c_int, P, P, P, P, P, P]),
             "lat_principal_ops": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P]),
             "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P]),
+            "lat_select_principal_rows": (ctypes.c_int, [P, P, I64, F, I32, P, P, P, P, P, P, P, P, P, P]),
             "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, F, I32, P]),
             "lat_basis_stack": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
             "lat_apply_plain": (ctypes.c_int, [P, P, P, P, I32, P]),
@@ -102,7 +103,8 @@ def _lib():
 def exported_symbols():
     """Names of the C entry points this binding uses (all declared in include/lat.h)."""
     return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_status_reset",
-            "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_apply_combo", "lat_basis_stack",
+            "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_select_principal_rows",
+            "lat_apply_combo", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
             "lat_plain_ops_to_canon", "lat_rom_solve", "lat_coarse_operator", "lat_newton_solve"]
@@ -204,7 +206,7 @@ class Plan:
         return out
 
     # ------------------------------------------------------------------ a5-a6
-    def select_principal(self, snap, tol, cap=None, keep_Z=True, out=None):
+    def select_principal(self, snap, tol, cap=None, keep_Z=True, out=None, rows=None):
         cap = self.cap if cap is None else cap
         out = dict(out or {})
         dev = self.device
@@ -215,10 +217,13 @@ class Plan:
                        nu=self._f64(self.ncells), R=self._f64(self.cap, self.cap), achieved=self._f64(1))
             if keep_Z:
                 out["Z"] = self._f64(self.cap, self.nsnap)
-        _ok(_lib().lat_select_principal(self._p, _ptr(snap), float(tol), int(cap), _ptr(out["S"]), _ptr(out["n_r"]),
-                                        _ptr(out["alpha"]), _ptr(out.get("beta")), _ptr(out.get("nu")),
-                                        _ptr(out["R"]), _ptr(out.get("Z")), _ptr(out["achieved"]),
-                                        _ptr(self.status_word), _stream()), "select_principal")
+        args = (_ptr(out["S"]), _ptr(out["n_r"]), _ptr(out["alpha"]), _ptr(out.get("beta")), _ptr(out.get("nu")),
+                _ptr(out["R"]), _ptr(out.get("Z")), _ptr(out["achieved"]), _ptr(self.status_word), _stream())
+        if rows is None:
+            _ok(_lib().lat_select_principal(self._p, _ptr(snap), float(tol), int(cap), *args), "select_principal")
+        else:
+            _ok(_lib().lat_select_principal_rows(self._p, _ptr(snap), int(rows), float(tol), int(cap), *args),
+                "select_principal_rows")
         return out
 
     # ------------------------------------------------------------------ a7-a8

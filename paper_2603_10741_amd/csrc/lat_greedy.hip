@@ -369,16 +369,29 @@ extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, doub
                                            int32_t *n_r, double *alpha, double *beta, double *nu, double *R, double *Z,
                                            double *achieved, int32_t *dev_status, hipStream_t stream)
 {
+    if (!P) return LAT_E_ARG;
+    return lat_select_principal_rows(P, snap, P->nsnap, tol, cap, S, n_r, alpha, beta, nu, R, Z, achieved,
+                                     dev_status, stream);
+}
+
+// The greedy on the first `rows` snapshot rows: the chunk sums and pairwise trees take a zero
+// chunk without rounding, so when the rows past `rows` are zero the result is the full sweep's,
+// bit for bit, at the cost of the data rows only.
+extern "C" lat_status lat_select_principal_rows(const lat_plan *P, double *snap, int64_t rows, double tol, int32_t cap,
+                                                int32_t *S, int32_t *n_r, double *alpha, double *beta, double *nu,
+                                                double *R, double *Z, double *achieved, int32_t *dev_status,
+                                                hipStream_t stream)
+{
     if (!P || !snap || !S || !n_r || !alpha || !R || !achieved) return LAT_E_ARG;
-    if (!(tol > 0.0) || cap < 1 || cap > P->cap) return LAT_E_ARG;
-    const int64_t ld = P->ld, ns = P->nsnap, nc = P->nchunk;
+    if (!(tol > 0.0) || cap < 1 || cap > P->cap || rows < 1 || rows > P->nsnap) return LAT_E_ARG;
+    const int64_t ld = P->ld, ns = rows, nc = lat_cdiv(rows, LAT_CHUNK);
     const dim3 cg = chunk_grid(ld, nc);
     const dim3 lg((unsigned)lat_cdiv(ld, 256));
     lat_status st;
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, stream, P->ictl, P->dctl, S, P->cap, n_r);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)lat_cdiv(ld * P->cap, 256)), dim3(256), 0, stream, ld * P->cap, P->beta_pl);
-    if (Z) hipLaunchKernelGGL(k_zero, dim3((unsigned)lat_cdiv((int64_t)P->cap * ns, 256)), dim3(256), 0, stream,
-                              (int64_t)P->cap * ns, Z);
+    if (Z) hipLaunchKernelGGL(k_zero, dim3((unsigned)lat_cdiv((int64_t)P->cap * P->nsnap, 256)), dim3(256), 0, stream,
+                              (int64_t)P->cap * P->nsnap, Z);
     LAT_LAUNCH_CHECK();
     // nu_s = ||t^s||_2 and the normalisation Delta_0 = t / nu
     hipLaunchKernelGGL(k_sq, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->g_sq);
@@ -395,7 +408,7 @@ extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, doub
         LAT_LAUNCH_CHECK();
         if (it == cap) break;
         hipLaunchKernelGGL(k_zeta, dim3((unsigned)lat_cdiv(ns, 256)), dim3(256), 0, stream, snap, ns, ld, P->ictl,
-                           P->dctl, P->zeta, Z ? Z + (int64_t)it * ns : nullptr);
+                           P->dctl, P->zeta, Z ? Z + (int64_t)it * P->nsnap : nullptr);
         hipLaunchKernelGGL(k_dot, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->ictl, P->g_dot);
         LAT_LAUNCH_CHECK();
         // beta_i lands directly in its column of the plan-order coordinate matrix

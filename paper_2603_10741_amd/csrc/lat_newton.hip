@@ -1245,8 +1245,10 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             int32_t hnr = 0;
             if (!full) {
                 NCHK(lat_status_reset(gst_d, s));
-                NCHK(lat_select_principal(P, snap, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R, nullptr,
-                                          scal + 1, gst_d, s));
+                // material snapshots fill n^d d^4 rows; the greedy reads only those
+                const int64_t rows = rule == LAT_RULE_MATERIAL ? (int64_t)P->nelem * d * d * d * d : P->nsnap;
+                NCHK(lat_select_principal_rows(P, snap, rows, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R,
+                                               nullptr, scal + 1, gst_d, s));
                 int32_t hg[2] = {0, 0};
                 double ach = 0.0;
                 LAT_HIP(hipMemcpyAsync(&hnr, nr_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -352,3 +352,22 @@ def test_material_snapshots_match_oracle(which):
         g = P.select_principal(out["snap"] if tol == 1e-2 else c.to_cil_T(To), tol, keep_Z=False)
         go = O.greedy(To, tol, cfg.cap, keep_Z=False)
         assert int(g["n_r"].item()) == go["n_r"]
+
+
+def test_greedy_on_the_data_rows_is_bit_identical():
+    # material snapshots fill n^d d^4 rows; the greedy restricted to them returns the full sweep's
+    # outputs bit for bit
+    from gpu_common import Case
+    cfg = L.config(0).with_(radius=(0.25, 0.35))
+    c = Case(cfg, m=1)
+    P = c.P
+    rows = cfg.n_elems * cfg.dim ** 4
+    outs = []
+    for r in (None, rows):
+        snap = P.residual_tangent(c.ug, c.mu_t, c.lam_t, snap_rule=c.B.RULE_MATERIAL, f=False, energy=False,
+                                  snap=True)["snap"]
+        g = P.select_principal(snap, 1e-3, keep_Z=True, rows=r)
+        outs.append({k: v.cpu().numpy() for k, v in g.items()} | {"delta": snap.cpu().numpy()})
+    assert outs[0]["n_r"][0] > 1
+    for k in ("S", "n_r", "alpha", "beta", "nu", "R", "Z", "achieved", "delta"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
