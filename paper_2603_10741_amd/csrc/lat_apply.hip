@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs A, const int32_t *__res
 //     4-slot register window (columns x-1 .. x+2 of rows y-1, y, y+1);
 //   - one barrier; then each wave applies the node's 2x2 blocks to its right-hand sides.
 // Every X entry is fetched once per row walk and all loads are issued a step ahead of use.
-template <int MW, int NR, int MODE, int LP>
+template <int MW, int NR, int MODE, int LP, bool IDLE = false>
 __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *__restrict__ goff,
                                                     const int32_t *__restrict__ uidx,
                                                     const uint64_t *__restrict__ umask, const double *__restrict__ K,
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int64_t p = (int64_t)g * LAT_WAVE + l;
     const int r0 = w * MW;
-    const bool act = r0 < m;                             // false for the waves past m (m < 8)
+    const bool act = !IDLE || r0 < m;                    // IDLE (m < 8): the waves past m only form
     const int e0 = (w * E) / NW, e1 = ((w + 1) * E) / NW;   // this wave's share of the entries
     const int32_t *ui = uidx + (int64_t)g * nloc;
     const int gq = goff[g];
@@ -983,15 +983,15 @@ lat_status launch_apply(const ApplyArgs &A, int nwaves, hipStream_t s)
     return launch_apply_nr<DIM, 1, MODE>(A, nwaves, s);
 }
 
-template <int MW, int MODE, int LP = 0>
+template <int MW, int MODE, int LP = 0, bool IDLE = false>
 lat_status launch_rowwalk_nr(const lat_plan *P, const ApplyArgs &A, hipStream_t s)
 {
     ApplyArgs B = A;
     // enough walks to fill the chip in whole waves of workgroups: split rows into x-segments
     B.nseg = P->ngroups * P->nn >= 1024 ? 1 : (P->nn >= 16 ? 2 : 1);
     dim3 grid((unsigned)(P->ngroups * P->nn * B.nseg)), block(512);
-#define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE, LP>), grid, block, 0, s, B, P->goff, P->uidx, P->umask, A.K, \
-                                   A.alpha_il, A.X, A.Y)
+#define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE, LP, IDLE>), grid, block, 0, s, B, P->goff, P->uidx, \
+                                   P->umask, A.K, A.alpha_il, A.X, A.Y)
     if (MODE == 2 || A.n_r <= 8) RW(8);
     else if (A.n_r <= 16) RW(16);
     else if (A.n_r <= 32) RW(32);
@@ -1012,6 +1012,11 @@ lat_status launch_rowwalk_mode(const lat_plan *P, const ApplyArgs &A, int mode, 
 lat_status launch_rowwalk(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
 {
     if (A.m == 16) return launch_rowwalk_mode<2>(P, A, mode, s);
+    if (A.m < 8) {   // ROM modes only: one wave per right-hand side, the others form and stage
+        if (mode == 0) return launch_rowwalk_nr<1, 0, 0, true>(P, A, s);
+        if (mode == 1) return launch_rowwalk_nr<1, 1, 0, true>(P, A, s);
+        return LAT_E_ARG;
+    }
     return launch_rowwalk_mode<1>(P, A, mode, s);
 }
 
