@@ -217,6 +217,11 @@ lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U
 
 }  // namespace
 
+lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
+{
+    return contract(P, n_r, V, U, out, s);
+}
+
 extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, const double *Z, const double *R,
                                         const double *nu, const int32_t *S, int32_t n_r, const double *alpha,
                                         const double *alpha_bar, const double *snap_mu, const double *snap_lam,

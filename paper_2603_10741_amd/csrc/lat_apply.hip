@@ -908,6 +908,56 @@ __global__ __launch_bounds__(512) void k_forms_mfma(ApplyArgs A, const int32_t *
     }
 }
 
+// The adjoint forms' cell data W[(a, e)][p] = sum_r Ybar[a, i, r] X[a + o, j, r] (e = (o d + i) d + j)
+// for every local node a and plan lane p, Ybar counted at the cell's owned DOFs and X at its owned
+// neighbour DOFs, zero where the node is not in the lane's group union; then
+// <Ybar_p, K_k X_p> = sum_(a, e) K_k[a][e] W[(a, e)][p] is one row contraction per stack.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int nloc, int m, const int32_t *__restrict__ goff,
+                                                 const int32_t *__restrict__ uidx, const int32_t *__restrict__ unbr,
+                                                 const uint64_t *__restrict__ umask, const double *__restrict__ X,
+                                                 const double *__restrict__ Ybar, double *__restrict__ W)
+{
+    constexpr int NO = DIM == 2 ? 9 : 27, E = NO * DIM * DIM, MM = 16;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int a = blockIdx.y;
+    if (p >= ld) return;
+    const int g = (int)(p / LAT_WAVE), l = (int)(p % LAT_WAVE);
+    const int qi = uidx[(int64_t)g * nloc + a];
+    double *wr = W + (int64_t)a * E * ld + p;
+    if (qi < 0) {
+        for (int e = 0; e < E; ++e) wr[(int64_t)e * ld] = 0.0;
+        return;
+    }
+    const int64_t q = (int64_t)goff[g] + qi;
+    const bool own = (umask[q] >> l) & 1;
+    double yb[DIM][MM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int r = 0; r < MM; ++r)
+            yb[i][r] = (own && r < m) ? Ybar[((q * DIM + i) * m + r) * LAT_WAVE + l] : 0.0;
+    for (int o = 0; o < NO; ++o) {
+        const int nb = unbr[q * NO + o];
+        const bool nbo = nb >= 0 && ((umask[nb] >> l) & 1);
+        double xv[DIM][MM];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+#pragma unroll
+            for (int r = 0; r < MM; ++r)
+                xv[j][r] = (nbo && r < m) ? X[(((int64_t)nb * DIM + j) * m + r) * LAT_WAVE + l] : 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                double v = 0.0;
+#pragma unroll
+                for (int r = 0; r < MM; ++r) v = fma(yb[i][r], xv[j][r], v);
+                wr[(int64_t)((o * DIM + i) * DIM + j) * ld] = v;
+            }
+    }
+}
+
 __global__ void k_alpha_il(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
                            const double *__restrict__ alpha, double *__restrict__ alpha_il)
 {
@@ -1211,13 +1261,36 @@ lat_status lat_apply_combo_adjoint(const lat_plan *P, const double *K, const dou
         if (alpha_bar) { stk[ns] = K; role[ns++] = 0; }
         if (mu_bar) { stk[ns] = K_mu; role[ns++] = 1; }
         if (lam_bar) { stk[ns] = K_lam; role[ns++] = 2; }
+        // the cells' W once (a streaming pass over X and Ybar), then one row contraction per stack on
+        // the matrix cores; the fused per-node kernel serves when W's workspace cannot be had
+        lat_plan *Pm = const_cast<lat_plan *>(P);
+        if (!Pm->w_forms && !Pm->w_forms_failed) {
+            const size_t bytes = (size_t)P->nsnap * P->ld * sizeof(double);
+            if (bytes > ((size_t)16 << 30) || hipMalloc((void **)&Pm->w_forms, bytes) != hipSuccess) {
+                Pm->w_forms = nullptr;
+                Pm->w_forms_failed = true;
+                (void)hipGetLastError();
+            }
+        }
         int cpg = 0;
-        if ((st = run_forms_fused(P, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) return st;
+        if (P->w_forms) {
+            const dim3 wg((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc);
+            if (P->dim == 2)
+                hipLaunchKernelGGL(k_forms_W<2>, wg, dim3(256), 0, stream, P->ld, P->nloc, m, P->goff, P->uidx, P->unbr,
+                                   P->umask, X, Ybar, P->w_forms);
+            else
+                hipLaunchKernelGGL(k_forms_W<3>, wg, dim3(256), 0, stream, P->ld, P->nloc, m, P->goff, P->uidx, P->unbr,
+                                   P->umask, X, Ybar, P->w_forms);
+            LAT_LAUNCH_CHECK();
+        } else if ((st = run_forms_fused(P, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) {
+            return st;
+        }
         const int64_t ldc = P->ld * P->cap;
         for (int t = 0; t < ns; ++t) {
-            if ((st = lat_tree_reduce(P->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, P->form_out, P->g_t1,
-                                      P->g_t2, stream)) != LAT_OK)
-                return st;
+            if (P->w_forms) st = lat_contract_rows(P, n_r, P->w_forms, stk[t], P->form_out, stream);
+            else st = lat_tree_reduce(P->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, P->form_out, P->g_t1, P->g_t2,
+                                      stream);
+            if (st != LAT_OK) return st;
             if (role[t] == 0) {
                 hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, P->ld, P->cap, P->perm, P->form_out,
                                    alpha_bar);

@@ -71,6 +71,9 @@ struct lat_plan {
     uint16_t *lp_cslice = nullptr; // [3][ld][64] bf16 slices of the coefficients (plan order)
     float *lp_kf32 = nullptr;      // [nloc][E][cap] FP32 principal stack
     float *lp_cf32 = nullptr;      // [cap][ld] FP32 coefficients
+    // adjoint forms: W[(a, e)][lane] = sum_r Ybar X, allocated on the first ROM-apply adjoint
+    double *w_forms = nullptr;     // [nsnap][ld]
+    bool w_forms_failed = false;   // the allocation was refused (too large): the fused kernel serves
 };
 
 // ---- bf16 slices (reduced-precision combination on the bf16 matrix cores)
@@ -138,6 +141,11 @@ __device__ inline void lat_flag(int32_t *st, int code, int cell)
 // sum (op 0) or max (op 1); result [ld] in out.  Uses t1/t2 as scratch ([ceil(nrows/256)][ld]).
 lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1,
                            double *t2, hipStream_t s);
+
+// Row contraction out[p][k] = sum_j V[j][p] U[j][k] over the n_snap snapshot rows, V [nsnap][ld],
+// U [nsnap][cap] (a principal stack), out [ld][cap] in plan order; fixed-order chunk partials and
+// tree (defined in lat_adjoint.hip).
+lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s);
 
 // Reduced-precision ROM apply (defined in lat_lowp.hip).
 // ROM apply with a reduced-precision combination inside the 2D row walk / 3D slice walk:
