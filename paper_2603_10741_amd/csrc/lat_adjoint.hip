@@ -142,6 +142,70 @@ __global__ __launch_bounds__(256) void k_aa_contract_mfma(int64_t nsnap, int64_t
         part[(b * ld + pw + l) * cap + k] = 0.0;
 }
 
+// The same row contraction against NS stacks at once: every V tile is loaded once and feeds the
+// NS accumulators (out_t[p][k] = sum_j V[j][p] U_t[j][k]); chunk partials part_t as above.
+template <int NR, int NS>
+__global__ __launch_bounds__(256) void k_aa_contract_ns_mfma(int64_t nsnap, int64_t ld, int cap, int rows_per_chunk,
+                                                             const double *__restrict__ V,
+                                                             const double *__restrict__ U0,
+                                                             const double *__restrict__ U1,
+                                                             const double *__restrict__ U2, double *__restrict__ part0,
+                                                             double *__restrict__ part1, double *__restrict__ part2)
+{
+    constexpr int NKT = NR / 16;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63;
+    const int64_t pw = (int64_t)blockIdx.x * 256 + 64 * w;
+    if (pw >= ld) return;                                             // wave-uniform (ld % 64 == 0)
+    const int64_t b = blockIdx.y;
+    const int64_t j0 = b * rows_per_chunk, j1 = j0 + rows_per_chunk < nsnap ? j0 + rows_per_chunk : nsnap;
+    const double *Us[3] = {U0, U1, U2};
+    aa_v4d acc[NS][4][NKT];
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+            for (int kt = 0; kt < NKT; ++kt) acc[t][pt][kt] = aa_v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = j0; j < j1; j += 4) {
+        const int64_t jr = j + (l >> 4);
+        const bool live = jr < j1;
+        const int64_t jc = live ? jr : j0;
+        double a[4];
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt) {
+            const double v = V[jc * ld + pw + 16 * pt + (l & 15)];
+            a[pt] = live ? v : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            double bv[NKT];
+#pragma unroll
+            for (int kt = 0; kt < NKT; ++kt) {
+                const double u = Us[t][jc * cap + 16 * kt + (l & 15)];
+                bv[kt] = live ? u : 0.0;
+            }
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+                for (int kt = 0; kt < NKT; ++kt)
+                    acc[t][pt][kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[pt], bv[kt], acc[t][pt][kt], 0, 0, 0);
+        }
+    }
+    double *parts[3] = {part0, part1, part2};
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+            for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    parts[t][(b * ld + pw + 16 * pt + (l >> 4) + 4 * r) * cap + 16 * kt + (l & 15)] = acc[t][pt][kt][r];
+        for (int k = NR; k < cap; ++k) parts[t][(b * ld + pw + l) * cap + k] = 0.0;
+    }
+}
+
 // per-cell term: bar_c += q_c . A[p_c]   (A = Z^T t^x, plan order [ld][cap])
 __global__ void k_aa_cellterm(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
                               const double *__restrict__ qv, const double *__restrict__ Am,
@@ -220,6 +284,25 @@ lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U
 lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
 {
     return contract(P, n_r, V, U, out, s);
+}
+
+lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const double *const *U, int ns,
+                                   double *const *part, hipStream_t s)
+{
+    if (ns < 1 || ns > 3 || n_r > 32 || P->cap < 16) return LAT_E_ARG;
+    dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->aa_nchunk);
+    const double *u1 = ns > 1 ? U[1] : U[0], *u2 = ns > 2 ? U[2] : U[0];
+    double *p1 = ns > 1 ? part[1] : part[0], *p2 = ns > 2 ? part[2] : part[0];
+#define CN(NRV, NSV) hipLaunchKernelGGL((k_aa_contract_ns_mfma<NRV, NSV>), grid, dim3(256), 0, s, P->nsnap, P->ld, \
+                                        P->cap, P->aa_rows, V, U[0], u1, u2, part[0], p1, p2)
+    if (n_r <= 16) {
+        if (ns == 1) CN(16, 1); else if (ns == 2) CN(16, 2); else CN(16, 3);
+    } else {
+        if (ns == 1) CN(32, 1); else if (ns == 2) CN(32, 2); else CN(32, 3);
+    }
+#undef CN
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
 }
 
 extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, const double *Z, const double *R,

@@ -1266,8 +1266,12 @@ lat_status lat_apply_combo_adjoint(const lat_plan *P, const double *K, const dou
         lat_plan *Pm = const_cast<lat_plan *>(P);
         if (!Pm->w_forms && !Pm->w_forms_failed) {
             const size_t bytes = (size_t)P->nsnap * P->ld * sizeof(double);
-            if (bytes > ((size_t)16 << 30) || hipMalloc((void **)&Pm->w_forms, bytes) != hipSuccess) {
+            const size_t pbytes = (size_t)3 * P->aa_nchunk * P->ld * P->cap * sizeof(double);
+            if (bytes > ((size_t)16 << 30) || hipMalloc((void **)&Pm->w_forms, bytes) != hipSuccess ||
+                hipMalloc((void **)&Pm->wf_part, pbytes) != hipSuccess) {
+                if (Pm->w_forms) (void)hipFree(Pm->w_forms);
                 Pm->w_forms = nullptr;
+                Pm->wf_part = nullptr;
                 Pm->w_forms_failed = true;
                 (void)hipGetLastError();
             }
@@ -1286,8 +1290,13 @@ lat_status lat_apply_combo_adjoint(const lat_plan *P, const double *K, const dou
             return st;
         }
         const int64_t ldc = P->ld * P->cap;
+        // n_r <= 32: the stacks' contractions share one pass over W (chunk partials per stack)
+        const bool multi = P->w_forms && n_r <= 32;
+        double *wparts[3] = {P->wf_part, P->wf_part + P->aa_nchunk * ldc, P->wf_part + 2 * P->aa_nchunk * ldc};
+        if (multi && (st = lat_contract_rows_multi(P, n_r, P->w_forms, stk, ns, wparts, stream)) != LAT_OK) return st;
         for (int t = 0; t < ns; ++t) {
-            if (P->w_forms) st = lat_contract_rows(P, n_r, P->w_forms, stk[t], P->form_out, stream);
+            if (multi) st = lat_tree_reduce(wparts[t], P->aa_nchunk, ldc, 0, P->form_out, P->g_t1, P->g_t2, stream);
+            else if (P->w_forms) st = lat_contract_rows(P, n_r, P->w_forms, stk[t], P->form_out, stream);
             else st = lat_tree_reduce(P->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, P->form_out, P->g_t1, P->g_t2,
                                       stream);
             if (st != LAT_OK) return st;

@@ -73,6 +73,7 @@ struct lat_plan {
     float *lp_cf32 = nullptr;      // [cap][ld] FP32 coefficients
     // adjoint forms: W[(a, e)][lane] = sum_r Ybar X, allocated on the first ROM-apply adjoint
     double *w_forms = nullptr;     // [nsnap][ld]
+    double *wf_part = nullptr;     // [3][aa_nchunk][ld][cap] contraction partials of the stacks
     bool w_forms_failed = false;   // the allocation was refused (too large): the fused kernel serves
 };
 
@@ -146,6 +147,10 @@ lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, 
 // U [nsnap][cap] (a principal stack), out [ld][cap] in plan order; fixed-order chunk partials and
 // tree (defined in lat_adjoint.hip).
 lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s);
+// The same for ns (1..3) stacks in one pass over V (n_r <= 32, cap >= 16): chunk partials
+// part[t] [aa_nchunk][ld][cap], to be reduced by lat_tree_reduce.
+lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const double *const *U, int ns,
+                                   double *const *part, hipStream_t s);
 
 // Reduced-precision ROM apply (defined in lat_lowp.hip).
 // ROM apply with a reduced-precision combination inside the 2D row walk / 3D slice walk:

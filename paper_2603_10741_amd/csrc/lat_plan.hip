@@ -356,7 +356,7 @@ void free_plan(lat_plan *P)
                     P->unode, P->unbr, P->umask, P->uidx, P->u_cil, P->w_part, P->w_part2, P->g_sq, P->g_inf,
                     P->g_dot, P->g_t1, P->g_t2, P->g_t3, P->g_t4, P->v_sq, P->v_inf, P->v_beta, P->v_nu, P->beta_pl, P->zeta,
                     P->ictl, P->dctl, P->form_part, P->form_out, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part,
-                    P->lp_kslice, P->lp_cslice, P->lp_kf32, P->lp_cf32, P->w_forms};
+                    P->lp_kslice, P->lp_cslice, P->lp_kf32, P->lp_cf32, P->w_forms, P->wf_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P;
