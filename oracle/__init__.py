@@ -25,7 +25,8 @@ _LIB = os.path.join(_HERE, "liblat_oracle.so")
 _lib = None
 
 OK, E_INVERTED, E_NONFINITE, W_CAP = 0, 5, 6, 7
-RULE_FULL, RULE_REDUCED, RULE_MATERIAL = 0, 1, 2
+RULE_FULL, RULE_REDUCED, RULE_MATERIAL, RULE_SAMPLED = 0, 1, 2, 3
+SAMPLE_STRIDE = 4          # node stride of the sampled-entry snapshots
 
 
 def build(force: bool = True) -> str:
@@ -273,3 +274,34 @@ def material_snapshots(dim, nel, keep, u_loc, mu, lam):
                 continue
             T[s, e * d4:(e + 1) * d4] = A[:dim, :dim, :dim, :dim].reshape(-1)
     return T, status
+
+
+# ----------------------------------------------------------------------------- f3: sampled entries
+def sampled_nodes(dim, nel, stride=SAMPLE_STRIDE):
+    """Local nodes whose every coordinate is a multiple of `stride`, lexicographic (x fastest)."""
+    nn = nel + 1
+    axis = list(range(0, nn, stride))
+    return [sum(c[ax] * nn ** ax for ax in range(dim)) for c in _lex(axis, dim)]
+
+
+def _lex(axis, dim):
+    if dim == 0:
+        yield []
+        return
+    for hi in axis:                                   # slowest axis outermost
+        for lo in _lex(axis, dim - 1):
+            yield lo + [hi]
+
+
+def sampled_snapshots(dim, nel, T_full, stride=SAMPLE_STRIDE):
+    """Snapshots made of a limited number of entries of the true tangent (the some_data(K) choice of
+    the Remark on snapshots in Sec. 3.2.2): the full-rule stencil rows (every 3^d d^2 entry) of the
+    local nodes on the sub-grid of node stride `stride`, node j of `sampled_nodes` in rows
+    j 3^d d^2 ... (j+1) 3^d d^2 - 1; rows past them are zero.  T_full [N_s][n_snap] is the cells'
+    full-rule snapshot matrix."""
+    E = 3 ** dim * dim * dim
+    T_full = np.asarray(T_full, np.float64)
+    T = np.zeros_like(T_full)
+    for j, a in enumerate(sampled_nodes(dim, nel, stride)):
+        T[:, j * E:(j + 1) * E] = T_full[:, a * E:(a + 1) * E]
+    return T

@@ -23,7 +23,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import OK, RULE_FULL, RULE_MATERIAL, assemble, cells_eval, dofmap, gather_local, greedy, material_snapshots
+from . import (OK, RULE_FULL, RULE_MATERIAL, RULE_SAMPLED, assemble, cells_eval, dofmap, gather_local, greedy,
+               material_snapshots, sampled_snapshots)
 
 NOCONV = 8
 
@@ -110,14 +111,16 @@ class Problem:
         """(r masked [n_global][d], T [N_s][n_snap] or None, status, energy per cell or None).
 
         The residual and energy always use the full rule (the residual is not reduced, Sec. 4);
-        the snapshots T use the problem's snapshot rule (full, one-point, or the material tangent
-        at the kept elements' centres)."""
+        the snapshots T use the problem's snapshot rule (full, one-point, the material tangent
+        at the kept elements' centres, or the full tangent's entries at sampled nodes)."""
         ul = gather_local(u, self.l2g)
-        full = self.rule == RULE_FULL
+        full = self.rule in (RULE_FULL, RULE_SAMPLED)
         ev = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=RULE_FULL, want_f=True,
                         want_energy=want_energy, want_T=want_T and full)
         T = ev["T"]
-        if want_T and self.rule == RULE_MATERIAL:
+        if want_T and self.rule == RULE_SAMPLED:
+            T = sampled_snapshots(self.dim, self.nel, T)
+        elif want_T and self.rule == RULE_MATERIAL:
             T, _ = material_snapshots(self.dim, self.nel, self.keep, ul, self.mu, self.lam)
         elif want_T and not full:
             T = cells_eval(self.dim, self.nel, self.keep, ul, self.mu, self.lam, rule=self.rule, want_f=False,

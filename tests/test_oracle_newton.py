@@ -214,6 +214,18 @@ def test_coarse_operator_kills_translations_and_is_galerkin():
     assert abs(a @ K0 @ c - (P @ a) @ (K @ (P @ c))) <= 1e-11 * np.abs(K0).max() * 2 * nc
 
 
+def test_sampled_snapshots_reach_the_same_equilibrium(exact_graded):
+    # Snapshots of sampled tangent entries change the principal cells, never the residual.
+    cfg, P_full, out_full = exact_graded
+    mu, lam = L.make_material(cfg)
+    bvp = L.make_bvp(cfg, L.LoadCase("compress_shear", 0.04, 0.01, 4))
+    P = ON.Problem(2, cfg.ncell_eff, cfg.nel, L.make_keep(cfg), mu, lam, bvp["fixed"], bvp["ubar"],
+                   rule=O.RULE_SAMPLED)
+    out = ON.newton_solve(P, n_inc=4, rb_tol=1e-4, cap=16, newton_tol=1e-10)
+    assert out["status"] == O.OK
+    assert np.abs(out["u"] - out_full["u"]).max() <= 1e-10 * np.abs(out_full["u"]).max()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_material_snapshots_at_rest_are_the_elasticity_tensor(dim):
     # At u = 0 every kept element carries the isotropic tensor
@@ -250,3 +262,54 @@ def test_material_snapshots_follow_a_homogeneous_stretch():
     A = O.neo_hooke(F3, 1.0, 10.0)[2][:2, :2, :2, :2].reshape(-1)
     for e in range(cfg.nel ** 2):
         np.testing.assert_allclose(T[0, e * 16:(e + 1) * 16], A, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim,nel", [(2, 8), (3, 4)])
+def test_sampled_snapshots_are_force_derivatives_at_sampled_nodes(dim, nel):
+    # some_data(K): every stored entry (j, o, i, c) is d f_(a_j, i) / d u_(a_j + o, c) of the cell's
+    # internal force at the j-th node of the stride-4 sub-grid, by central differences of the force
+    # alone; neighbours outside the cell give zeros, and the rows past the sampled nodes are zero.
+    rng = np.random.default_rng(4)
+    nn = nel + 1
+    nloc = nn ** dim
+    if dim == 2:
+        keep = np.ones(nel * nel, np.uint8); keep[[nel + 2, 2 * nel + 5]] = 0
+    else:
+        keep = (rng.random(nel ** 3) < 0.8).astype(np.uint8)
+    u = 0.02 * rng.standard_normal((nloc, dim))
+    mu, lam = 1.2, 6.0
+    T_full = O.cells_eval(dim, nel, keep[None], u[None], mu, lam, want_f=False, want_energy=False)["T"]
+    T = O.sampled_snapshots(dim, nel, T_full)[0]
+    nodes = O.sampled_nodes(dim, nel)
+    assert len(nodes) == (nel // 4 + 1) ** dim and nodes[1] == 4 and nodes == sorted(nodes)
+    E = 3 ** dim * dim * dim
+    h = 1e-6
+    fd = {}
+    for j, a in enumerate(nodes):
+        ca = [(a // nn ** ax) % nn for ax in range(dim)]
+        for o in range(3 ** dim):
+            off = [(o // 3 ** ax) % 3 - 1 for ax in range(dim)]
+            cb = [ca[ax] + off[ax] for ax in range(dim)]
+            inside = all(0 <= cb[ax] < nn for ax in range(dim))
+            for c in range(dim):
+                blk = np.array([T[j * E + (o * dim + i) * dim + c] for i in range(dim)])
+                if not inside:
+                    assert not blk.any()
+                    continue
+                b = sum(cb[ax] * nn ** ax for ax in range(dim))
+                if (b, c) not in fd:
+                    up = u.copy(); up[b, c] += h
+                    um = u.copy(); um[b, c] -= h
+                    fd[(b, c)] = (O.cell_eval(dim, nel, keep, up, mu, lam)["f"]
+                                  - O.cell_eval(dim, nel, keep, um, mu, lam)["f"]) / (2 * h)
+                np.testing.assert_allclose(blk, fd[(b, c)][a], rtol=0, atol=1e-7 * np.abs(T).max())
+    assert not T[len(nodes) * E:].any()
+
+
+def test_sampled_snapshots_at_stride_one_are_the_full_snapshots():
+    cfg = L.config(0).with_(ncell=(2, 2), nel=4)
+    keep = L.make_keep(cfg)
+    u = 0.01 * np.random.default_rng(2).standard_normal((4, 25, 2))
+    T_full = O.cells_eval(2, 4, keep, u, 1.0, 10.0, want_f=False, want_energy=False)["T"]
+    np.testing.assert_array_equal(O.sampled_snapshots(2, 4, T_full, stride=1), T_full)
+    assert O.sampled_nodes(2, 4, stride=4) == [0, 4, 20, 24]
