@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--max-newton", type=int, default=30, help="--newton: iterations per increment")
     ap.add_argument("--solve-tol", type=float, default=1e-8, help="--newton: tangent-solve tolerance")
     ap.add_argument("--solve-maxit", type=int, default=200000, help="--newton: tangent-solve iteration limit")
-    ap.add_argument("--snap-rule", choices=["full", "reduced", "material"], default="full",
+    ap.add_argument("--snap-rule", choices=["full", "reduced", "material", "sampled"], default="full",
                     help="--newton: snapshot data")
     ap.add_argument("--radius", type=float, default=None, help="--newton: one hole radius for every cell")
     ap.add_argument("--matvec", choices=["stencils", "rom"], default="stencils",
@@ -267,7 +267,7 @@ def main():
         e[0].record(cs)
         P.residual_tangent(ug, mu_t, lam_t, snap_rule=rule, f=False, energy=False, snap=True, out=buf)
         e[1].record(cs)
-        g = P.select_principal(buf["snap"], tol, keep_Z=False)
+        g = P.select_principal(buf["snap"], tol, keep_Z=False, rows=P.snapshot_rows(rule))
         e[2].record(cs)
         torch.cuda.synchronize()
         nr = int(g["n_r"].item())
@@ -280,7 +280,8 @@ def main():
 
     snap_variants = {f"{name}_tol_{tol:g}": snapshot_variant(rule, tol)
                      for tol in (1e-3, 1e-4) for name, rule in (("full", B.RULE_FULL), ("reduced", B.RULE_REDUCED),
-                                                                ("material", B.RULE_MATERIAL))}
+                                                                ("material", B.RULE_MATERIAL),
+                                                                ("sampled", B.RULE_SAMPLED))}
     P.reset_status()
 
     cpu = None
@@ -392,7 +393,7 @@ def newton_main(args):
                               cap=args.cap, rb_tol=args.rb_tol, cg_tol=args.solve_tol, cg_maxit=args.solve_maxit,
                               cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0,
                               snap_rule={"full": B.RULE_FULL, "reduced": B.RULE_REDUCED,
-                                         "material": B.RULE_MATERIAL}[args.snap_rule],
+                                         "material": B.RULE_MATERIAL, "sampled": B.RULE_SAMPLED}[args.snap_rule],
                               matvec=1 if args.matvec == "rom" else 0, precond=0 if args.precond == "diag" else 1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

@@ -70,9 +70,12 @@ typedef enum {
     LAT_E_SINGULAR = 9    /* the tangent solve met an operator singular on its Krylov space */
 } lat_status;
 
-/* snapshot data: the assembled cell tangent with 2^d Gauss points / with 1 point per element, or the
- * material tangent dP/dF at the centre of every kept element (see lat_residual_tangent) */
-typedef enum { LAT_RULE_FULL = 0, LAT_RULE_REDUCED = 1, LAT_RULE_MATERIAL = 2 } lat_rule;
+/* snapshot data: the assembled cell tangent with 2^d Gauss points / with 1 point per element, the
+ * material tangent dP/dF at the centre of every kept element, or the full-rule tangent's entries at
+ * a sub-grid of local nodes (see lat_residual_tangent) */
+typedef enum { LAT_RULE_FULL = 0, LAT_RULE_REDUCED = 1, LAT_RULE_MATERIAL = 2, LAT_RULE_SAMPLED = 3 } lat_rule;
+/* node stride of LAT_RULE_SAMPLED: the local nodes whose every coordinate is a multiple of it */
+#define LAT_SAMPLE_STRIDE 2
 typedef enum { LAT_F64 = 0, LAT_F32 = 1, LAT_BF16 = 2 } lat_prec;
 
 typedef struct lat_plan lat_plan;
@@ -123,12 +126,22 @@ lat_status lat_dofmap(const lat_plan *plan, int32_t *l2g, int32_t *n_active, int
  *                      LAT_RULE_MATERIAL, the material tangent A = dP/dF at the centre of every
  *                      kept element (the Remark on snapshots of Sec. 3.2.2), A_iJkL of element e in
  *                      row (e d^2 + i d + J) d^2 + k d + L, zeros for elements not kept and for the
- *                      rows past n^d d^4
+ *                      rows past n^d d^4; or, with LAT_RULE_SAMPLED, a limited set of entries of the
+ *                      full-rule tangent (the some_data(K) choice of the same Remark): the complete
+ *                      stencil rows (3^d d^2 entries) of the nodes of the sub-grid of stride
+ *                      LAT_SAMPLE_STRIDE, node j (lexicographic, x fastest) in rows j 3^d d^2 ...,
+ *                      zeros past them; those rows equal the FULL snapshot's rows of the same node
+ *                      bit for bit
  *   plain_ops packed   every cell's full-rule tangent in stencil form (for lat_apply_plain)
  * Errors J <= 0 / non-finite go to dev_status. */
 lat_status lat_residual_tangent(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
                                 lat_rule snap_rule, double *f_int, double *energy, double *snap, double *plain_ops,
                                 int32_t *dev_status, hipStream_t stream);
+
+/* Number of leading snapshot rows that `rule` can make nonzero (the rest of the n_snap rows are
+ * zero): n_snap for FULL / REDUCED, n^d d^4 for MATERIAL, ((n / LAT_SAMPLE_STRIDE) + 1)^d 3^d d^2 for
+ * SAMPLED; the `rows` argument of lat_select_principal_rows.  -1 for a NULL plan or unknown rule. */
+int64_t lat_snapshot_rows(const lat_plan *plan, lat_rule rule);
 
 /* Principal operators K^r = K^{s_r}(u^{s_r}) (eq. reducedbasis), full rule, in the principal
  * stack layout, for the cells S[0..n_r) (device int32 [cap], canonical ids; n_r <= cap is a
@@ -158,7 +171,7 @@ lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, 
                                 double *achieved, int32_t *dev_status, hipStream_t stream);
 
 /* lat_select_principal on the first `rows` snapshot rows only (1 <= rows <= n_snap): for snapshots
- * whose rows past `rows` are zero (LAT_RULE_MATERIAL fills n^d d^4 of them) the outputs equal those
+ * whose rows past `rows` are zero (lat_snapshot_rows of their rule) the outputs equal those
  * of lat_select_principal bit for bit (the chunk sums and pairwise trees take a zero chunk
  * exactly), at the cost of the rows read.  Rows past `rows` are neither read nor written; Z keeps
  * its [cap][n_snap] layout with zeros there. */

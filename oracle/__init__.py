@@ -26,7 +26,7 @@ _lib = None
 
 OK, E_INVERTED, E_NONFINITE, W_CAP = 0, 5, 6, 7
 RULE_FULL, RULE_REDUCED, RULE_MATERIAL, RULE_SAMPLED = 0, 1, 2, 3
-SAMPLE_STRIDE = 4          # node stride of the sampled-entry snapshots
+SAMPLE_STRIDE = 2          # node stride of the sampled-entry snapshots (every element has one corner there)
 
 
 def build(force: bool = True) -> str:

@@ -18,7 +18,8 @@ LIB_PATH = os.environ.get("LAT_LIBRARY") or os.path.join(_HERE, "liblat.so")
 
 (LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP, LAT_E_NOCONV,
  LAT_E_SINGULAR) = range(10)
-RULE_FULL, RULE_REDUCED, RULE_MATERIAL = 0, 1, 2
+RULE_FULL, RULE_REDUCED, RULE_MATERIAL, RULE_SAMPLED = 0, 1, 2, 3
+SAMPLE_STRIDE = 2
 F64, F32, BF16 = 0, 1, 2
 INFO_KEYS = ["dim", "nel", "ncells", "nloc", "nelem", "E", "nsnap", "ld", "ngroups", "npacked", "nglobal", "cap"]
 
@@ -72,6 +73,7 @@ def _lib():
             "lat_status_reset": (ctypes.c_int, [P, P]),
             "lat_dofmap": (ctypes.c_int, [P, P, P, P, P, P]),
             "lat_residual_tangent": (ctypes.c_int, [P, P, P, P, ctypes.c_int, P, P, P, P, P, P]),
+            "lat_snapshot_rows": (I64, [P, ctypes.c_int]),
             "lat_principal_ops": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P]),
             "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P]),
             "lat_select_principal_rows": (ctypes.c_int, [P, P, I64, F, I32, P, P, P, P, P, P, P, P, P, P]),
@@ -103,7 +105,7 @@ def _lib():
 def exported_symbols():
     """Names of the C entry points this binding uses (all declared in include/lat.h)."""
     return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_status_reset",
-            "lat_dofmap", "lat_residual_tangent", "lat_principal_ops", "lat_select_principal", "lat_select_principal_rows",
+            "lat_dofmap", "lat_residual_tangent", "lat_snapshot_rows", "lat_principal_ops", "lat_select_principal", "lat_select_principal_rows",
             "lat_apply_combo", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
@@ -194,6 +196,13 @@ class Plan:
                                         _ptr(out.get("energy")), _ptr(out.get("snap")), _ptr(out.get("plain")),
                                         _ptr(self.status_word), _stream()), "residual_tangent")
         return out
+
+    def snapshot_rows(self, rule):
+        """Leading snapshot rows the rule can make nonzero (the rest are zero)."""
+        n = int(_lib().lat_snapshot_rows(self._p, int(rule)))
+        if n < 0:
+            raise ValueError(f"unknown snapshot rule {rule}")
+        return n
 
     def principal_ops(self, u_global, mu, lam, S, n_r, parts=False, out=None):
         out = dict(out or {})

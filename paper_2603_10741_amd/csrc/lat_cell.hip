@@ -69,6 +69,7 @@ struct CellArgs {
     int n_r, cap;
     double *Kst;                // [(a*E+e)*cap + k]
     int32_t *st;
+    int nsa;                    // sampled rule: sub-grid nodes per axis
 };
 
 template <int DIM, int RULE, bool PRINCIPAL>
@@ -79,7 +80,14 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
     constexpr int NROW = DIM == 2 ? 2 : 1;       // tangent rows per thread
     const int nel = A.nel, nn = nel + 1;
     const int64_t ld = A.ld;
-    const int a = blockIdx.y;
+    // sampled rule: full-rule rows of the sub-grid node arow (every coordinate a multiple of the
+    // stride), written to snapshot row arow; otherwise arow is the node itself
+    const int arow = blockIdx.y;
+    int a = arow;
+    if (RULE == LAT_RULE_SAMPLED) {
+        const int nsa = A.nsa;
+        a = LAT_SAMPLE_STRIDE * ((arow % nsa) + nn * ((arow / nsa) % nsa) + (DIM == 3 ? nn * nn * (arow / (nsa * nsa)) : 0));
+    }
     // 3D: blockIdx.z = row i (3) x offset plane (3); a thread accumulates the 9 offsets of its
     // plane, which keeps the accumulators in registers (all 27 would spill)
     const int row0 = DIM == 2 ? 0 : (int)blockIdx.z / 3;
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
                 for (int j = 0; j < DIM; ++j) {
                     const int i = DIM == 2 ? r : row0;
                     const int ent = ((obase + o) * DIM + i) * DIM + j;
-                    A.T[((int64_t)a * E + ent) * ld + p] = acc[o][r][j];
+                    A.T[((int64_t)arow * E + ent) * ld + p] = acc[o][r][j];
                 }
     }
     if (A.ops) {
@@ -608,6 +616,18 @@ __global__ void k_zero_rows(int64_t n, double *__restrict__ y)
         y[j] = 0.0;
 }
 
+// zeros in the snapshot rows past `rows` (the greedy over all n_snap rows then sees the same data)
+lat_status zero_rows_past(const lat_plan *P, int64_t rows, double *snap, hipStream_t s)
+{
+    const int64_t rest = (P->nsnap - rows) * P->ld;
+    if (rest > 0) {
+        hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)std::min<int64_t>(lat_cdiv(rest, 256), 4096)), dim3(256), 0, s,
+                           rest, snap + rows * P->ld);
+        LAT_LAUNCH_CHECK();
+    }
+    return LAT_OK;
+}
+
 lat_status gather_u(const lat_plan *P, const double *u_global, int32_t *st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gather_u, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc), dim3(256), 0, s, P->dim,
@@ -620,12 +640,27 @@ lat_status gather_u(const lat_plan *P, const double *u_global, int32_t *st, hipS
 
 extern "C" {
 
+int64_t lat_snapshot_rows(const lat_plan *P, lat_rule rule)
+{
+    if (!P) return -1;
+    const int64_t d2 = (int64_t)P->dim * P->dim;
+    switch (rule) {
+    case LAT_RULE_FULL:
+    case LAT_RULE_REDUCED: return P->nsnap;
+    case LAT_RULE_MATERIAL: return P->nelem * d2 * d2;
+    case LAT_RULE_SAMPLED: return (int64_t)lat_ipow(P->nel / LAT_SAMPLE_STRIDE + 1, P->dim) * P->E;
+    default: return -1;
+    }
+}
+
 lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
                                 lat_rule snap_rule, double *f_int, double *energy, double *snap, double *plain_ops,
                                 int32_t *dev_status, hipStream_t stream)
 {
     if (!P || !u_global || !mu || !lam) return LAT_E_ARG;
-    if (snap_rule != LAT_RULE_FULL && snap_rule != LAT_RULE_REDUCED && snap_rule != LAT_RULE_MATERIAL) return LAT_E_ARG;
+    if (snap_rule != LAT_RULE_FULL && snap_rule != LAT_RULE_REDUCED && snap_rule != LAT_RULE_MATERIAL &&
+        snap_rule != LAT_RULE_SAMPLED)
+        return LAT_E_ARG;
     lat_status st = gather_u(P, u_global, dev_status, stream);
     if (st != LAT_OK) return st;
     CellArgs A = base_args(P);
@@ -653,11 +688,20 @@ lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const
         else
             hipLaunchKernelGGL(k_material_snap<3>, grid, dim3(256), 0, stream, P->nel, P->ld, P->keep_il, P->perm,
                                P->u_cil, mu, lam, snap, dev_status);
-        const int64_t rest = (P->nsnap - rows) * P->ld;
-        if (rest > 0)
-            hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)std::min<int64_t>(lat_cdiv(rest, 256), 4096)), dim3(256), 0,
-                               stream, rest, snap + rows * P->ld);
+        if ((st = zero_rows_past(P, rows, snap, stream)) != LAT_OK) return st;
+    }
+    if (snap && snap_rule == LAT_RULE_SAMPLED) {
+        CellArgs B = base_args(P);
+        B.mu = mu; B.lam = lam; B.matmode = 0; B.st = dev_status; B.T = snap;
+        B.nsa = P->nel / LAT_SAMPLE_STRIDE + 1;
+        const int64_t nsamp = lat_snapshot_rows(P, LAT_RULE_SAMPLED) / P->E;
+        const dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)nsamp, P->dim == 3 ? 9 : 1);
+        if (P->dim == 2)
+            hipLaunchKernelGGL((k_cell<2, LAT_RULE_SAMPLED, false>), grid, dim3(256), 0, stream, B);
+        else
+            hipLaunchKernelGGL((k_cell<3, LAT_RULE_SAMPLED, false>), grid, dim3(256), 0, stream, B);
         LAT_LAUNCH_CHECK();
+        if ((st = zero_rows_past(P, nsamp * P->E, snap, stream)) != LAT_OK) return st;
     }
     if (energy) {
         if ((st = lat_tree_reduce(P->w_part, P->nloc, P->ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;

@@ -1176,7 +1176,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
         o->cg_maxit < 1 || o->cg_check < 1 || (o->matvec != 0 && o->matvec != 1) ||
         (o->tangent != 0 && o->tangent != 1) || (o->precond != 0 && o->precond != 1) ||
-        (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED && o->snap_rule != LAT_RULE_MATERIAL) ||
+        (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED && o->snap_rule != LAT_RULE_MATERIAL &&
+         o->snap_rule != LAT_RULE_SAMPLED) ||
         !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
         !(o->armijo_c >= 0.0 && o->armijo_c < 1.0) || !(o->cg_tol > 0.0) || max_records < 0 ||
         (max_records > 0 && !records))
@@ -1245,8 +1246,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             int32_t hnr = 0;
             if (!full) {
                 NCHK(lat_status_reset(gst_d, s));
-                // material snapshots fill n^d d^4 rows; the greedy reads only those
-                const int64_t rows = rule == LAT_RULE_MATERIAL ? (int64_t)P->nelem * d * d * d * d : P->nsnap;
+                // the greedy reads only the rows the snapshot rule fills
+                const int64_t rows = lat_snapshot_rows(P, rule);
                 NCHK(lat_select_principal_rows(P, snap, rows, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R,
                                                nullptr, scal + 1, gst_d, s));
                 int32_t hg[2] = {0, 0};

@@ -158,7 +158,7 @@ def test_rom_solve_indefinite_matches_direct_solve(graded):
     assert rel(x, xo) <= 1e-5
 
 
-@pytest.mark.parametrize("rule", [O.RULE_FULL, O.RULE_REDUCED, O.RULE_MATERIAL])
+@pytest.mark.parametrize("rule", [O.RULE_FULL, O.RULE_REDUCED, O.RULE_MATERIAL, O.RULE_SAMPLED])
 def test_newton_matches_oracle(graded, rule):
     nc = graded
     u = nc.zeros_u()
@@ -354,17 +354,49 @@ def test_material_snapshots_match_oracle(which):
         assert int(g["n_r"].item()) == go["n_r"]
 
 
-def test_greedy_on_the_data_rows_is_bit_identical():
-    # material snapshots fill n^d d^4 rows; the greedy restricted to them returns the full sweep's
-    # outputs bit for bit
+@pytest.mark.parametrize("which", ["hole", "bcc"])
+def test_sampled_snapshots_are_the_full_rows_of_the_subgrid_nodes(which):
+    # snap_rule SAMPLED: the full-rule snapshot's rows of the stride-2 sub-grid nodes, bit for bit,
+    # zeros past them; against the oracle's selection of its own full-rule snapshots
+    from gpu_common import Case
+    cfg = L.config(0).with_(radius=(0.25, 0.35)) if which == "hole" else L.config(2).with_sub((2, 2, 2))
+    c = Case(cfg, m=1)
+    P = c.P
+    full = P.residual_tangent(c.ug, c.mu_t, c.lam_t, snap_rule=c.B.RULE_FULL, f=False, energy=False,
+                              snap=True)["snap"].view(P.nsnap, P.ld)
+    samp = P.residual_tangent(c.ug, c.mu_t, c.lam_t, snap_rule=c.B.RULE_SAMPLED, f=False, energy=False,
+                              snap=True)["snap"].view(P.nsnap, P.ld)
+    nodes = O.sampled_nodes(cfg.dim, cfg.nel)
+    E = P.E
+    rows = P.snapshot_rows(c.B.RULE_SAMPLED)
+    assert rows == len(nodes) * E
+    for j, a in enumerate(nodes):
+        assert torch.equal(samp[j * E:(j + 1) * E], full[a * E:(a + 1) * E]), (j, a)
+    assert not samp[rows:].any()
+    To = O.sampled_snapshots(cfg.dim, cfg.nel, c.orc["T"])
+    assert np.abs(c.canon_T(samp) - To).max() <= 1e-12 * np.abs(To).max()
+    code, _ = P.check_status(allow_cap=True)
+    assert code == c.B.LAT_OK
+    g = P.select_principal(c.to_cil_T(To), 1e-3, keep_Z=False, rows=rows)
+    go = O.greedy(To, 1e-3, cfg.cap, keep_Z=False)
+    assert int(g["n_r"].item()) == go["n_r"]
+    np.testing.assert_array_equal(g["S"].cpu().numpy()[:go["n_r"]], go["S"][:go["n_r"]])
+
+
+@pytest.mark.parametrize("rule", ["material", "sampled"])
+def test_greedy_on_the_data_rows_is_bit_identical(rule):
+    # material and sampled snapshots fill only their leading rows; the greedy restricted to them
+    # returns the full sweep's outputs bit for bit
     from gpu_common import Case
     cfg = L.config(0).with_(radius=(0.25, 0.35))
     c = Case(cfg, m=1)
     P = c.P
-    rows = cfg.n_elems * cfg.dim ** 4
+    code = c.B.RULE_MATERIAL if rule == "material" else c.B.RULE_SAMPLED
+    rows = P.snapshot_rows(code)
+    assert rows == (cfg.n_elems * cfg.dim ** 4 if rule == "material" else (cfg.nel // 2 + 1) ** 2 * P.E)
     outs = []
     for r in (None, rows):
-        snap = P.residual_tangent(c.ug, c.mu_t, c.lam_t, snap_rule=c.B.RULE_MATERIAL, f=False, energy=False,
+        snap = P.residual_tangent(c.ug, c.mu_t, c.lam_t, snap_rule=code, f=False, energy=False,
                                   snap=True)["snap"]
         g = P.select_principal(snap, 1e-3, keep_Z=True, rows=r)
         outs.append({k: v.cpu().numpy() for k, v in g.items()} | {"delta": snap.cpu().numpy()})

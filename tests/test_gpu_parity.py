@@ -132,6 +132,18 @@ def test_applies(case):
 
 
 def test_combo_adjoint_forms_and_lame(case):
+    _check_combo_adjoint(case)
+
+
+@pytest.mark.parametrize("mk", [lambda: L.config(2).with_sub((4, 4, 3)), lambda: L.config(1).with_sub((6, 6))],
+                         ids=["bcc_48", "hole_36"])
+def test_combo_adjoint_wide_basis(mk):
+    # N_r in (32, 64]: the widest contraction tiles of the adjoint forms
+    case = Case(mk().with_(tol=1e-13, cap=64))
+    assert _check_combo_adjoint(case) > 32
+
+
+def _check_combo_adjoint(case):
     P, cfg = case.P, case.cfg
     o = case.orc
     go = O.greedy(o["T"], cfg.tol, cfg.cap, keep_Z=False)
@@ -155,6 +167,7 @@ def test_combo_adjoint_forms_and_lame(case):
     for k, s in enumerate(go["S"][:n_r]):
         mub[s] = np.sum(go["alpha"][:, k] * Gm[:, k])
     assert rel(ad["mu_bar"].cpu().numpy(), mub) <= 1e-10
+    return n_r
 
 
 def test_residual_adjoint(case):
