@@ -16,31 +16,46 @@
 namespace {
 
 // q_i, v_i per lane (plan order), written to qv[0][p][cap], qv[1][p][cap]
-__global__ void k_aa_solve(int64_t ld, int cap, int n_r, const int32_t *__restrict__ perm,
-                           const double *__restrict__ R, const double *__restrict__ abar,
-                           double *__restrict__ qv)
+// NR = the plan's cap: every index below is a compile-time constant, so q stays in registers; v
+// overwrites q in place (entry k of the backward pass reads only entries above k, already final).
+template <int NR>
+__global__ __launch_bounds__(256) void k_aa_solve(int64_t ld, int n_r, const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ R, const double *__restrict__ abar,
+                                                  double *__restrict__ qv)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ld) return;
     const int c = perm[p];
-    double q[LAT_MAX_CAP], v[LAT_MAX_CAP];
-    for (int k = 0; k < LAT_MAX_CAP; ++k) { q[k] = 0.0; v[k] = 0.0; }
+    double q[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) q[k] = 0.0;
     if (c >= 0) {
-        for (int k = 0; k < n_r; ++k) {                 // R^T q = abar (forward)
-            double acc = abar[(int64_t)c * cap + k];
-            for (int l = 0; l < k; ++l) acc = fma(-R[l * cap + k], q[l], acc);
-            q[k] = acc / R[k * cap + k];
-        }
-        for (int k = n_r - 1; k >= 0; --k) {            // R v = q (backward)
-            double acc = q[k];
-            for (int l = k + 1; l < n_r; ++l) acc = fma(-R[k * cap + l], v[l], acc);
-            v[k] = acc / R[k * cap + k];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {                  // R^T q = abar (forward)
+            if (k < n_r) {
+                double acc = abar[(int64_t)c * NR + k];
+#pragma unroll
+                for (int l = 0; l < k; ++l) acc = fma(-R[l * NR + k], q[l], acc);
+                q[k] = acc / R[k * NR + k];
+            }
         }
     }
-    for (int k = 0; k < cap; ++k) {
-        qv[p * cap + k] = q[k];
-        qv[(ld + p) * cap + k] = v[k];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) qv[p * NR + k] = q[k];
+    if (c >= 0) {
+#pragma unroll
+        for (int k = NR - 1; k >= 0; --k) {             // R v = q (backward)
+            if (k < n_r) {
+                double acc = q[k];
+#pragma unroll
+                for (int l = k + 1; l < NR; ++l)
+                    if (l < n_r) acc = fma(-R[k * NR + l], q[l], acc);
+                q[k] = acc / R[k * NR + k];
+            }
+        }
     }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) qv[(ld + p) * NR + k] = q[k];
 }
 
 // U[j][k] = Z[k][j] (k < n_r), 0 beyond
@@ -316,7 +331,15 @@ extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, 
     const int64_t ld = P->ld, cap = P->cap;
     const dim3 lg((unsigned)lat_cdiv(ld, 256)), sg((unsigned)lat_cdiv(P->nsnap, 256));
     double *Am = P->aa_A, *Al = P->aa_A + ld * cap, *Bm = P->aa_B, *Bl = P->aa_B + ld * cap;
-    hipLaunchKernelGGL(k_aa_solve, lg, dim3(256), 0, stream, ld, (int)cap, n_r, P->perm, R, alpha_bar, P->aa_q);
+#define SOLVE(NRV) hipLaunchKernelGGL(k_aa_solve<NRV>, lg, dim3(256), 0, stream, ld, n_r, P->perm, R, alpha_bar, P->aa_q)
+    switch (cap) {
+    case 8: SOLVE(8); break;
+    case 16: SOLVE(16); break;
+    case 32: SOLVE(32); break;
+    case 64: SOLVE(64); break;
+    default: return LAT_E_SHAPE;
+    }
+#undef SOLVE
     LAT_LAUNCH_CHECK();
     lat_status st;
     // A = Z^T T^mu, Z^T T^lam
@@ -327,10 +350,26 @@ extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, 
     // B = Delta^T T^mu_S, Delta^T T^lam_S
     hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_mu, P->aa_gath);
     LAT_LAUNCH_CHECK();
-    if ((st = contract(P, n_r, delta, P->aa_gath, Bm, stream)) != LAT_OK) return st;
-    hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_lam, P->aa_gath);
-    LAT_LAUNCH_CHECK();
-    if ((st = contract(P, n_r, delta, P->aa_gath, Bl, stream)) != LAT_OK) return st;
+    if (n_r <= 32 && cap >= 16 && P->w_forms && P->wf_part) {
+        // one pass over Delta for both: the second gathered set goes to the forms workspace
+        // ([n_snap][ld] >= [n_snap][cap], free between calls on the plan's stream order)
+        double *gath2 = P->w_forms;
+        hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_lam,
+                           gath2);
+        LAT_LAUNCH_CHECK();
+        const int64_t ldc = ld * cap;
+        const double *U2[2] = {P->aa_gath, gath2};
+        double *parts[2] = {P->wf_part, P->wf_part + P->aa_nchunk * ldc};
+        if ((st = lat_contract_rows_multi(P, n_r, delta, U2, 2, parts, stream)) != LAT_OK) return st;
+        if ((st = lat_tree_reduce(parts[0], P->aa_nchunk, ldc, 0, Bm, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        if ((st = lat_tree_reduce(parts[1], P->aa_nchunk, ldc, 0, Bl, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+    } else {
+        if ((st = contract(P, n_r, delta, P->aa_gath, Bm, stream)) != LAT_OK) return st;
+        hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_lam,
+                           P->aa_gath);
+        LAT_LAUNCH_CHECK();
+        if ((st = contract(P, n_r, delta, P->aa_gath, Bl, stream)) != LAT_OK) return st;
+    }
     hipLaunchKernelGGL(k_aa_cellterm, lg, dim3(256), 0, stream, ld, (int)cap, n_r, P->perm, P->aa_q, Am, Al, mu_bar,
                        lam_bar);
     hipLaunchKernelGGL(k_aa_principal, dim3((unsigned)n_r), dim3(256), 0, stream, P->ncells, ld, (int)cap, n_r, S, P->lane,
