@@ -295,10 +295,13 @@ __global__ void k_build_R(int cap, int pcap, const int32_t *__restrict__ ictl, c
 
 // alpha^s: R alpha = nu_s beta^s by back-substitution from the last row (fma order
 // acc = fma(-R[k][l], alpha_l, acc) for l = k+1 .. n_r-1); outputs in canonical order.
-__global__ void k_alpha(int64_t ld, int cap, int pcap, const int32_t *__restrict__ ictl,
-                        const int32_t *__restrict__ perm, const double *__restrict__ R,
-                        const double *__restrict__ nu_pl, const double *__restrict__ beta_pl,
-                        double *__restrict__ alpha, double *__restrict__ beta, double *__restrict__ nu)
+// NR = the plan's cap: every index is a compile-time constant, so alpha stays in registers.
+template <int NR>
+__global__ __launch_bounds__(256) void k_alpha(int64_t ld, int pcap, const int32_t *__restrict__ ictl,
+                                               const int32_t *__restrict__ perm, const double *__restrict__ R,
+                                               const double *__restrict__ nu_pl, const double *__restrict__ beta_pl,
+                                               double *__restrict__ alpha, double *__restrict__ beta,
+                                               double *__restrict__ nu)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ld) return;
@@ -306,16 +309,23 @@ __global__ void k_alpha(int64_t ld, int cap, int pcap, const int32_t *__restrict
     if (c < 0) return;
     const int nr = ictl[C_NR];
     const double n = nu_pl[p];
-    double a[LAT_MAX_CAP];
-    for (int k = 0; k < LAT_MAX_CAP; ++k) a[k] = 0.0;
-    for (int k = nr - 1; k >= 0; --k) {
-        double acc = n * beta_pl[p * pcap + k];
-        for (int l = k + 1; l < nr; ++l) acc = fma(-R[k * cap + l], a[l], acc);
-        a[k] = acc / R[k * cap + k];
+    double a[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) a[k] = 0.0;
+#pragma unroll
+    for (int k = NR - 1; k >= 0; --k) {
+        if (k < nr) {
+            double acc = n * beta_pl[p * pcap + k];
+#pragma unroll
+            for (int l = k + 1; l < NR; ++l)
+                if (l < nr) acc = fma(-R[k * NR + l], a[l], acc);
+            a[k] = acc / R[k * NR + k];
+        }
     }
-    for (int k = 0; k < cap; ++k) {
-        alpha[(int64_t)c * cap + k] = a[k];
-        if (beta) beta[(int64_t)c * cap + k] = k < nr ? beta_pl[p * pcap + k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        alpha[(int64_t)c * NR + k] = a[k];
+        if (beta) beta[(int64_t)c * NR + k] = k < nr ? beta_pl[p * pcap + k] : 0.0;
     }
     if (nu) nu[c] = n;
 }
@@ -423,8 +433,16 @@ extern "C" lat_status lat_select_principal_rows(const lat_plan *P, double *snap,
     // R, alpha (canonical order), beta, nu, achieved
     hipLaunchKernelGGL(k_build_R, dim3((unsigned)P->cap), dim3(64), 0, stream, P->cap, P->cap, P->ictl, S, P->lane,
                        P->v_nu, P->beta_pl, R);
-    hipLaunchKernelGGL(k_alpha, lg, dim3(256), 0, stream, ld, P->cap, P->cap, P->ictl, P->perm, R, P->v_nu, P->beta_pl,
-                       alpha, beta, nu);
+#define ALPHA(NRV) hipLaunchKernelGGL(k_alpha<NRV>, lg, dim3(256), 0, stream, ld, P->cap, P->ictl, P->perm, R, P->v_nu, \
+                                    P->beta_pl, alpha, beta, nu)
+    switch (P->cap) {
+    case 8: ALPHA(8); break;
+    case 16: ALPHA(16); break;
+    case 32: ALPHA(32); break;
+    case 64: ALPHA(64); break;
+    default: return LAT_E_SHAPE;
+    }
+#undef ALPHA
     hipLaunchKernelGGL(k_achieved, dim3(1), dim3(64), 0, stream, P->dctl, achieved);
     LAT_LAUNCH_CHECK();
     return LAT_OK;
