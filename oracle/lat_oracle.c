@@ -24,7 +24,7 @@
  *   Gauss-Legendre quadrature: eq. (fullquadraturerule) and eq. (snapshots);
  *   greedy: Algorithm 1 (Sec. 3.2.2); coefficients: the least-squares formula of Sec. 3.2.2;
  *   ROM operator: eq. (romstiffnessmatrix).
- * Readings where the paper is silent are listed in the design doc of the repository.
+ * Where the paper leaves a choice open, the choice taken is stated at the function that makes it.
  *
  * Compiled with -ffp-contract=off: every fused multiply-add below is an explicit fma().
  */
