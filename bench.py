@@ -227,6 +227,13 @@ def main():
     alg_bytes = 16.0 * dofs_rhs + 8.0 * P.ncells * n_r + 8.0 * P.nloc * P.E * n_r
     achieved = alg_bytes / t_apply / 1e9
     traffic = measured_traffic(cfg.name)
+    # the whole reverse-mode stage against the bytes the method has to move once: X and Ybar read
+    # and Xbar written (24 B per active DOF and RHS), the three principal stacks and alpha, the
+    # greedy's Delta and both snapshot parts (3 x 8 B per snapshot entry per cell) with Z, and the
+    # residual adjoint's cotangent read and local result written
+    t_adj = ms_stage["adjoint"] * 1e-3
+    adj_bytes = (24.0 * dofs_rhs + 3 * 8.0 * P.nloc * P.E * n_r + 8.0 * P.ncells * n_r
+                 + 3 * 8.0 * P.nsnap * P.ncells + 8.0 * n_r * P.nsnap + 2 * 8.0 * P.nloc * cfg.dim * P.ncells)
 
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 8
@@ -310,6 +317,11 @@ def main():
                      "kernel": ("k_apply2d_rw<2,32,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
                      + " (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(alg_bytes)},
         "cpu_baseline": cpu,
+        "adjoint_roofline": {"bound": "hbm", "achieved": round(adj_bytes / t_adj / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(adj_bytes / t_adj / 1e9 / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes": int(adj_bytes), "ms": round(ms_stage["adjoint"], 4),
+                             "stage": "ROM apply adjoint (Xbar, alpha_bar, mu/lam through the principal "
+                                      "tangents) + coefficient adjoint + residual adjoint"},
         "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
         "rom_over_plain_speedup": round(t_plain / t_apply, 3),
         "reduced_precision": {"kernel": ("k_apply2d_rw" if cfg.dim == 2 else "k_apply3d_mfma")
