@@ -98,16 +98,34 @@ def _check(d, m):
     assert rel(Yp, Ypo) <= 1e-10
 
 
+def _check_sampled(d):
+    # sampled-entry snapshots at full size: the full-rule rows of the sub-grid nodes, bit for bit,
+    # zeros past them
+    from paper_2603_10741_amd import binding as B
+    P, cfg = d["P"], d["cfg"]
+    samp = P.residual_tangent(d["ug"], d["mu_t"], d["lam_t"], snap_rule=B.RULE_SAMPLED, f=False, energy=False,
+                              snap=True)["snap"].view(P.nsnap, P.ld)
+    full = d["T0"].view(P.nsnap, P.ld)
+    nodes = O.sampled_nodes(cfg.dim, cfg.nel)
+    rows = len(nodes) * P.E
+    assert rows == P.snapshot_rows(B.RULE_SAMPLED)
+    idx = torch.tensor([a * P.E + e for a in nodes for e in range(P.E)], dtype=torch.int64, device=d["dev"])
+    assert torch.equal(samp[:rows], full[idx])
+    assert not samp[rows:].any()
+
+
 def test_bcc_10x10x10_full():
     cfg = L.config(2)
     d = _run_full(cfg, cfg.m)
     _check(d, cfg.m)
+    _check_sampled(d)
 
 
 def test_hole_32x32_full():
     cfg = L.config(1)
     d = _run_full(cfg, cfg.m)
     _check(d, cfg.m)
+    _check_sampled(d)
 
 
 def test_mixed_20x20x20_full():
