@@ -92,6 +92,19 @@ def _check(d, m):
     alpha = g["alpha"].cpu().numpy()
     Yo = O.combo_apply(dim, nel, Kp, alpha[sample], d["l2g"][sample], X[sample])
     assert rel(Y, Yo) <= 1e-10
+    # reverse mode in the benchmark's configuration (X, Ybar, the three principal stacks): Xbar and
+    # alpha_bar of the sampled cells against the oracle, cell by cell
+    parts = P.principal_ops(d["ug"], d["mu_t"], d["lam_t"], g["S"], n_r, parts=True)
+    Yb = L.make_rhs(cfg, m=m, stream=1)
+    Ybp = P.pack(torch.from_numpy(Yb).to(d["dev"]), m)
+    ad = P.apply_combo_adjoint(parts["K"], n_r, g["alpha"], Xp, Ybp, m, K_mu=parts["K_mu"], K_lam=parts["K_lam"],
+                               S=g["S"])
+    Xb = P.unpack(ad["Xbar"], m)[idx].cpu().numpy()
+    Xbo = O.combo_apply(dim, nel, Kp, alpha[sample], d["l2g"][sample], Yb[sample], transpose=True)
+    assert rel(Xb, Xbo) <= 1e-10
+    Go = O.combo_forms(dim, nel, Kp, cfg.cap, d["l2g"][sample], X[sample], Yb[sample])
+    assert rel(ad["alpha_bar"][idx].cpu().numpy(), Go) <= 1e-10
+    del parts, ad
     Ks = np.stack([O.cell_eval(dim, nel, d["keep"][c], d["uloc_s"][t], d["mu"][c], d["lam"][c])["stencil"]
                    for t, c in enumerate(sample)])
     Ypo = O.plain_apply(dim, nel, Ks, d["l2g"][sample], X[sample])
