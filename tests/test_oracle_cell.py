@@ -244,3 +244,122 @@ def test_workload_cells_converge_under_fd(orc):
     fm = orc.cell_eval(2, cfg.nel, keep[c], uloc[c] - h * v, 1.0, 10.0)["f"]
     Kv = r["K"] @ v.ravel()
     assert np.linalg.norm(Kv - ((fp - fm) / (2 * h)).ravel()) <= 1e-7 * np.linalg.norm(Kv)
+
+
+# ---------------------------------------------------------------------------------------------
+# One-point (reduced) quadrature, the snapshot rule with fewer points per direction of
+# eq. (snapshots): one point at the element centre with weight 1 (times h^d).  Pinned without
+# the oracle's own formulas: the weight by closed forms that hold for any point, the point by
+# the textbook centroid B-matrix stiffness and by the centroid stress written out here, the
+# tangent's consistency by finite differences of the one-point force, and the rank deficiency
+# (hourglass modes) that every one-point Q1 element has.
+def _centroid_grads(dim, h):
+    """g_c = grad_X N_c at the element centre: the axis factor is -+1/h, the others 1/2."""
+    nc = 2 ** dim
+    g = np.zeros((nc, dim))
+    for c in range(nc):
+        for ax in range(dim):
+            g[c, ax] = (1.0 if (c >> ax) & 1 else -1.0) / h * 0.5 ** (dim - 1)
+    return g
+
+
+def _piola(F3, mu, lam):
+    Fit = np.linalg.inv(F3).T
+    lnJ = np.log(np.linalg.det(F3))
+    return mu * (F3 - Fit) + lam * lnJ * Fit
+
+
+@pytest.mark.parametrize("dim,nel", [(2, 6), (3, 3)])
+def test_reduced_rule_homogeneous_energy_closed_form(orc, dim, nel):
+    # homogeneous F: the one point sees F, so Pi = W(F) n_kept h^d -- fixes the weight (1)
+    keep, _ = _cell(dim, nel, seed=21)
+    rng = np.random.default_rng(23)
+    Fd = np.eye(dim) + 0.1 * rng.standard_normal((dim, dim))
+    u = _node_coords(dim, nel) @ (Fd - np.eye(dim)).T
+    mu, lam = 0.9, 4.0
+    r = orc.cell_eval(dim, nel, keep, u, mu, lam, rule=orc.RULE_REDUCED)
+    F3 = np.eye(3); F3[:dim, :dim] = Fd
+    J = np.linalg.det(F3)
+    W = 0.5 * mu * (np.sum(F3 ** 2) - 3) - mu * np.log(J) + 0.5 * lam * np.log(J) ** 2
+    assert abs(r["energy"] - W * keep.sum() / nel ** dim) < 1e-14 * abs(W) * keep.sum()
+
+
+@pytest.mark.parametrize("dim,nel", [(2, 6), (3, 3)])
+def test_reduced_rule_affine_force_equals_full_rule(orc, dim, nel):
+    # affine u: P is constant and the corner gradients are linear in the other coordinates, so
+    # one centre point integrates P g_a exactly -- equal to the 2^d-point force
+    keep, _ = _cell(dim, nel, seed=25)
+    rng = np.random.default_rng(27)
+    Fd = np.eye(dim) + 0.08 * rng.standard_normal((dim, dim))
+    u = _node_coords(dim, nel) @ (Fd - np.eye(dim)).T + 0.01
+    r1 = orc.cell_eval(dim, nel, keep, u, 1.0, 5.0, rule=orc.RULE_REDUCED)
+    r2 = orc.cell_eval(dim, nel, keep, u, 1.0, 5.0, rule=orc.RULE_FULL)
+    np.testing.assert_allclose(r1["f"], r2["f"], rtol=0, atol=1e-13 * np.abs(r2["f"]).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reduced_rule_reference_tangent_is_centroid_B_matrix(orc, dim):
+    # u = 0: one-point stiffness = h^d B(centroid)^T D B(centroid), D isotropic Hooke
+    nel = 1
+    h = 1.0
+    mu, lam = 1.0, 10.0 if dim == 2 else 5.0
+    r = orc.cell_eval(dim, nel, np.ones(1, np.uint8), np.zeros((2 ** dim, dim)), mu, lam, rule=orc.RULE_REDUCED,
+                      dense=True)
+    g = _centroid_grads(dim, h)
+    nstr = 3 if dim == 2 else 6
+    D = np.zeros((nstr, nstr))
+    D[:dim, :dim] = lam
+    for i in range(dim):
+        D[i, i] += 2 * mu
+    for k in range(dim, nstr):
+        D[k, k] = mu
+    B = np.zeros((nstr, dim * 2 ** dim))
+    for a in range(2 ** dim):
+        if dim == 2:
+            B[0, 2 * a] = g[a, 0]; B[1, 2 * a + 1] = g[a, 1]; B[2, 2 * a] = g[a, 1]; B[2, 2 * a + 1] = g[a, 0]
+        else:
+            for ax in range(3):
+                B[ax, 3 * a + ax] = g[a, ax]
+            B[3, 3 * a + 1] = g[a, 2]; B[3, 3 * a + 2] = g[a, 1]
+            B[4, 3 * a + 0] = g[a, 2]; B[4, 3 * a + 2] = g[a, 0]
+            B[5, 3 * a + 0] = g[a, 1]; B[5, 3 * a + 1] = g[a, 0]
+    Kt = h ** dim * B.T @ D @ B
+    np.testing.assert_allclose(r["K"], Kt, atol=1e-13 * np.abs(Kt).max())
+    # one point leaves the hourglass modes in the kernel: rank = (3 or 6) strain components
+    sv = np.linalg.svd(r["K"], compute_uv=False)
+    assert int(np.sum(sv > 1e-12 * sv[0])) == nstr
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reduced_rule_force_is_centroid_stress(orc, dim):
+    # one element, non-affine u: f_c = h^d P(F(centroid)) g_c(centroid)
+    nel = 1
+    h = 1.0
+    rng = np.random.default_rng(29)
+    u = 0.05 * rng.standard_normal((2 ** dim, dim))
+    mu, lam = 1.2, 3.0
+    r = orc.cell_eval(dim, nel, np.ones(1, np.uint8), u, mu, lam, rule=orc.RULE_REDUCED)
+    g = _centroid_grads(dim, h)
+    F3 = np.eye(3)
+    F3[:dim, :dim] += u.T @ g
+    P = _piola(F3, mu, lam)[:dim, :dim]
+    f = h ** dim * g @ P.T                      # f[c, i] = sum_J P_iJ g_cJ
+    np.testing.assert_allclose(r["f"], f, rtol=0, atol=1e-14 * np.abs(f).max())
+
+
+@pytest.mark.parametrize("dim,nel", [(2, 5), (3, 3)])
+def test_reduced_rule_tangent_is_force_jacobian(orc, dim, nel):
+    keep, u = _cell(dim, nel, seed=31)
+    mu, lam = 1.0, 5.0
+    R = orc.RULE_REDUCED
+    r = orc.cell_eval(dim, nel, keep, u, mu, lam, rule=R, dense=True)
+    act = _active(dim, nel, keep)
+    v = np.random.default_rng(33).standard_normal(u.shape) * act[:, None]
+    h = 1e-6
+    fp = orc.cell_eval(dim, nel, keep, u + h * v, mu, lam, rule=R)["f"]
+    fm = orc.cell_eval(dim, nel, keep, u - h * v, mu, lam, rule=R)["f"]
+    Kv = r["K"] @ v.ravel()
+    assert np.linalg.norm(Kv - ((fp - fm) / (2 * h)).ravel()) <= 1e-7 * np.linalg.norm(Kv)
+    # and the one-point tangent is not the full-rule one (the rule is really in use)
+    rf = orc.cell_eval(dim, nel, keep, u, mu, lam, rule=orc.RULE_FULL, dense=True)
+    assert np.linalg.norm(rf["K"] - r["K"]) > 1e-3 * np.linalg.norm(rf["K"])
