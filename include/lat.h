@@ -20,11 +20,23 @@
  *   - Every call is enqueued on the given HIP stream and returns without waiting, unless
  *     stated otherwise.  Argument and shape errors are detected on the host and returned
  *     synchronously; nothing is enqueued then.
- *   - Data-dependent failures (an inverted element, a non-finite value) are written to a
- *     caller-provided device status word `dev_status` int32[2] = {code, first bad cell}
- *     (initialise it with lat_status_reset); the caller reads it after synchronising.
- *   - A plan owns immutable tables and a scratch workspace; calls on one plan must not
- *     overlap in time (use one stream per plan, or synchronise).
+ *   - Data-dependent failures (an inverted element, a non-finite value) and the greedy's cap
+ *     warning are written to a caller-provided device status word `dev_status` int32[2] =
+ *     {code, first bad cell} (initialise it with lat_status_reset); the caller reads it after
+ *     synchronising.  The code word keeps the most severe code raised since the reset: LAT_OK,
+ *     then LAT_W_CAP, then any error (LAT_E_INVERTED < LAT_E_NONFINITE), so a later warning never
+ *     hides an error; the cell word keeps the lowest canonical id of a cell that raised an error
+ *     (INT32_MAX when none did).
+ *   - Scratch.  A plan owns immutable tables and a default scratch workspace.  Every stream-ordered
+ *     call that needs scratch takes `work` / `work_bytes`: a caller device buffer (256-byte
+ *     aligned) of at least the call's minimum size from lat_plan_query, or NULL for the plan's
+ *     default workspace.  Calls with NULL work on one plan must not overlap in time (one stream
+ *     per plan, or synchronise); calls with distinct caller workspaces may run concurrently on
+ *     different streams.  The library keeps no pointer to `work` after the call's kernels end.
+ *     A workspace of the "fast" size enables the faster variants named at each call.
+ *   - Principal-cell arrays: every array documented below as [..][cap] or [cap] uses the PLAN's
+ *     cap as its stride, i.e. LAT_INFO_CAP from lat_plan_info (the cap given to lat_plan_create
+ *     rounded up to a power of two >= 8), whatever cap a later call passes.
  *   - Indices are 0-based.  Geometry: cell edge 1, n Q1 elements per cell axis, h = 1/n;
  *     element e = ex + n(ey + n ez); local node a = ix + (n+1)(iy + (n+1) iz); element
  *     corners x-fastest; cells numbered x-fastest over the lattice ("canonical" order).
@@ -80,6 +92,18 @@ typedef enum { LAT_F64 = 0, LAT_F32 = 1, LAT_BF16 = 2 } lat_prec;
 
 typedef struct lat_plan lat_plan;
 
+/* The calls that take a caller workspace (index of lat_plan_query's arrays). */
+typedef enum {
+    LAT_CALL_RESIDUAL_TANGENT = 0,   /* lat_residual_tangent */
+    LAT_CALL_PRINCIPAL_OPS = 1,      /* lat_principal_ops */
+    LAT_CALL_SELECT_PRINCIPAL = 2,   /* lat_select_principal, lat_select_principal_rows */
+    LAT_CALL_APPLY_COMBO = 3,        /* lat_apply_combo */
+    LAT_CALL_APPLY_COMBO_ADJOINT = 4,/* lat_apply_combo_adjoint */
+    LAT_CALL_ALPHA_ADJOINT = 5,      /* lat_alpha_adjoint */
+    LAT_CALL_RESIDUAL_ADJOINT = 6,   /* lat_residual_adjoint */
+    LAT_CALL_N = 7
+} lat_call;
+
 enum {
     LAT_INFO_DIM = 0, LAT_INFO_NEL, LAT_INFO_NCELLS, LAT_INFO_NLOC, LAT_INFO_NELEM, LAT_INFO_E,
     LAT_INFO_NSNAP, LAT_INFO_LD, LAT_INFO_NGROUPS, LAT_INFO_NPACKED, LAT_INFO_NGLOBAL, LAT_INFO_CAP,
@@ -91,7 +115,8 @@ const char *lat_status_string(lat_status s);
 
 /* Builds a plan for a lattice of ncell[0] x ncell[1] (x ncell[2]) congruent cells of
  * nel^dim Q1 elements.  keep_host: HOST uint8 [N_s][nel^dim], 1 = element kept.
- * cap: maximum number of principal cells any later call will use (1..64).
+ * cap: maximum number of principal cells any later call will use (1..64); the plan rounds it up
+ * to a power of two >= 8 (LAT_INFO_CAP), the stride of every principal-cell array.
  * Runs the DOF-map kernels (active nodes, global numbering, local-to-global maps;
  * eq. residualvector) on `stream`, then derives the plan's lane grouping and packed
  * layout on the host.  Synchronises `stream`.  Allocates device memory.
@@ -101,6 +126,12 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
 lat_status lat_plan_destroy(lat_plan *plan);
 /* info: HOST int64[LAT_INFO_N], filled with the sizes above. */
 lat_status lat_plan_info(const lat_plan *plan, int64_t *info);
+
+/* Workspace sizes in bytes of every call that takes one (HOST size_t[LAT_CALL_N] each, either may
+ * be NULL): min_bytes[c] is the least `work_bytes` call c accepts (below it the call returns
+ * LAT_E_SHAPE), fast_bytes[c] >= min_bytes[c] the size from which the call's faster variant runs.
+ * The sizes depend on the plan only. */
+lat_status lat_plan_query(const lat_plan *plan, size_t *min_bytes, size_t *fast_bytes);
 
 /* Writes {LAT_OK, INT32_MAX} to the device status word. */
 lat_status lat_status_reset(int32_t *dev_status, hipStream_t stream);
@@ -133,10 +164,12 @@ lat_status lat_dofmap(const lat_plan *plan, int32_t *l2g, int32_t *n_active, int
  *                      zeros past them; those rows equal the FULL snapshot's rows of the same node
  *                      bit for bit
  *   plain_ops packed   every cell's full-rule tangent in stencil form (for lat_apply_plain)
- * Errors J <= 0 / non-finite go to dev_status. */
+ * Errors J <= 0 (LAT_E_INVERTED) / a non-finite displacement or Jacobian (LAT_E_NONFINITE) go to
+ * dev_status with the cell; the outputs of such a cell are then undefined.
+ * work: LAT_CALL_RESIDUAL_TANGENT workspace or NULL (see the conventions). */
 lat_status lat_residual_tangent(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
                                 lat_rule snap_rule, double *f_int, double *energy, double *snap, double *plain_ops,
-                                int32_t *dev_status, hipStream_t stream);
+                                int32_t *dev_status, void *work, size_t work_bytes, hipStream_t stream);
 
 /* Number of leading snapshot rows that `rule` can make nonzero (the rest of the n_snap rows are
  * zero): n_snap for FULL / REDUCED, n^d d^4 for MATERIAL, ((n / LAT_SAMPLE_STRIDE) + 1)^d 3^d d^2 for
@@ -146,10 +179,11 @@ int64_t lat_snapshot_rows(const lat_plan *plan, lat_rule rule);
 /* Principal operators K^r = K^{s_r}(u^{s_r}) (eq. reducedbasis), full rule, in the principal
  * stack layout, for the cells S[0..n_r) (device int32 [cap], canonical ids; n_r <= cap is a
  * HOST value).  K = mu K_mu + lam K_lam at fixed u; K_mu / K_lam (may be NULL) receive those
- * parts, for the adjoint.  Slots k >= n_r are zeroed. */
+ * parts, for the adjoint.  Slots k >= n_r are zeroed.  LAT_E_SHAPE when n_r > LAT_INFO_CAP.
+ * work: LAT_CALL_PRINCIPAL_OPS workspace or NULL. */
 lat_status lat_principal_ops(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
                              const int32_t *S, int32_t n_r, double *K, double *K_mu, double *K_lam,
-                             int32_t *dev_status, hipStream_t stream);
+                             int32_t *dev_status, void *work, size_t work_bytes, hipStream_t stream);
 
 /* Greedy selection of principal cells (Algorithm 1) on the snapshot matrix `snap` (CIL(E),
  * overwritten by the residuals Delta), tolerance tol > 0, at most cap <= plan cap selections.
@@ -165,10 +199,13 @@ lat_status lat_principal_ops(const lat_plan *plan, const double *u_global, const
  *   R        f64 [cap][cap]   R[j][k] = nu_{s_k} beta_j^{s_k}, j <= k
  *   Z        f64 [cap][n_snap] orthonormal basis zeta_i                   (may be NULL)
  *   achieved f64 [1]          max_s ||Delta^s||_inf at exit
- * LAT_W_CAP goes to dev_status when the cap stops the loop above tol. */
+ * LAT_W_CAP goes to dev_status when the cap stops the loop above tol.  The arrays' cap dimension is
+ * the plan's LAT_INFO_CAP; the argument cap (1..LAT_INFO_CAP, else LAT_E_SHAPE) only limits the
+ * number of selections.  work: LAT_CALL_SELECT_PRINCIPAL workspace or NULL. */
 lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, int32_t cap, int32_t *S,
                                 int32_t *n_r, double *alpha, double *beta, double *nu, double *R, double *Z,
-                                double *achieved, int32_t *dev_status, hipStream_t stream);
+                                double *achieved, int32_t *dev_status, void *work, size_t work_bytes,
+                                hipStream_t stream);
 
 /* lat_select_principal on the first `rows` snapshot rows only (1 <= rows <= n_snap): for snapshots
  * whose rows past `rows` are zero (lat_snapshot_rows of their rule) the outputs equal those
@@ -177,27 +214,36 @@ lat_status lat_select_principal(const lat_plan *plan, double *snap, double tol, 
  * its [cap][n_snap] layout with zeros there. */
 lat_status lat_select_principal_rows(const lat_plan *plan, double *snap, int64_t rows, double tol, int32_t cap,
                                      int32_t *S, int32_t *n_r, double *alpha, double *beta, double *nu, double *R,
-                                     double *Z, double *achieved, int32_t *dev_status, hipStream_t stream);
+                                     double *Z, double *achieved, int32_t *dev_status, void *work,
+                                     size_t work_bytes, hipStream_t stream);
 
 /* ROM apply (eq. romstiffnessmatrix): Y_i = M_i (sum_k alpha_ik K_k) M_i X_i for every cell at
  * once, M_i the active-DOF mask of cell i.  K: a stack of n_r stencils in the principal stack
  * layout (cap slots) -- the principal tangents from lat_principal_ops with alpha the RB
  * coefficients, or the greedy's orthonormal basis with its coefficients (lat_basis_stack), which
- * is the same operator when the snapshots use the full rule.  n_r is a HOST value, alpha
- * [N_s][cap] canonical, X and Y packed with m right-hand sides.
- * prec = LAT_F64: FP64 throughout (transpose != 0 applies the transposed operator).
- * prec = LAT_F32: stack and coefficients rounded to FP32; the combination runs on the FP32
- *   matrix cores (2D with m in {8, 16}, 3D with m <= 16; the apply of the combined stencil is
- *   then FP64), otherwise on the FP32 VALU with an FP32 apply.
- * prec = LAT_BF16: the combination runs on the bf16 matrix cores with FP32 accumulation on
- *   operands split into bf16 slices; the slice products are grouped in levels of 2^-8 relative
- *   size, 1 to 3 levels as refine_tol requires (>= 2^-8: 1, >= 2^-16: 2, else 3), each level summed
- *   in FP64; the apply is FP64 (2D with m in {8, 16}, 3D with m <= 16), FP32 otherwise.
- *   Requires m in {1, 2, 4, 8, 16}.
- * X and Y stay FP64 for every prec; transpose is LAT_F64 only. */
+ * is the same operator when the snapshots use the full rule.  n_r is a HOST value
+ * (0..LAT_INFO_CAP, else LAT_E_SHAPE), alpha [N_s][cap] canonical, X and Y packed with m >= 1
+ * right-hand sides; transpose != 0 applies the transposed operator.  X and Y are FP64 for every
+ * prec, and so is the apply of the combined stencil to X; prec selects the precision of the
+ * combination sum_k alpha_ik K_k (the dense contraction over the principal cells):
+ *   LAT_F64   FP64 (FP64 matrix cores);
+ *   LAT_F32   operands rounded to FP32 on the FP32 matrix cores;
+ *   LAT_BF16  operands split into bf16 slices x = x0 + x1 + x2 (remainders formed in FP64), slice
+ *             products grouped in levels p + q (each level about 2^-8 below the one before) on the
+ *             bf16 matrix cores with FP32 accumulation per level and FP64 sums of the levels;
+ *             1, 2 or 3 levels to start with, as refine_tol >= 2^-8, >= 2^-16 or less.
+ * FP64-measured refinement (F32 / BF16): every pass forms the combination of one node (2D) or
+ * one stencil slice (3D) per workgroup a second time in FP64 and measures the relative
+ * Frobenius difference over all of them; when it exceeds refine_tol (>= 0, else LAT_E_ARG) the
+ * apply runs again with one more bf16 level, and after the third level (or after FP32) with the
+ * FP64 combination.  The decisions are taken on the device (no host synchronisation).
+ * err_est (device double, may be NULL) receives the estimate of the pass that stood: the relative
+ * error of the combined operator against its FP64 value at the sampled nodes, 0 for LAT_F64 and
+ * when the FP64 combination ran.
+ * work: LAT_CALL_APPLY_COMBO workspace or NULL. */
 lat_status lat_apply_combo(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
                            const double *X, double *Y, int32_t m, lat_prec prec, double refine_tol,
-                           int32_t transpose, hipStream_t stream);
+                           int32_t transpose, double *err_est, void *work, size_t work_bytes, hipStream_t stream);
 
 /* The greedy's orthonormal basis as a ROM stack: stack[(a E + e) cap + k] = Z[k][(a, e)] and
  * coefficients coef[s][k] = nu_s beta_k^s (the certified decomposition of Algorithm 1), k < n_r
@@ -217,29 +263,40 @@ lat_status lat_apply_plain(const lat_plan *plan, const double *plain_ops, const 
  *   mu_bar, lam_bar f64 [N_s]   the part through the principal tangents:
  *                               lam/mu_bar_{s_k} = sum_i alpha_ik <Ybar_i, K_{mu/lam,k} X_i>
  *                               (written, not accumulated; zero for non-principal cells).
- *                               Requires K_mu / K_lam from lat_principal_ops. */
+ *                               Requires K_mu / K_lam from lat_principal_ops and S.
+ * prec / refine_tol / err_est: the precision of Xbar's combination, as for lat_apply_combo (its
+ * transposed apply).  The forms <Ybar_i, K_k X_i> are sums of products of FP64 data; with a
+ * workspace of the fast size they are taken from the cells' W[(a, e)] = sum_r Ybar X, held in FP64
+ * (LAT_F64) or FP32 (LAT_F32 / LAT_BF16), by one contraction per stack on the FP64 matrix cores;
+ * otherwise by a fused per-node kernel in FP64.  work: LAT_CALL_APPLY_COMBO_ADJOINT workspace or
+ * NULL (no fast variant then). */
 lat_status lat_apply_combo_adjoint(const lat_plan *plan, const double *K, const double *K_mu, const double *K_lam,
                                    const int32_t *S, int32_t n_r, const double *alpha, const double *X,
                                    const double *Ybar, int32_t m, double *Xbar, double *alpha_bar, double *mu_bar,
-                                   double *lam_bar, hipStream_t stream);
+                                   double *lam_bar, lat_prec prec, double refine_tol, double *err_est, void *work,
+                                   size_t work_bytes, hipStream_t stream);
 
 /* Reverse mode of the RB coefficients alpha = (T_S^T T_S)^{-1} T_S^T t (least squares, S frozen),
  * chained to the per-cell Lame parameters through the snapshots t_s = mu_s t^mu_s + lam_s t^lam_s.
  * Uses the greedy's outputs: Delta (= snap after lat_select_principal), Z, R, nu, and the snapshot
  * parts snap_mu, snap_lam (CIL(E), from lat_residual_tangent with mu = 1, lam = 0 and mu = 0,
- * lam = 1).  alpha_bar [N_s][cap].  ACCUMULATES into mu_bar, lam_bar [N_s]. */
+ * lam = 1).  alpha_bar [N_s][cap].  ACCUMULATES into mu_bar, lam_bar [N_s].
+ * work: LAT_CALL_ALPHA_ADJOINT workspace or NULL (with the fast size, n_r <= 32: one pass over
+ * Delta for both Lame parts). */
 lat_status lat_alpha_adjoint(const lat_plan *plan, const double *delta, const double *Z, const double *R,
                              const double *nu, const int32_t *S, int32_t n_r, const double *alpha,
                              const double *alpha_bar, const double *snap_mu, const double *snap_lam,
-                             double *mu_bar, double *lam_bar, hipStream_t stream);
+                             double *mu_bar, double *lam_bar, void *work, size_t work_bytes, hipStream_t stream);
 
 /* Reverse mode of the residual r = sum_s A^s f^{int,s}(u^s) for a cell-local cotangent
  * w (CIL(d)):  ubar_local = K_s^T w_s (CIL(d), may be NULL), ubar_global = sum_s A^s ubar_local
  * ([n_global][d], may be NULL), mu_bar_s = <w_s, f^mu_s>, lam_bar_s = <w_s, f^lam_s> ([N_s],
- * written; may be NULL), with f = mu f^mu + lam f^lam at fixed u. */
+ * written; may be NULL), with f = mu f^mu + lam f^lam at fixed u.
+ * work: LAT_CALL_RESIDUAL_ADJOINT workspace or NULL. */
 lat_status lat_residual_adjoint(const lat_plan *plan, const double *u_global, const double *mu, const double *lam,
                                 const double *w, double *ubar_local, double *ubar_global, double *mu_bar,
-                                double *lam_bar, int32_t *dev_status, hipStream_t stream);
+                                double *lam_bar, int32_t *dev_status, void *work, size_t work_bytes,
+                                hipStream_t stream);
 
 /* Assembly r = sum_s A^s v_s of a cell-local field v (CIL(k)) into out [n_global][k], summing the
  * cells that share a node in ascending canonical order (deterministic). */
@@ -263,7 +320,8 @@ lat_status lat_plain_ops_to_canon(const lat_plan *plan, const double *ops, doubl
  * rebuilt at every iteration, Sec. 3.2.3).  Global vectors are [n_global][d], node-major, in the
  * plan's global numbering; `fixed` is a device uint8 [n_global][d] (1 = prescribed component).
  * These calls synchronise `stream`, allocate their device workspace for the duration of the call
- * and free it before returning.
+ * and free it before returning; the hot-path calls inside them use the plan's default workspace
+ * (so they must not overlap other NULL-workspace calls on the plan).
  * ------------------------------------------------------------------------------------------- */
 
 /* Tangent solve K~ x = b on the free components (eq. linsys with the ROM operator of

@@ -34,15 +34,28 @@ class RomState:
     nu: Optional[torch.Tensor] = None
     snap_mu: Optional[torch.Tensor] = None
     snap_lam: Optional[torch.Tensor] = None
+    # what the state was built from (LatCombo rebuilds it for other Lame parameters)
+    u_global: Optional[torch.Tensor] = None
+    mu: Optional[torch.Tensor] = None
+    lam: Optional[torch.Tensor] = None
+    tol: float = 0.0
+    cap: Optional[int] = None
+    snap_rule: int = B.RULE_FULL
+    # precision of the combination in the forward and transposed applies (lat_apply_combo's prec)
+    prec: int = B.F64
+    refine_tol: float = 1e-6
 
 
-def build_rom_state(plan: B.Plan, u_global, mu, lam, tol, cap=None, for_adjoint=True, snap_rule=B.RULE_FULL):
+def build_rom_state(plan: B.Plan, u_global, mu, lam, tol, cap=None, for_adjoint=True, snap_rule=B.RULE_FULL,
+                    prec=B.F64, refine_tol=1e-6):
     """Snapshots -> greedy -> alpha -> principal operators (and, for the adjoint, the Lame parts)."""
     r = plan.residual_tangent(u_global, mu, lam, snap_rule=snap_rule, f=False, energy=False, snap=True)
     g = plan.select_principal(r["snap"], tol, cap=cap, keep_Z=for_adjoint)
     n_r = int(g["n_r"].item())
     ops = plan.principal_ops(u_global, mu, lam, g["S"], n_r, parts=for_adjoint)
-    st = RomState(plan=plan, K=ops["K"], S=g["S"], n_r=n_r, alpha=g["alpha"])
+    st = RomState(plan=plan, K=ops["K"], S=g["S"], n_r=n_r, alpha=g["alpha"], u_global=u_global,
+                  mu=mu.detach().clone(), lam=lam.detach().clone(), tol=tol, cap=cap, snap_rule=snap_rule, prec=prec,
+                  refine_tol=refine_tol)
     if for_adjoint:
         ones = torch.ones_like(mu)
         zeros = torch.zeros_like(mu)
@@ -57,9 +70,17 @@ def build_rom_state(plan: B.Plan, u_global, mu, lam, tol, cap=None, for_adjoint=
 class LatCombo(torch.autograd.Function):
     @staticmethod
     def forward(ctx, X, mu, lam, state: RomState, m: int):
+        if state.mu is None or not (torch.equal(mu, state.mu) and torch.equal(lam, state.lam)):
+            # the operator depends on (mu, lam): a state built for other values is rebuilt at these
+            if state.u_global is None:
+                raise RuntimeError("RomState does not record its displacement; build it with build_rom_state")
+            state = build_rom_state(state.plan, state.u_global, mu.detach(), lam.detach(), state.tol, state.cap,
+                                    for_adjoint=state.K_mu is not None, snap_rule=state.snap_rule, prec=state.prec,
+                                    refine_tol=state.refine_tol)
         ctx.state, ctx.m = state, m
         ctx.save_for_backward(X)
-        return state.plan.apply_combo(state.K, state.n_r, state.alpha, X.contiguous(), m)
+        return state.plan.apply_combo(state.K, state.n_r, state.alpha, X.contiguous(), m, prec=state.prec,
+                                      refine_tol=state.refine_tol)
 
     @staticmethod
     def backward(ctx, Ybar):
@@ -71,7 +92,8 @@ class LatCombo(torch.autograd.Function):
             raise RuntimeError("RomState was built without adjoint data (for_adjoint=False)")
         r = P.apply_combo_adjoint(st.K, st.n_r, st.alpha, X.contiguous(), Ybar.contiguous(), m,
                                   K_mu=st.K_mu if want_lame else None, K_lam=st.K_lam if want_lame else None,
-                                  S=st.S, want_xbar=ctx.needs_input_grad[0], want_alpha_bar=want_lame)
+                                  S=st.S, want_xbar=ctx.needs_input_grad[0], want_alpha_bar=want_lame, prec=st.prec,
+                                  refine_tol=st.refine_tol)
         mu_bar = lam_bar = None
         if want_lame:
             mu_bar, lam_bar = r["mu_bar"], r["lam_bar"]

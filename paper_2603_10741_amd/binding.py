@@ -19,6 +19,11 @@ LIB_PATH = os.environ.get("LAT_LIBRARY") or os.path.join(_HERE, "liblat.so")
 (LAT_OK, LAT_E_ARG, LAT_E_SHAPE, LAT_E_DEVICE, LAT_E_NOMEM, LAT_E_INVERTED, LAT_E_NONFINITE, LAT_W_CAP, LAT_E_NOCONV,
  LAT_E_SINGULAR) = range(10)
 RULE_FULL, RULE_REDUCED, RULE_MATERIAL, RULE_SAMPLED = 0, 1, 2, 3
+(CALL_RESIDUAL_TANGENT, CALL_PRINCIPAL_OPS, CALL_SELECT_PRINCIPAL, CALL_APPLY_COMBO, CALL_APPLY_COMBO_ADJOINT,
+ CALL_ALPHA_ADJOINT, CALL_RESIDUAL_ADJOINT) = range(7)
+N_CALLS = 7
+# the binding gives a call its fast workspace when that stays within this many bytes, else the minimum
+WORK_FAST_LIMIT = int(os.environ.get("LAT_WORK_FAST_LIMIT", str(24 << 30)))
 SAMPLE_STRIDE = 2
 F64, F32, BF16 = 0, 1, 2
 INFO_KEYS = ["dim", "nel", "ncells", "nloc", "nelem", "E", "nsnap", "ld", "ngroups", "npacked", "nglobal", "cap"]
@@ -65,24 +70,27 @@ def _lib():
                               f"python -m paper_2603_10741_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        Z = ctypes.c_size_t
         sig = {
             "lat_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "lat_plan_create": (ctypes.c_int, [I32, P, I32, P, I32, P, P]),
             "lat_plan_destroy": (ctypes.c_int, [P]),
             "lat_plan_info": (ctypes.c_int, [P, P]),
+            "lat_plan_query": (ctypes.c_int, [P, P, P]),
             "lat_status_reset": (ctypes.c_int, [P, P]),
             "lat_dofmap": (ctypes.c_int, [P, P, P, P, P, P]),
-            "lat_residual_tangent": (ctypes.c_int, [P, P, P, P, ctypes.c_int, P, P, P, P, P, P]),
+            "lat_residual_tangent": (ctypes.c_int, [P, P, P, P, ctypes.c_int, P, P, P, P, P, P, Z, P]),
             "lat_snapshot_rows": (I64, [P, ctypes.c_int]),
-            "lat_principal_ops": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P]),
-            "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P]),
-            "lat_select_principal_rows": (ctypes.c_int, [P, P, I64, F, I32, P, P, P, P, P, P, P, P, P, P]),
-            "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, F, I32, P]),
+            "lat_principal_ops": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P, Z, P]),
+            "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P, Z, P]),
+            "lat_select_principal_rows": (ctypes.c_int, [P, P, I64, F, I32, P, P, P, P, P, P, P, P, P, P, Z, P]),
+            "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, F, I32, P, P, Z, P]),
             "lat_basis_stack": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
             "lat_apply_plain": (ctypes.c_int, [P, P, P, P, I32, P]),
-            "lat_apply_combo_adjoint": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, I32, P, P, P, P, P]),
-            "lat_alpha_adjoint": (ctypes.c_int, [P, P, P, P, P, P, I32, P, P, P, P, P, P, P]),
-            "lat_residual_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P]),
+            "lat_apply_combo_adjoint": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, I32, P, P, P, P, ctypes.c_int, F, P,
+                                                       P, Z, P]),
+            "lat_alpha_adjoint": (ctypes.c_int, [P, P, P, P, P, P, I32, P, P, P, P, P, P, P, Z, P]),
+            "lat_residual_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, P, P, Z, P]),
             "lat_assemble": (ctypes.c_int, [P, P, I32, P, P]),
             "lat_gather": (ctypes.c_int, [P, P, I32, P, P]),
             "lat_pack": (ctypes.c_int, [P, P, P, I32, P]),
@@ -104,7 +112,8 @@ def _lib():
 
 def exported_symbols():
     """Names of the C entry points this binding uses (all declared in include/lat.h)."""
-    return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_status_reset",
+    return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_plan_query",
+            "lat_status_reset",
             "lat_dofmap", "lat_residual_tangent", "lat_snapshot_rows", "lat_principal_ops", "lat_select_principal", "lat_select_principal_rows",
             "lat_apply_combo", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
@@ -117,6 +126,17 @@ def _ptr(t):
         return None
     assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, n, dtype, name):
+    """Host-side check of a tensor handed to the library: the C ABI takes bare pointers, so a
+    tensor smaller than the size the call will touch must be refused here."""
+    if t is None:
+        return
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} elements, the call needs {n}")
 
 
 def _stream():
@@ -146,6 +166,12 @@ class Plan:
         self.info = {k: int(info[i]) for i, k in enumerate(INFO_KEYS)}
         for k, v in self.info.items():
             setattr(self, k, v)
+        mn = (ctypes.c_size_t * N_CALLS)()
+        fs = (ctypes.c_size_t * N_CALLS)()
+        _ok(_lib().lat_plan_query(self._p, mn, fs), "plan_query")
+        self.work_min = [int(x) for x in mn]
+        self.work_fast = [int(x) for x in fs]
+        self._work = {}
         self.status_word = torch.zeros(2, dtype=torch.int32, device=self.device)
         self.reset_status()
 
@@ -160,6 +186,21 @@ class Plan:
     # ------------------------------------------------------------------ helpers
     def _f64(self, *shape):
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def workspace(self, call, fast=None):
+        """The cached device workspace of a call (a uint8 tensor of the call's fast size when that is
+        at most WORK_FAST_LIMIT bytes, else of its minimum size): (pointer, bytes)."""
+        if fast is None:
+            fast = self.work_fast[call] <= WORK_FAST_LIMIT
+        key = (call, bool(fast))
+        if key not in self._work:
+            n = self.work_fast[call] if fast else self.work_min[call]
+            self._work[key] = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+        t = self._work[key]
+        return _ptr(t), ctypes.c_size_t(t.numel())
+
+    def _stack_elems(self):
+        return self.nloc * self.E * self.cap
 
     def reset_status(self):
         _ok(_lib().lat_status_reset(_ptr(self.status_word), _stream()), "status_reset")
@@ -192,9 +233,18 @@ class Plan:
             out["snap"] = self._f64(self.nsnap * self.ld)
         if plain and "plain" not in out:
             out["plain"] = self._f64(self.npacked * self.E * 64)
+        f64 = torch.float64
+        _need(u_global, self.nglobal * self.dim, f64, "u_global")
+        _need(mu, self.ncells, f64, "mu")
+        _need(lam, self.ncells, f64, "lam")
+        _need(out.get("f"), self.nloc * self.dim * self.ld, f64, "f")
+        _need(out.get("energy"), self.ncells, f64, "energy")
+        _need(out.get("snap"), self.nsnap * self.ld, f64, "snap")
+        _need(out.get("plain"), self.npacked * self.E * 64, f64, "plain")
+        w, wb = self.workspace(CALL_RESIDUAL_TANGENT)
         _ok(_lib().lat_residual_tangent(self._p, _ptr(u_global), _ptr(mu), _ptr(lam), snap_rule, _ptr(out.get("f")),
                                         _ptr(out.get("energy")), _ptr(out.get("snap")), _ptr(out.get("plain")),
-                                        _ptr(self.status_word), _stream()), "residual_tangent")
+                                        _ptr(self.status_word), w, wb, _stream()), "residual_tangent")
         return out
 
     def snapshot_rows(self, rule):
@@ -209,9 +259,13 @@ class Plan:
         for key in (["K", "K_mu", "K_lam"] if parts else ["K"]):
             if key not in out:
                 out[key] = self._f64(self.nloc * self.E * self.cap)
+        for key in ("K", "K_mu", "K_lam"):
+            _need(out.get(key), self._stack_elems(), torch.float64, key)
+        _need(S, min(int(n_r), self.cap), torch.int32, "S")
+        w, wb = self.workspace(CALL_PRINCIPAL_OPS)
         _ok(_lib().lat_principal_ops(self._p, _ptr(u_global), _ptr(mu), _ptr(lam), _ptr(S), int(n_r), _ptr(out["K"]),
                                      _ptr(out.get("K_mu")), _ptr(out.get("K_lam")), _ptr(self.status_word),
-                                     _stream()), "principal_ops")
+                                     w, wb, _stream()), "principal_ops")
         return out
 
     # ------------------------------------------------------------------ a5-a6
@@ -226,8 +280,17 @@ class Plan:
                        nu=self._f64(self.ncells), R=self._f64(self.cap, self.cap), achieved=self._f64(1))
             if keep_Z:
                 out["Z"] = self._f64(self.cap, self.nsnap)
+        f64, c = torch.float64, self.cap
+        _need(snap, self.nsnap * self.ld, f64, "snap")
+        _need(out["S"], c, torch.int32, "S")
+        _need(out["alpha"], self.ncells * c, f64, "alpha")
+        _need(out.get("beta"), self.ncells * c, f64, "beta")
+        _need(out.get("nu"), self.ncells, f64, "nu")
+        _need(out["R"], c * c, f64, "R")
+        _need(out.get("Z"), c * self.nsnap, f64, "Z")
+        w, wb = self.workspace(CALL_SELECT_PRINCIPAL)
         args = (_ptr(out["S"]), _ptr(out["n_r"]), _ptr(out["alpha"]), _ptr(out.get("beta")), _ptr(out.get("nu")),
-                _ptr(out["R"]), _ptr(out.get("Z")), _ptr(out["achieved"]), _ptr(self.status_word), _stream())
+                _ptr(out["R"]), _ptr(out.get("Z")), _ptr(out["achieved"]), _ptr(self.status_word), w, wb, _stream())
         if rows is None:
             _ok(_lib().lat_select_principal(self._p, _ptr(snap), float(tol), int(cap), *args), "select_principal")
         else:
@@ -239,10 +302,20 @@ class Plan:
     def packed_size(self, m):
         return self.npacked * self.dim * m * 64
 
-    def apply_combo(self, K, n_r, alpha, X, m, transpose=False, prec=F64, refine_tol=1e-6, out=None):
+    def apply_combo(self, K, n_r, alpha, X, m, transpose=False, prec=F64, refine_tol=1e-6, out=None, err_est=None):
+        """ROM apply (lat_apply_combo).  err_est: optional device float64 tensor of one element that
+        receives the FP64-measured error estimate of a reduced-precision combination."""
         Y = self._f64(self.packed_size(m)) if out is None else out
+        f64 = torch.float64
+        _need(K, self._stack_elems(), f64, "K")
+        _need(alpha, self.ncells * self.cap, f64, "alpha")
+        _need(X, self.packed_size(m), f64, "X")
+        _need(Y, self.packed_size(m), f64, "Y")
+        _need(err_est, 1, f64, "err_est")
+        w, wb = self.workspace(CALL_APPLY_COMBO)
         _ok(_lib().lat_apply_combo(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(X), _ptr(Y), int(m), prec,
-                                   float(refine_tol), int(bool(transpose)), _stream()), "apply_combo")
+                                   float(refine_tol), int(bool(transpose)), _ptr(err_est), w, wb, _stream()),
+            "apply_combo")
         return Y
 
     def basis_stack(self, Z, nu, beta, n_r, out=None):
@@ -256,33 +329,59 @@ class Plan:
 
     def apply_plain(self, ops, X, m, out=None):
         Y = self._f64(self.packed_size(m)) if out is None else out
+        _need(ops, self.npacked * self.E * 64, torch.float64, "ops")
+        _need(X, self.packed_size(m), torch.float64, "X")
+        _need(Y, self.packed_size(m), torch.float64, "Y")
         _ok(_lib().lat_apply_plain(self._p, _ptr(ops), _ptr(X), _ptr(Y), int(m), _stream()), "apply_plain")
         return Y
 
     # ------------------------------------------------------------------ a9
     def apply_combo_adjoint(self, K, n_r, alpha, X, Ybar, m, K_mu=None, K_lam=None, S=None, want_xbar=True,
-                            want_alpha_bar=True):
+                            want_alpha_bar=True, prec=F64, refine_tol=1e-6, err_est=None, fast=None):
+        """Adjoint of the ROM apply (lat_apply_combo_adjoint).  fast: force (True) or refuse (False)
+        the workspace of the fast size (default: as workspace() decides)."""
         Xbar = self._f64(self.packed_size(m)) if want_xbar else None
         abar = self._f64(self.ncells, self.cap) if want_alpha_bar else None
         mub = self._f64(self.ncells) if K_mu is not None else None
         lamb = self._f64(self.ncells) if K_lam is not None else None
+        f64 = torch.float64
+        for key, t in (("K", K), ("K_mu", K_mu), ("K_lam", K_lam)):
+            _need(t, self._stack_elems(), f64, key)
+        _need(alpha, self.ncells * self.cap, f64, "alpha")
+        _need(X, self.packed_size(m), f64, "X")
+        _need(Ybar, self.packed_size(m), f64, "Ybar")
+        _need(S, min(int(n_r), self.cap), torch.int32, "S")
+        _need(err_est, 1, f64, "err_est")
+        w, wb = self.workspace(CALL_APPLY_COMBO_ADJOINT, fast=fast)
         _ok(_lib().lat_apply_combo_adjoint(self._p, _ptr(K), _ptr(K_mu), _ptr(K_lam), _ptr(S), int(n_r), _ptr(alpha),
                                            _ptr(X), _ptr(Ybar), int(m), _ptr(Xbar), _ptr(abar), _ptr(mub), _ptr(lamb),
-                                           _stream()), "apply_combo_adjoint")
+                                           int(prec), float(refine_tol), _ptr(err_est), w, wb, _stream()),
+            "apply_combo_adjoint")
         return {"Xbar": Xbar, "alpha_bar": abar, "mu_bar": mub, "lam_bar": lamb}
 
     def alpha_adjoint(self, delta, Z, R, nu, S, n_r, alpha, alpha_bar, snap_mu, snap_lam, mu_bar, lam_bar):
+        f64, c = torch.float64, self.cap
+        for key, t in (("delta", delta), ("snap_mu", snap_mu), ("snap_lam", snap_lam)):
+            _need(t, self.nsnap * self.ld, f64, key)
+        _need(Z, c * self.nsnap, f64, "Z")
+        _need(R, c * c, f64, "R")
+        _need(alpha, self.ncells * c, f64, "alpha")
+        _need(alpha_bar, self.ncells * c, f64, "alpha_bar")
+        w, wb = self.workspace(CALL_ALPHA_ADJOINT)
         _ok(_lib().lat_alpha_adjoint(self._p, _ptr(delta), _ptr(Z), _ptr(R), _ptr(nu), _ptr(S), int(n_r), _ptr(alpha),
                                      _ptr(alpha_bar), _ptr(snap_mu), _ptr(snap_lam), _ptr(mu_bar), _ptr(lam_bar),
-                                     _stream()), "alpha_adjoint")
+                                     w, wb, _stream()), "alpha_adjoint")
 
     def residual_adjoint(self, u_global, mu, lam, w_cil, local=True, glob=True, lame=True):
         ub = self._f64(self.nloc * self.dim * self.ld) if (local or glob) else None
         ug = self._f64(max(self.nglobal, 1) * self.dim) if glob else None
         mub = self._f64(self.ncells) if lame else None
         lamb = self._f64(self.ncells) if lame else None
+        _need(w_cil, self.nloc * self.dim * self.ld, torch.float64, "w")
+        w, wb = self.workspace(CALL_RESIDUAL_ADJOINT)
         _ok(_lib().lat_residual_adjoint(self._p, _ptr(u_global), _ptr(mu), _ptr(lam), _ptr(w_cil), _ptr(ub), _ptr(ug),
-                                        _ptr(mub), _ptr(lamb), _ptr(self.status_word), _stream()), "residual_adjoint")
+                                        _ptr(mub), _ptr(lamb), _ptr(self.status_word), w, wb, _stream()),
+            "residual_adjoint")
         return {"ubar_local": ub, "ubar_global": ug, "mu_bar": mub, "lam_bar": lamb}
 
     # ------------------------------------------------------------------ layouts

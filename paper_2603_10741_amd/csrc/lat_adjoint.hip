@@ -75,10 +75,10 @@ __global__ void k_aa_cols(int64_t nsnap, int64_t ld, int cap, int n_r, const int
     for (int k = 0; k < cap; ++k) U[j * cap + k] = k < n_r ? V[j * ld + lane[S[k]]] : 0.0;
 }
 
-// part[chunk][p][k] = sum_{j in chunk} V[j][p] U[j][k]
-template <int NR>
+// part[chunk][p][k] = sum_{j in chunk} V[j][p] U[j][k]   (V FP64 or FP32; FP64 arithmetic)
+template <int NR, class VT>
 __global__ __launch_bounds__(256) void k_aa_contract(int64_t nsnap, int64_t ld, int cap, int rows_per_chunk,
-                                                     const double *__restrict__ V, const double *__restrict__ U,
+                                                     const VT *__restrict__ V, const double *__restrict__ U,
                                                      double *__restrict__ part)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_aa_contract(int64_t nsnap, int64_t ld, 
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = 0.0;
     for (int64_t j = j0; j < j1; ++j) {
-        const double x = V[j * ld + p];
+        const double x = (double)V[j * ld + p];
         const double *u = U + j * cap;
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[k] = fma(x, u[k], acc[k]);
@@ -108,9 +108,9 @@ __global__ __launch_bounds__(256) void k_aa_contract(int64_t nsnap, int64_t ld, 
 // MFMA, and chunks are combined by the fixed tree.
 typedef double aa_v4d __attribute__((ext_vector_type(4)));
 
-template <int NR>
+template <int NR, class VT>
 __global__ __launch_bounds__(256) void k_aa_contract_mfma(int64_t nsnap, int64_t ld, int cap, int rows_per_chunk,
-                                                          const double *__restrict__ V, const double *__restrict__ U,
+                                                          const VT *__restrict__ V, const double *__restrict__ U,
                                                           double *__restrict__ part)
 {
     constexpr int NKT = NR / 16;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_aa_contract_mfma(int64_t nsnap, int64_t
         double a[4], bv[NKT];
 #pragma unroll
         for (int pt = 0; pt < 4; ++pt) {
-            const double v = V[jc * ld + pw + 16 * pt + (l & 15)];
+            const double v = (double)V[jc * ld + pw + 16 * pt + (l & 15)];
             a[pt] = live ? v : 0.0;
         }
 #pragma unroll
@@ -159,9 +159,9 @@ __global__ __launch_bounds__(256) void k_aa_contract_mfma(int64_t nsnap, int64_t
 
 // The same row contraction against NS stacks at once: every V tile is loaded once and feeds the
 // NS accumulators (out_t[p][k] = sum_j V[j][p] U_t[j][k]); chunk partials part_t as above.
-template <int NR, int NS>
+template <int NR, int NS, class VT>
 __global__ __launch_bounds__(256) void k_aa_contract_ns_mfma(int64_t nsnap, int64_t ld, int cap, int rows_per_chunk,
-                                                             const double *__restrict__ V,
+                                                             const VT *__restrict__ V,
                                                              const double *__restrict__ U0,
                                                              const double *__restrict__ U1,
                                                              const double *__restrict__ U2, double *__restrict__ part0,
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_aa_contract_ns_mfma(int64_t nsnap, int6
         double a[4];
 #pragma unroll
         for (int pt = 0; pt < 4; ++pt) {
-            const double v = V[jc * ld + pw + 16 * pt + (l & 15)];
+            const double v = (double)V[jc * ld + pw + 16 * pt + (l & 15)];
             a[pt] = live ? v : 0.0;
         }
 #pragma unroll
@@ -278,37 +278,42 @@ __global__ __launch_bounds__(256) void k_aa_principal(int64_t ncells, int64_t ld
     }
 }
 
-lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
+template <class VT>
+lat_status contract_t(const lat_plan *P, int n_r, const VT *V, const double *U, double *out, hipStream_t s)
 {
     const int rows = P->aa_rows;
     dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->aa_nchunk);
+#define CM(NRV) hipLaunchKernelGGL((k_aa_contract_mfma<NRV, VT>), grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, \
+                                   U, P->aa_part)
+#define CV(NRV) hipLaunchKernelGGL((k_aa_contract<NRV, VT>), grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, \
+                                   P->aa_part)
     if (n_r > 8 && P->cap >= 16) {
-        if (n_r <= 16) hipLaunchKernelGGL(k_aa_contract_mfma<16>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
-        else if (n_r <= 32) hipLaunchKernelGGL(k_aa_contract_mfma<32>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
-        else hipLaunchKernelGGL(k_aa_contract_mfma<64>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
-    } else if (n_r <= 8) hipLaunchKernelGGL(k_aa_contract<8>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
-    else if (n_r <= 16) hipLaunchKernelGGL(k_aa_contract<16>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
-    else if (n_r <= 32) hipLaunchKernelGGL(k_aa_contract<32>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
-    else hipLaunchKernelGGL(k_aa_contract<64>, grid, dim3(256), 0, s, P->nsnap, P->ld, P->cap, rows, V, U, P->aa_part);
+        if (n_r <= 16) CM(16);
+        else if (n_r <= 32) CM(32);
+        else CM(64);
+    } else if (n_r <= 8) CV(8);
+    else if (n_r <= 16) CV(16);
+    else if (n_r <= 32) CV(32);
+    else CV(64);
+#undef CM
+#undef CV
     LAT_LAUNCH_CHECK();
     return lat_tree_reduce(P->aa_part, P->aa_nchunk, P->ld * P->cap, 0, out, P->g_t1, P->g_t2, s);
 }
 
-}  // namespace
-
-lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
+lat_status contract(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s)
 {
-    return contract(P, n_r, V, U, out, s);
+    return contract_t<double>(P, n_r, V, U, out, s);
 }
 
-lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const double *const *U, int ns,
-                                   double *const *part, hipStream_t s)
+template <class VT>
+lat_status contract_multi_t(const lat_plan *P, int n_r, const VT *V, const double *const *U, int ns,
+                            double *const *part, hipStream_t s)
 {
-    if (ns < 1 || ns > 3 || n_r > 32 || P->cap < 16) return LAT_E_ARG;
     dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->aa_nchunk);
     const double *u1 = ns > 1 ? U[1] : U[0], *u2 = ns > 2 ? U[2] : U[0];
     double *p1 = ns > 1 ? part[1] : part[0], *p2 = ns > 2 ? part[2] : part[0];
-#define CN(NRV, NSV) hipLaunchKernelGGL((k_aa_contract_ns_mfma<NRV, NSV>), grid, dim3(256), 0, s, P->nsnap, P->ld, \
+#define CN(NRV, NSV) hipLaunchKernelGGL((k_aa_contract_ns_mfma<NRV, NSV, VT>), grid, dim3(256), 0, s, P->nsnap, P->ld, \
                                         P->cap, P->aa_rows, V, U[0], u1, u2, part[0], p1, p2)
     if (n_r <= 16) {
         if (ns == 1) CN(16, 1); else if (ns == 2) CN(16, 2); else CN(16, 3);
@@ -320,13 +325,34 @@ lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, 
     return LAT_OK;
 }
 
-extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, const double *Z, const double *R,
+}  // namespace
+
+lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const float *V32, const double *U,
+                             double *out, hipStream_t s)
+{
+    if ((V == nullptr) == (V32 == nullptr)) return LAT_E_ARG;
+    return V ? contract_t<double>(P, n_r, V, U, out, s) : contract_t<float>(P, n_r, V32, U, out, s);
+}
+
+lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const float *V32,
+                                   const double *const *U, int ns, double *const *part, hipStream_t s)
+{
+    if (ns < 1 || ns > 3 || n_r > 32 || P->cap < 16 || (V == nullptr) == (V32 == nullptr)) return LAT_E_ARG;
+    return V ? contract_multi_t<double>(P, n_r, V, U, ns, part, s) : contract_multi_t<float>(P, n_r, V32, U, ns, part, s);
+}
+
+extern "C" lat_status lat_alpha_adjoint(const lat_plan *Pp, const double *delta, const double *Z, const double *R,
                                         const double *nu, const int32_t *S, int32_t n_r, const double *alpha,
                                         const double *alpha_bar, const double *snap_mu, const double *snap_lam,
-                                        double *mu_bar, double *lam_bar, hipStream_t stream)
+                                        double *mu_bar, double *lam_bar, void *work, size_t work_bytes,
+                                        hipStream_t stream)
 {
-    if (!P || !delta || !Z || !R || !nu || !S || !alpha || !alpha_bar || !snap_mu || !snap_lam) return LAT_E_ARG;
-    if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
+    if (!Pp || !delta || !Z || !R || !nu || !S || !alpha || !alpha_bar || !snap_mu || !snap_lam) return LAT_E_ARG;
+    if (n_r < 0 || n_r > Pp->cap) return LAT_E_SHAPE;
+    lat_plan Vw;
+    lat_status st0 = lat_ws_bind(Pp, LAT_CALL_ALPHA_ADJOINT, work, work_bytes, &Vw);
+    if (st0 != LAT_OK) return st0;
+    const lat_plan *P = &Vw;
     if (n_r == 0) return LAT_OK;
     const int64_t ld = P->ld, cap = P->cap;
     const dim3 lg((unsigned)lat_cdiv(ld, 256)), sg((unsigned)lat_cdiv(P->nsnap, 256));
@@ -350,17 +376,16 @@ extern "C" lat_status lat_alpha_adjoint(const lat_plan *P, const double *delta, 
     // B = Delta^T T^mu_S, Delta^T T^lam_S
     hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_mu, P->aa_gath);
     LAT_LAUNCH_CHECK();
-    if (n_r <= 32 && cap >= 16 && P->w_forms && P->wf_part) {
-        // one pass over Delta for both: the second gathered set goes to the forms workspace
-        // ([n_snap][ld] >= [n_snap][cap], free between calls on the plan's stream order)
-        double *gath2 = P->w_forms;
+    if (n_r <= 32 && cap >= 16 && P->aa_gath2 && P->wf_part) {
+        // one pass over Delta for both (the caller's workspace holds the second gathered set)
+        double *gath2 = P->aa_gath2;
         hipLaunchKernelGGL(k_aa_cols, sg, dim3(256), 0, stream, P->nsnap, ld, (int)cap, n_r, S, P->lane, snap_lam,
                            gath2);
         LAT_LAUNCH_CHECK();
         const int64_t ldc = ld * cap;
         const double *U2[2] = {P->aa_gath, gath2};
         double *parts[2] = {P->wf_part, P->wf_part + P->aa_nchunk * ldc};
-        if ((st = lat_contract_rows_multi(P, n_r, delta, U2, 2, parts, stream)) != LAT_OK) return st;
+        if ((st = lat_contract_rows_multi(P, n_r, delta, nullptr, U2, 2, parts, stream)) != LAT_OK) return st;
         if ((st = lat_tree_reduce(parts[0], P->aa_nchunk, ldc, 0, Bm, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
         if ((st = lat_tree_reduce(parts[1], P->aa_nchunk, ldc, 0, Bl, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
     } else {

@@ -24,7 +24,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct ApplyArgs {
     int nn, m, cap, n_r, nch, chunks_per_group, nseg;
+    int rb, mc;               // walks: right-hand sides rb .. rb + mc - 1 of the m columns
     int64_t ld;
+    const int32_t *gate;      // walks: run only when *gate != 0 (NULL: always)
+    double *errp;             // reduced-precision walks: per-block error partials [2 * grid] (or NULL)
     const int32_t *goff, *unode, *unbr;
     const uint64_t *umask;
     const double *K;          // principal stack [(a*E+e)*cap + k]  or plain ops [(q*E+e)*64 + l]
@@ -39,6 +42,27 @@ __device__ __forceinline__ int offset_node(int a, int o, int nn, int dim)
     int ix = a % nn + o % 3 - 1, iy = (a / nn) % nn + (o / 3) % 3 - 1;
     int iz = dim == 3 ? a / (nn * nn) + o / 9 - 1 : 0;
     return ix + nn * (iy + nn * iz);
+}
+
+// Sum of (a, b) over the 512 threads of a walk workgroup (fixed order: wave butterflies, then the
+// waves in order); thread 0 writes the pair to out[0..1].
+__device__ __forceinline__ void block_sum2_512(double a, double b, double *red, double *out)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int t = 0; t < 8; ++t) { sa += red[2 * t]; sb += red[2 * t + 1]; }
+        out[0] = sa;
+        out[1] = sb;
+    }
 }
 
 // MODE 0: ROM apply, 1: ROM apply transposed, 2: plain apply.
@@ -160,6 +184,13 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     // BFS: the staged block as bf16 slices [buf][slice][48 rows][KSR], sliced once per node
     constexpr int KSR = 32 * (NR <= 32 ? 1 : NR / 32) + 8;
     __shared__ __align__(16) uint16_t ks_s[2][NLV][BFS ? 48 * KSR : 1];
+    // reduced precision: the combination of one node per workgroup (the segment's middle node) is
+    // formed again in FP64 from an FP64 copy of its block, and the squared differences are summed
+    constexpr bool SAMPLE = LP >= 1;
+    __shared__ double kb64[SAMPLE ? E * KSTR : 1];
+    __shared__ double kts[SAMPLE ? E * 64 : 1];          // the sampled node's reduced-precision stencils
+    __shared__ double red[16];
+    if (A.gate && *A.gate == 0) return;                  // a refinement pass that is not needed
     const int nn = A.nn, nloc = nn * nn, m = A.m, cap = A.cap;
     const int lb = lat_xcd_block(blockIdx.x, gridDim.x);
     const int nseg = A.nseg;                             // each row is walked in nseg x-segments
@@ -168,8 +199,9 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int64_t p = (int64_t)g * LAT_WAVE + l;
-    const int r0 = w * MW;
-    const bool act = !IDLE || r0 < m;                    // IDLE (m < 8): the waves past m only form
+    const int r0 = A.rb + w * MW;
+    const bool act = !IDLE || w * MW < A.mc;             // IDLE (chunks < 8): the waves past it only form
+    const int xsamp = SAMPLE && A.errp ? (xs0 + xs1) / 2 : -1;
     const int e0 = (w * E) / NW, e1 = ((w + 1) * E) / NW;   // this wave's share of the entries
     const int32_t *ui = uidx + (int64_t)g * nloc;
     const int gq = goff[g];
@@ -228,12 +260,13 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
             kpre[t] = v;
         }
     };
-    auto store_block = [&](int buf) {
+    auto store_block = [&](int buf, int xnode) {
         if (MODE == 2) return;
 #pragma unroll
         for (int t = 0; t < KPT; ++t) {
             const int idx = tid + t * NW * 64;
             if (idx < KB) {
+                if (SAMPLE && xnode == xsamp) kb64[(idx / NR) * KSTR + idx % NR] = kpre[t];
                 if (BFS) {
                     uint16_t b3[3];
                     lat_slice3(kpre[t], b3);
@@ -326,7 +359,10 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                             double v = 0.0;
 #pragma unroll
                             for (int lev = NLV - 1; lev >= 0; --lev) v += (double)acc[lev][r];
-                            if (e < E) kt_s[buf][e][c16] = v;
+                            if (e < E) {
+                                kt_s[buf][e][c16] = v;
+                                if (x == xsamp) kts[e * 64 + c16] = v;
+                            }
                         }
                     };
                     if (heavy) {
@@ -348,7 +384,10 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int e = 16 * et + 4 * (l >> 4) + r;
-                            if (e < E) kt_s[buf][e][c16] = (double)c[r];
+                            if (e < E) {
+                                kt_s[buf][e][c16] = (double)c[r];
+                                if (x == xsamp) kts[e * 64 + c16] = (double)c[r];
+                            }
                         }
                     };
                     if (heavy) {
@@ -384,7 +423,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
             }
         }
         // (2) stage the next node's block, prefetch the one after, and the next X column
-        store_block(buf ^ 1);
+        store_block(buf ^ 1, x + 1);
         fetch_block(x + 2);
         fetch_plain(x + 1);
         load_col(xw[sf], x + 2);
@@ -423,7 +462,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     load_col(xw[1], xs0);
     load_col(xw[2], xs0 + 1);
     fetch_block(xs0);
-    store_block(xs0 & 1);
+    store_block(xs0 & 1, xs0);
     fetch_block(xs0 + 1);
     fetch_plain(xs0);
     __syncthreads();
@@ -437,6 +476,40 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     if (x < xs1) step(x, 0, 1, 2, 3);
     if (x + 1 < xs1) step(x + 1, 1, 2, 3, 0);
     if (x + 2 < xs1) step(x + 2, 2, 3, 0, 1);
+    if (SAMPLE && A.errp) {
+        // the sampled node once more in FP64 (v_mfma_f64_16x16x4, output rows l / 16 + 4 r): each wave
+        // its formation tiles of that node, against the reduced-precision values kept in kts
+        __syncthreads();
+        double d2 = 0.0, r2 = 0.0;
+        if (ui[xsamp + nn * y] >= 0) {
+            const bool heavy = (w < 4) == ((xsamp & 1) == 0);
+            const int c16 = ct * 16 + (l & 15);
+            auto ref_tile = [&](int et) {
+                v4d c = {0.0, 0.0, 0.0, 0.0};
+                const int er = 16 * et + (l & 15) < E ? 16 * et + (l & 15) : E - 1;
+                const double *rp = kb64 + er * KSTR + (l >> 4);
+                for (int s2 = 0; s2 < NR / 4; ++s2) {
+                    const double a64 = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + c16];
+                    c = __builtin_amdgcn_mfma_f64_16x16x4f64(rp[4 * s2], a64, c, 0, 0, 0);
+                }
+                for (int r = 0; r < 4; ++r) {
+                    const int e = 16 * et + (l >> 4) + 4 * r;
+                    if (e < E) {
+                        const double dv = kts[e * 64 + c16] - c[r];
+                        d2 = fma(dv, dv, d2);
+                        r2 = fma(c[r], c[r], r2);
+                    }
+                }
+            };
+            if (heavy) {
+                ref_tile(0);
+                ref_tile(2);
+            } else {
+                ref_tile(1);
+            }
+        }
+        block_sum2_512(d2, r2, red, A.errp + 2 * (int64_t)blockIdx.x);
+    }
 }
 
 // 3D ROM apply (and its transpose), formation on the matrix cores.  One workgroup of 8 waves =
@@ -472,6 +545,12 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     // BFS: the staged slice as bf16 slices [buf][slice][ER rows][KSR]
     constexpr int KSR = 32 * (NR <= 32 ? 1 : NR / 32) + 8;
     __shared__ __align__(16) uint16_t ks_s[2][NLV][BFS ? ER * KSR : 1];
+    // reduced precision: one slice per workgroup (the run's middle slice) is formed again in FP64
+    constexpr bool SAMPLE = LP >= 1;
+    __shared__ double kb64[SAMPLE ? ER * KR : 1];
+    __shared__ double kts[SAMPLE ? ER * 64 : 1];         // the sampled slice's reduced-precision stencils
+    __shared__ double red[16];
+    if (A.gate && *A.gate == 0) return;                  // a refinement pass that is not needed
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63, tid = threadIdx.x;
     const int run = lat_xcd_block(blockIdx.x, gridDim.x);
@@ -480,9 +559,10 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     if (q0 >= q1) return;
     const int nn = A.nn, m = A.m, cap = A.cap;
     const int ct = w & 3, et = w >> 2;                   // formation tile of this wave
-    const int r0 = 2 * w;                                // this wave's right-hand sides (apply)
-    const int nrw = max(0, min(2, m - r0));
+    const int r0 = A.rb + 2 * w;                         // this wave's right-hand sides (apply)
+    const int nrw = max(0, min(2, A.mc - 2 * w));
     const int nsl = (q1 - q0) * NSL;
+    const int ssamp = SAMPLE && A.errp ? nsl / 2 : -1;
     // ---- principal block slice sl (node q0 + sl / 9, offsets 3 (sl % 9) ..): coalesced fetch
     double kpre[SPT];
     bool kval[SPT];
@@ -509,12 +589,13 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             kval[t] = valid;
         }
     };
-    auto store = [&](int buf) __attribute__((always_inline)) {
+    auto store = [&](int buf, int sl) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
             const int idx = tid + 512 * t;
             if (idx < ER * NR) {
                 const double v = kval[t] ? kpre[t] : 0.0;
+                if (SAMPLE && sl == ssamp) kb64[(idx / NR) * KR + idx % NR] = v;
                 if (BFS) {
                     uint16_t b3[3];
                     lat_slice3(v, b3);
@@ -565,7 +646,7 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     };
     load_x(nbv, mlo, mhi, 0);
     fetch(0);
-    store(0);
+    store(0, 0);
     fetch(1);
     __syncthreads();
     for (int q = q0; q < q1; ++q) {
@@ -629,7 +710,10 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
                 for (int s2 = 0; s2 < NR / 4; ++s2)
                     c = __builtin_amdgcn_mfma_f32_16x16x4f32((float)pa[4 * s2], (float)aB[s2], c, 0, 0, 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) kt_s[buf][(16 * et + 4 * (l >> 4) + r) * TR + ct * 16 + (l & 15)] = (double)c[r];
+                for (int r = 0; r < 4; ++r) {
+                    kt_s[buf][(16 * et + 4 * (l >> 4) + r) * TR + ct * 16 + (l & 15)] = (double)c[r];
+                    if (sl0 + h == ssamp) kts[(16 * et + 4 * (l >> 4) + r) * 64 + ct * 16 + (l & 15)] = (double)c[r];
+                }
             } else if (!BFS) {
                 v4d c = {0.0, 0.0, 0.0, 0.0};
                 const double *pa = &kb_s[buf][(16 * et + (l & 15)) * KR + (l >> 4)];
@@ -666,10 +750,11 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
 #pragma unroll
                     for (int lev = NLV - 1; lev >= 0; --lev) v += (double)acc32[lev][r];
                     kt_s[buf][(16 * et + 4 * (l >> 4) + r) * TR + ct * 16 + (l & 15)] = v;
+                    if (sl0 + h == ssamp) kts[(16 * et + 4 * (l >> 4) + r) * 64 + ct * 16 + (l & 15)] = v;
                 }
             }
             // (2) stage the next slice, fetch the one after
-            store(buf ^ 1);
+            store(buf ^ 1, sl0 + h + 1);
             fetch(sl0 + h + 2);
             __syncthreads();
             // (3) apply the slice's 27 entries
@@ -695,6 +780,29 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             for (int r = 0; r < 2; ++r)
                 if (r < nrw) Y[(((int64_t)q * 3 + i) * m + r0 + r) * LAT_WAVE + l] = own ? acc[i][r] : 0.0;
         nbv = nbv_n; mlo = mlo_n; mhi = mhi_n;
+    }
+    if (SAMPLE && A.errp) {
+        // the sampled slice once more in FP64 (output rows l / 16 + 4 r): each wave its formation tile,
+        // against the reduced-precision values kept in kts; rows past the slice's 27 entries are padding
+        __syncthreads();
+        const int gs = qgroup[q0 + ssamp / NSL];
+        const int c16 = ct * 16 + (l & 15);
+        v4d c = {0.0, 0.0, 0.0, 0.0};
+        const double *pa = &kb64[(16 * et + (l & 15)) * KR + (l >> 4)];
+        for (int s2 = 0; s2 < NR / 4; ++s2) {
+            const double a64 = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)gs * LAT_WAVE + c16];
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s2], a64, c, 0, 0, 0);
+        }
+        double d2 = 0.0, r2 = 0.0;
+        for (int r = 0; r < 4; ++r) {
+            const int e = 16 * et + (l >> 4) + 4 * r;
+            if (e < ES) {
+                const double dv = kts[e * 64 + c16] - c[r];
+                d2 = fma(dv, dv, d2);
+                r2 = fma(c[r], c[r], r2);
+            }
+        }
+        block_sum2_512(d2, r2, red, A.errp + 2 * (int64_t)blockIdx.x);
     }
 }
 
@@ -912,11 +1020,11 @@ __global__ __launch_bounds__(512) void k_forms_mfma(ApplyArgs A, const int32_t *
 // for every local node a and plan lane p, Ybar counted at the cell's owned DOFs and X at its owned
 // neighbour DOFs, zero where the node is not in the lane's group union; then
 // <Ybar_p, K_k X_p> = sum_(a, e) K_k[a][e] W[(a, e)][p] is one row contraction per stack.
-template <int DIM>
+template <int DIM, class WT>
 __global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int nloc, int m, const int32_t *__restrict__ goff,
                                                  const int32_t *__restrict__ uidx, const int32_t *__restrict__ unbr,
                                                  const uint64_t *__restrict__ umask, const double *__restrict__ X,
-                                                 const double *__restrict__ Ybar, double *__restrict__ W)
+                                                 const double *__restrict__ Ybar, WT *__restrict__ W)
 {
     constexpr int NO = DIM == 2 ? 9 : 27, E = NO * DIM * DIM, MM = 16;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -924,9 +1032,9 @@ __global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int nloc, int m, co
     if (p >= ld) return;
     const int g = (int)(p / LAT_WAVE), l = (int)(p % LAT_WAVE);
     const int qi = uidx[(int64_t)g * nloc + a];
-    double *wr = W + (int64_t)a * E * ld + p;
+    WT *wr = W + (int64_t)a * E * ld + p;
     if (qi < 0) {
-        for (int e = 0; e < E; ++e) wr[(int64_t)e * ld] = 0.0;
+        for (int e = 0; e < E; ++e) wr[(int64_t)e * ld] = (WT)0;
         return;
     }
     const int64_t q = (int64_t)goff[g] + qi;
@@ -953,7 +1061,7 @@ __global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int nloc, int m, co
                 double v = 0.0;
 #pragma unroll
                 for (int r = 0; r < MM; ++r) v = fma(yb[i][r], xv[j][r], v);
-                wr[(int64_t)((o * DIM + i) * DIM + j) * ld] = v;
+                wr[(int64_t)((o * DIM + i) * DIM + j) * ld] = (WT)v;
             }
     }
 }
@@ -1033,13 +1141,18 @@ lat_status launch_apply(const ApplyArgs &A, int nwaves, hipStream_t s)
     return launch_apply_nr<DIM, 1, MODE>(A, nwaves, s);
 }
 
-template <int MW, int MODE, int LP = 0, bool IDLE = false>
+// 2D row walk grid: one workgroup per (group, node row, x-segment); rows are split into two
+// segments when that is needed to fill the chip with whole waves of workgroups
+int rowwalk_nseg(const lat_plan *P) { return P->ngroups * P->nn >= 1024 ? 1 : (P->nn >= 16 ? 2 : 1); }
+int64_t rowwalk_grid(const lat_plan *P) { return (int64_t)P->ngroups * P->nn * rowwalk_nseg(P); }
+int64_t apply3d_grid(const lat_plan *P) { return lat_cdiv(P->npacked, APPLY3_RUN); }
+
+template <int MW, int MODE, int LP, bool IDLE>
 lat_status launch_rowwalk_nr(const lat_plan *P, const ApplyArgs &A, hipStream_t s)
 {
     ApplyArgs B = A;
-    // enough walks to fill the chip in whole waves of workgroups: split rows into x-segments
-    B.nseg = P->ngroups * P->nn >= 1024 ? 1 : (P->nn >= 16 ? 2 : 1);
-    dim3 grid((unsigned)(P->ngroups * P->nn * B.nseg)), block(512);
+    B.nseg = rowwalk_nseg(P);
+    dim3 grid((unsigned)rowwalk_grid(P)), block(512);
 #define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE, LP, IDLE>), grid, block, 0, s, B, P->goff, P->uidx, \
                                    P->umask, A.K, A.alpha_il, A.X, A.Y)
     if (MODE == 2 || A.n_r <= 8) RW(8);
@@ -1051,38 +1164,20 @@ lat_status launch_rowwalk_nr(const lat_plan *P, const ApplyArgs &A, hipStream_t 
     return LAT_OK;
 }
 
-template <int MW>
-lat_status launch_rowwalk_mode(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
+// One row walk over the right-hand sides A.rb .. A.rb + A.mc - 1: 16 (two per wave), 8 (one per
+// wave) or fewer (one per wave, the waves past them only form and stage)
+template <int MODE, int LP>
+lat_status launch_rowwalk_chunk(const lat_plan *P, const ApplyArgs &A, hipStream_t s)
 {
-    if (mode == 0) return launch_rowwalk_nr<MW, 0>(P, A, s);
-    if (mode == 1) return launch_rowwalk_nr<MW, 1>(P, A, s);
-    return launch_rowwalk_nr<MW, 2>(P, A, s);
-}
-
-lat_status launch_rowwalk(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
-{
-    if (A.m == 16) return launch_rowwalk_mode<2>(P, A, mode, s);
-    if (A.m < 8) {   // ROM modes only: one wave per right-hand side, the others form and stage
-        if (mode == 0) return launch_rowwalk_nr<1, 0, 0, true>(P, A, s);
-        if (mode == 1) return launch_rowwalk_nr<1, 1, 0, true>(P, A, s);
-        return LAT_E_ARG;
-    }
-    return launch_rowwalk_mode<1>(P, A, mode, s);
-}
-
-template <int MW>
-lat_status launch_rowwalk_bf16_mw(const lat_plan *P, const ApplyArgs &A, int nlev, hipStream_t s)
-{
-    if (nlev == 1) return launch_rowwalk_nr<MW, 0, 1>(P, A, s);
-    if (nlev == 2) return launch_rowwalk_nr<MW, 0, 2>(P, A, s);
-    if (nlev == 3) return launch_rowwalk_nr<MW, 0, 3>(P, A, s);
-    return launch_rowwalk_nr<MW, 0, 4>(P, A, s);
+    if (A.mc == 16) return launch_rowwalk_nr<2, MODE, LP, false>(P, A, s);
+    if (A.mc == 8) return launch_rowwalk_nr<1, MODE, LP, false>(P, A, s);
+    return launch_rowwalk_nr<1, MODE, LP, true>(P, A, s);
 }
 
 template <int LP>
 lat_status launch_apply3d(const lat_plan *P, const ApplyArgs &A, int mode, hipStream_t s)
 {
-    dim3 grid((unsigned)lat_cdiv(P->npacked, APPLY3_RUN)), block(512);
+    dim3 grid((unsigned)apply3d_grid(P)), block(512);
     const int32_t *qgroup = P->goff + P->ngroups + 1;
 #define A3(NRV, MD) hipLaunchKernelGGL((k_apply3d_mfma<NRV, MD, LP>), grid, block, 0, s, A, A.goff, A.unode, A.unbr, \
                                        A.umask, A.K, A.alpha_il, A.X, A.Y, (int)P->npacked, qgroup)
@@ -1105,6 +1200,7 @@ ApplyArgs base_args(const lat_plan *P, int m, int nch)
 {
     ApplyArgs A{};
     A.nn = P->nn; A.m = m; A.cap = P->cap; A.ld = P->ld; A.nch = nch;
+    A.rb = 0; A.mc = m;
     A.chunks_per_group = (int)lat_cdiv(std::max(P->maxunion, 1), nch);
     A.goff = P->goff; A.unode = P->unode; A.unbr = P->unbr; A.umask = P->umask;
     return A;
@@ -1113,33 +1209,159 @@ ApplyArgs base_args(const lat_plan *P, int m, int nch)
 constexpr int APPLY_NODES_PER_WAVE = 4;
 constexpr int FORM_NODES_PER_WAVE = 8;
 
+lat_status interleave_alpha(const lat_plan *P, int n_r, const double *alpha, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_alpha_il, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->cap), dim3(256), 0, s, P->ld,
+                       P->cap, n_r, P->perm, alpha, P->alpha_il);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
+// One pass of the ROM apply (mode 0, or 1 = transposed) through the walk kernels, over all right-hand
+// sides in chunks of 16, 8 or fewer columns.  LP: 0 = FP64 combination, 1..3 = bf16 slice levels,
+// 4 = FP32 operands.  A.errp (reduced precision) receives the error partials of the first chunk
+// (the combination is the same for every chunk).
+template <int LP>
+lat_status walk_pass_lp(const lat_plan *P, ApplyArgs A, int mode, hipStream_t s)
+{
+    const int m = A.m;
+    for (int rb = 0; rb < m;) {
+        const int rest = m - rb;
+        A.rb = rb;
+        A.mc = rest >= 16 ? 16 : (rest >= 8 ? 8 : rest);
+        lat_status st;
+        if (P->dim == 2) st = mode == 0 ? launch_rowwalk_chunk<0, LP>(P, A, s) : launch_rowwalk_chunk<1, LP>(P, A, s);
+        else st = launch_apply3d<LP>(P, A, mode, s);
+        if (st != LAT_OK) return st;
+        A.errp = nullptr;
+        rb += A.mc;
+    }
+    return LAT_OK;
+}
+
+lat_status walk_pass(const lat_plan *P, const ApplyArgs &A, int mode, int lev, hipStream_t s)
+{
+    switch (lev) {
+    case 0: return walk_pass_lp<0>(P, A, mode, s);
+    case 1: return walk_pass_lp<1>(P, A, mode, s);
+    case 2: return walk_pass_lp<2>(P, A, mode, s);
+    case 3: return walk_pass_lp<3>(P, A, mode, s);
+    default: return walk_pass_lp<4>(P, A, mode, s);
+    }
+}
+
+// FP64 apply: ROM (mode 0), transposed ROM (mode 1) or plain per-cell (mode 2).
 lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, const double *alpha, const double *X,
                      double *Y, int m, hipStream_t s)
 {
     if (P->npacked == 0) return LAT_OK;              // no owned DOF anywhere: nothing to write
     ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
     A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
+    lat_status st;
     if (mode != 2) {
-        hipLaunchKernelGGL(k_alpha_il, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->cap), dim3(256), 0, s, P->ld,
-                           P->cap, n_r, P->perm, alpha, P->alpha_il);
-        LAT_LAUNCH_CHECK();
+        if ((st = interleave_alpha(P, n_r, alpha, s)) != LAT_OK) return st;
         A.alpha_il = P->alpha_il;
     }
     const int nwaves = P->ngroups * A.chunks_per_group;
-    // the row walk: m in {8, 16}; for the ROM modes also m in {1, 2, 4} (waves past m idle in the
-    // apply; the combination on the matrix cores is what the walk buys there), while the per-cell
-    // stencil apply with so few right-hand sides streams faster in the per-group kernel
-    if (P->dim == 2 && P->nn >= 3 && (m == 8 || m == 16 || (mode != 2 && (m == 1 || m == 2 || m == 4))))
-        return launch_rowwalk(P, A, mode, s);
-    if (P->dim == 2) {
-        if (mode == 0) return launch_apply<2, 0>(A, nwaves, s);
-        if (mode == 1) return launch_apply<2, 1>(A, nwaves, s);
-        return launch_apply<2, 2>(A, nwaves, s);
+    if (mode == 2) {
+        // the per-cell stencil apply: the 2D row walk for m in {8, 16}; with fewer right-hand sides
+        // the per-group kernel streams the stencils faster
+        if (P->dim == 2 && P->nn >= 3 && (m == 8 || m == 16))
+            return m == 16 ? launch_rowwalk_nr<2, 2, 0, false>(P, A, s) : launch_rowwalk_nr<1, 2, 0, false>(P, A, s);
+        return P->dim == 2 ? launch_apply<2, 2>(A, nwaves, s) : launch_apply<3, 2>(A, nwaves, s);
     }
-    if (mode != 2 && m <= 16) return launch_apply3d<0>(P, A, mode, s);
-    if (mode == 0) return launch_apply<3, 0>(A, nwaves, s);
-    if (mode == 1) return launch_apply<3, 1>(A, nwaves, s);
-    return launch_apply<3, 2>(A, nwaves, s);
+    if (P->dim == 2 && P->nn < 3) return mode == 0 ? launch_apply<2, 0>(A, nwaves, s) : launch_apply<2, 1>(A, nwaves, s);
+    return walk_pass(P, A, mode, 0, s);
+}
+
+// Relative error estimate of one reduced-precision pass: err = sqrt(sum d2 / sum r2) over the
+// per-block partials (fixed order: strided per-thread sums, then a tree); the next pass's gate
+// opens when err > tol (or err is not a number).  A pass that its own gate skipped leaves the
+// estimate as it is and closes the next gate.
+__global__ __launch_bounds__(256) void k_lp_err(int64_t nblk, const double *__restrict__ part, double tol,
+                                                const int32_t *gate_in, int32_t *gate_out, double *err_est)
+{
+    __shared__ double sa[256], sb[256];
+    if (gate_in && *gate_in == 0) {
+        if (threadIdx.x == 0) *gate_out = 0;
+        return;
+    }
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nblk; i += 256) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double d = sa[0], r = sb[0];
+        const double err = r > 0.0 ? sqrt(d / r) : (d > 0.0 ? INFINITY : 0.0);
+        if (err_est) *err_est = err;
+        *gate_out = (err <= tol) ? 0 : 1;
+    }
+}
+
+// The FP64 pass of a refinement chain ran: its combination is the FP64 one, estimate 0.
+__global__ void k_lp_exact(const int32_t *gate, double *err_est)
+{
+    if (threadIdx.x == 0 && *gate && err_est) *err_est = 0.0;
+}
+
+__global__ void k_fill_scalar(double *x, double v)
+{
+    if (threadIdx.x == 0) *x = v;
+}
+
+// Reduced-precision ROM apply with FP64-measured refinement.  The combination sum_k c_ik K_k runs
+// in reduced precision (prec F32: FP32 operands on the FP32 matrix cores; BF16: bf16 slices in
+// levels), the apply of the combined stencil in FP64.  Every pass measures its combination
+// against the FP64 one at one node (2D) or stencil slice (3D) per workgroup; when that relative
+// estimate exceeds refine_tol the apply runs again with one more bf16 level, and after the third
+// level (or after FP32) with the FP64 combination.  The passes are chained by device gates: no host
+// synchronisation, the skipped passes exit at once.
+lat_status run_apply_lowp(const lat_plan *P, int mode, const double *K, int n_r, const double *coef, const double *X,
+                          double *Y, int m, int prec, double refine_tol, double *err_est, hipStream_t s)
+{
+    lat_status st;
+    if (n_r < 1 || P->npacked == 0 || (P->dim == 2 && P->nn < 3)) {
+        // nothing to combine, or a lattice too small for the walks: the FP64 apply, estimate 0
+        if ((st = run_apply(P, mode, K, n_r, coef, X, Y, m, s)) != LAT_OK) return st;
+        if (err_est) {
+            hipLaunchKernelGGL(k_fill_scalar, dim3(1), dim3(64), 0, s, err_est, 0.0);
+            LAT_LAUNCH_CHECK();
+        }
+        return LAT_OK;
+    }
+    ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
+    A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
+    if ((st = interleave_alpha(P, n_r, coef, s)) != LAT_OK) return st;
+    A.alpha_il = P->alpha_il;
+    const int64_t nblk = P->dim == 2 ? rowwalk_grid(P) : apply3d_grid(P);
+    int lev = prec == LAT_F32 ? 4 : (refine_tol >= 0x1p-8 ? 1 : (refine_tol >= 0x1p-16 ? 2 : 3));
+    const int32_t *gate = nullptr;
+    for (int gi = 0;; ++gi) {
+        A.gate = gate;
+        A.errp = lev ? P->lp_err : nullptr;
+        if ((st = walk_pass(P, A, mode, lev, s)) != LAT_OK) return st;
+        if (lev == 0) {
+            hipLaunchKernelGGL(k_lp_exact, dim3(1), dim3(64), 0, s, gate, err_est);
+            LAT_LAUNCH_CHECK();
+            return LAT_OK;
+        }
+        hipLaunchKernelGGL(k_lp_err, dim3(1), dim3(256), 0, s, nblk, P->lp_err, refine_tol, gate, P->lp_gate + gi,
+                           err_est);
+        LAT_LAUNCH_CHECK();
+        gate = P->lp_gate + gi;
+        lev = lev >= 3 ? 0 : lev + 1;
+    }
 }
 
 // Fused forms for ns (1..3) stacks -> P->form_part laid out [stack][chunk][ld][cap].
@@ -1202,38 +1424,111 @@ lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *
     return lat_tree_reduce(P->form_part, A.chunks_per_group, P->ld * P->cap, 0, out_pl, P->g_t1, P->g_t2, s);
 }
 
-}  // namespace
-
-lat_status lat_apply_lowp_walk(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
-                               double *Y, int m, int nlev, hipStream_t s)
+// The adjoint forms of the requested stacks (ROM coefficients, Lame parts) with the plan copy V's
+// scratch.  With the caller's W buffer: one streaming W pass (FP64, or FP32 when prec != LAT_F64),
+// then one row contraction per stack (or one pass for all of them when n_r <= 32); without it the
+// fused per-node kernel (m <= 16), or one per-node pass per stack.
+lat_status run_adjoint_forms(const lat_plan *V, const double *K, const double *K_mu, const double *K_lam,
+                             const int32_t *S, int n_r, const double *alpha, const double *X, const double *Ybar,
+                             int m, double *alpha_bar, double *mu_bar, double *lam_bar, int prec, hipStream_t stream)
 {
-    if (P->npacked == 0) return LAT_OK;
-    ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
-    A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
-    hipLaunchKernelGGL(k_alpha_il, dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->cap), dim3(256), 0, s, P->ld,
-                       P->cap, n_r, P->perm, coef, P->alpha_il);
-    LAT_LAUNCH_CHECK();
-    A.alpha_il = P->alpha_il;
-    if (P->dim == 3) {
-        if (nlev == 1) return launch_apply3d<1>(P, A, 0, s);
-        if (nlev == 2) return launch_apply3d<2>(P, A, 0, s);
-        if (nlev == 3) return launch_apply3d<3>(P, A, 0, s);
-        return launch_apply3d<4>(P, A, 0, s);
+    lat_status st;
+    const dim3 lg((unsigned)lat_cdiv(V->ld, 256));
+    const double *stk[3];
+    int role[3], ns = 0;
+    if (alpha_bar) { stk[ns] = K; role[ns++] = 0; }
+    if (mu_bar) { stk[ns] = K_mu; role[ns++] = 1; }
+    if (lam_bar) { stk[ns] = K_lam; role[ns++] = 2; }
+    if (ns == 0) return LAT_OK;
+    auto finish = [&](int t) -> lat_status {      // form_out [ld][cap] -> the requested output
+        if (role[t] == 0) {
+            hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, V->ld, V->cap, V->perm, V->form_out, alpha_bar);
+        } else {
+            double *bar = role[t] == 1 ? mu_bar : lam_bar;
+            hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)lat_cdiv(V->ncells, 256)), dim3(256), 0, stream, V->ncells,
+                               bar);
+            if (n_r > 0)
+                hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)n_r), dim3(256), 0, stream, V->ncells, V->cap, S,
+                                   V->lane, alpha, V->form_out, bar);
+        }
+        LAT_LAUNCH_CHECK();
+        return LAT_OK;
+    };
+    if (V->npacked == 0 || m > 16 || V->cap < 16) {
+        // one per-node pass per stack
+        for (int t = 0; t < ns; ++t) {
+            if ((st = run_forms(V, stk[t], n_r, X, Ybar, m, V->form_out, stream)) != LAT_OK) return st;
+            if ((st = finish(t)) != LAT_OK) return st;
+        }
+        return LAT_OK;
     }
-    return m == 16 ? launch_rowwalk_bf16_mw<2>(P, A, nlev, s) : launch_rowwalk_bf16_mw<1>(P, A, nlev, s);
+    const bool low = prec != LAT_F64 && V->w_forms32;
+    const bool haveW = low || V->w_forms;
+    int cpg = 0;
+    if (haveW) {
+        const dim3 wg((unsigned)lat_cdiv(V->ld, 256), (unsigned)V->nloc);
+        if (low) {
+            if (V->dim == 2)
+                hipLaunchKernelGGL((k_forms_W<2, float>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff, V->uidx,
+                                   V->unbr, V->umask, X, Ybar, V->w_forms32);
+            else
+                hipLaunchKernelGGL((k_forms_W<3, float>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff, V->uidx,
+                                   V->unbr, V->umask, X, Ybar, V->w_forms32);
+        } else {
+            if (V->dim == 2)
+                hipLaunchKernelGGL((k_forms_W<2, double>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff,
+                                   V->uidx, V->unbr, V->umask, X, Ybar, V->w_forms);
+            else
+                hipLaunchKernelGGL((k_forms_W<3, double>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff,
+                                   V->uidx, V->unbr, V->umask, X, Ybar, V->w_forms);
+        }
+        LAT_LAUNCH_CHECK();
+    } else if ((st = run_forms_fused(V, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) {
+        return st;
+    }
+    const int64_t ldc = V->ld * V->cap;
+    const double *W64 = low ? nullptr : V->w_forms;
+    const float *W32 = low ? V->w_forms32 : nullptr;
+    // n_r <= 32: the stacks' contractions share one pass over W (chunk partials per stack)
+    const bool multi = haveW && n_r <= 32;
+    double *wparts[3] = {V->wf_part, V->wf_part + V->aa_nchunk * ldc, V->wf_part + 2 * V->aa_nchunk * ldc};
+    if (multi && (st = lat_contract_rows_multi(V, n_r, W64, W32, stk, ns, wparts, stream)) != LAT_OK) return st;
+    for (int t = 0; t < ns; ++t) {
+        if (multi) st = lat_tree_reduce(wparts[t], V->aa_nchunk, ldc, 0, V->form_out, V->g_t1, V->g_t2, stream);
+        else if (haveW) st = lat_contract_rows(V, n_r, W64, W32, stk[t], V->form_out, stream);
+        else st = lat_tree_reduce(V->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, V->form_out, V->g_t1, V->g_t2,
+                                  stream);
+        if (st != LAT_OK) return st;
+        if ((st = finish(t)) != LAT_OK) return st;
+    }
+    return LAT_OK;
 }
+
+}  // namespace
 
 extern "C" {
 
 lat_status lat_apply_combo(const lat_plan *P, const double *K, int32_t n_r, const double *alpha, const double *X,
-                           double *Y, int32_t m, lat_prec prec, double refine_tol, int32_t transpose,
-                           hipStream_t stream)
+                           double *Y, int32_t m, lat_prec prec, double refine_tol, int32_t transpose, double *err_est,
+                           void *work, size_t work_bytes, hipStream_t stream)
 {
     if (!P || !K || !alpha || !X || !Y || m < 1) return LAT_E_ARG;
     if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
-    if (prec == LAT_F64) return run_apply(P, transpose ? 1 : 0, K, n_r, alpha, X, Y, m, stream);
-    if ((prec != LAT_F32 && prec != LAT_BF16) || transpose) return LAT_E_ARG;
-    return lat_apply_lowp(P, K, n_r, alpha, X, Y, m, prec, refine_tol, stream);
+    if (prec != LAT_F64 && prec != LAT_F32 && prec != LAT_BF16) return LAT_E_ARG;
+    if (!(refine_tol >= 0.0)) return LAT_E_ARG;
+    lat_plan V;
+    lat_status st = lat_ws_bind(P, LAT_CALL_APPLY_COMBO, work, work_bytes, &V);
+    if (st != LAT_OK) return st;
+    const int mode = transpose ? 1 : 0;
+    if (prec == LAT_F64) {
+        if ((st = run_apply(&V, mode, K, n_r, alpha, X, Y, m, stream)) != LAT_OK) return st;
+        if (err_est) {
+            hipLaunchKernelGGL(k_fill_scalar, dim3(1), dim3(64), 0, stream, err_est, 0.0);
+            LAT_LAUNCH_CHECK();
+        }
+        return LAT_OK;
+    }
+    return run_apply_lowp(&V, mode, K, n_r, alpha, X, Y, m, prec, refine_tol, err_est, stream);
 }
 
 lat_status lat_apply_plain(const lat_plan *P, const double *plain_ops, const double *X, double *Y, int32_t m,
@@ -1246,93 +1541,27 @@ lat_status lat_apply_plain(const lat_plan *P, const double *plain_ops, const dou
 lat_status lat_apply_combo_adjoint(const lat_plan *P, const double *K, const double *K_mu, const double *K_lam,
                                    const int32_t *S, int32_t n_r, const double *alpha, const double *X,
                                    const double *Ybar, int32_t m, double *Xbar, double *alpha_bar, double *mu_bar,
-                                   double *lam_bar, hipStream_t stream)
+                                   double *lam_bar, lat_prec prec, double refine_tol, double *err_est, void *work,
+                                   size_t work_bytes, hipStream_t stream)
 {
     if (!P || !K || !alpha || !X || !Ybar || m < 1) return LAT_E_ARG;
     if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
     if ((mu_bar && !K_mu) || (lam_bar && !K_lam) || ((mu_bar || lam_bar) && !S)) return LAT_E_ARG;
-    lat_status st;
-    if (Xbar && (st = run_apply(P, 1, K, n_r, alpha, Ybar, Xbar, m, stream)) != LAT_OK) return st;
-    const dim3 lg((unsigned)lat_cdiv(P->ld, 256));
-    if (m <= 16 && P->cap >= 16 && (alpha_bar || mu_bar || lam_bar) && P->npacked > 0) {
-        // one pass over X and Ybar for every requested stack
-        const double *stk[3];
-        int role[3], ns = 0;
-        if (alpha_bar) { stk[ns] = K; role[ns++] = 0; }
-        if (mu_bar) { stk[ns] = K_mu; role[ns++] = 1; }
-        if (lam_bar) { stk[ns] = K_lam; role[ns++] = 2; }
-        // the cells' W once (a streaming pass over X and Ybar), then one row contraction per stack on
-        // the matrix cores; the fused per-node kernel serves when W's workspace cannot be had
-        lat_plan *Pm = const_cast<lat_plan *>(P);
-        if (!Pm->w_forms && !Pm->w_forms_failed) {
-            const size_t bytes = (size_t)P->nsnap * P->ld * sizeof(double);
-            const size_t pbytes = (size_t)3 * P->aa_nchunk * P->ld * P->cap * sizeof(double);
-            if (bytes > ((size_t)16 << 30) || hipMalloc((void **)&Pm->w_forms, bytes) != hipSuccess ||
-                hipMalloc((void **)&Pm->wf_part, pbytes) != hipSuccess) {
-                if (Pm->w_forms) (void)hipFree(Pm->w_forms);
-                Pm->w_forms = nullptr;
-                Pm->wf_part = nullptr;
-                Pm->w_forms_failed = true;
-                (void)hipGetLastError();
-            }
-        }
-        int cpg = 0;
-        if (P->w_forms) {
-            const dim3 wg((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc);
-            if (P->dim == 2)
-                hipLaunchKernelGGL(k_forms_W<2>, wg, dim3(256), 0, stream, P->ld, P->nloc, m, P->goff, P->uidx, P->unbr,
-                                   P->umask, X, Ybar, P->w_forms);
-            else
-                hipLaunchKernelGGL(k_forms_W<3>, wg, dim3(256), 0, stream, P->ld, P->nloc, m, P->goff, P->uidx, P->unbr,
-                                   P->umask, X, Ybar, P->w_forms);
-            LAT_LAUNCH_CHECK();
-        } else if ((st = run_forms_fused(P, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) {
-            return st;
-        }
-        const int64_t ldc = P->ld * P->cap;
-        // n_r <= 32: the stacks' contractions share one pass over W (chunk partials per stack)
-        const bool multi = P->w_forms && n_r <= 32;
-        double *wparts[3] = {P->wf_part, P->wf_part + P->aa_nchunk * ldc, P->wf_part + 2 * P->aa_nchunk * ldc};
-        if (multi && (st = lat_contract_rows_multi(P, n_r, P->w_forms, stk, ns, wparts, stream)) != LAT_OK) return st;
-        for (int t = 0; t < ns; ++t) {
-            if (multi) st = lat_tree_reduce(wparts[t], P->aa_nchunk, ldc, 0, P->form_out, P->g_t1, P->g_t2, stream);
-            else if (P->w_forms) st = lat_contract_rows(P, n_r, P->w_forms, stk[t], P->form_out, stream);
-            else st = lat_tree_reduce(P->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, P->form_out, P->g_t1, P->g_t2,
-                                      stream);
-            if (st != LAT_OK) return st;
-            if (role[t] == 0) {
-                hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, P->ld, P->cap, P->perm, P->form_out,
-                                   alpha_bar);
-            } else {
-                double *bar = role[t] == 1 ? mu_bar : lam_bar;
-                hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)lat_cdiv(P->ncells, 256)), dim3(256), 0, stream,
-                                   P->ncells, bar);
-                if (n_r > 0)
-                    hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)n_r), dim3(256), 0, stream, P->ncells, P->cap, S,
-                                       P->lane, alpha, P->form_out, bar);
-            }
-            LAT_LAUNCH_CHECK();
-        }
-        return LAT_OK;
+    if (prec != LAT_F64 && prec != LAT_F32 && prec != LAT_BF16) return LAT_E_ARG;
+    if (!(refine_tol >= 0.0)) return LAT_E_ARG;
+    lat_plan V;
+    lat_status st = lat_ws_bind(P, LAT_CALL_APPLY_COMBO_ADJOINT, work, work_bytes, &V);
+    if (st != LAT_OK) return st;
+    if (Xbar) {
+        if (prec == LAT_F64) st = run_apply(&V, 1, K, n_r, alpha, Ybar, Xbar, m, stream);
+        else st = run_apply_lowp(&V, 1, K, n_r, alpha, Ybar, Xbar, m, prec, refine_tol, err_est, stream);
+        if (st != LAT_OK) return st;
     }
-    if (alpha_bar) {
-        if ((st = run_forms(P, K, n_r, X, Ybar, m, P->form_out, stream)) != LAT_OK) return st;
-        hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, P->ld, P->cap, P->perm, P->form_out, alpha_bar);
+    if (err_est && (prec == LAT_F64 || !Xbar)) {
+        hipLaunchKernelGGL(k_fill_scalar, dim3(1), dim3(64), 0, stream, err_est, 0.0);
         LAT_LAUNCH_CHECK();
     }
-    const double *parts[2] = {K_mu, K_lam};
-    double *bars[2] = {mu_bar, lam_bar};
-    for (int t = 0; t < 2; ++t) {
-        if (!bars[t]) continue;
-        if ((st = run_forms(P, parts[t], n_r, X, Ybar, m, P->form_out, stream)) != LAT_OK) return st;
-        hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)lat_cdiv(P->ncells, 256)), dim3(256), 0, stream, P->ncells,
-                           bars[t]);
-        if (n_r > 0)
-            hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)n_r), dim3(256), 0, stream, P->ncells, P->cap, S, P->lane,
-                               alpha, P->form_out, bars[t]);
-        LAT_LAUNCH_CHECK();
-    }
-    return LAT_OK;
+    return run_adjoint_forms(&V, K, K_mu, K_lam, S, n_r, alpha, X, Ybar, m, alpha_bar, mu_bar, lam_bar, prec, stream);
 }
 
 }  // extern "C"

@@ -653,15 +653,19 @@ int64_t lat_snapshot_rows(const lat_plan *P, lat_rule rule)
     }
 }
 
-lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
+lat_status lat_residual_tangent(const lat_plan *Pp, const double *u_global, const double *mu, const double *lam,
                                 lat_rule snap_rule, double *f_int, double *energy, double *snap, double *plain_ops,
-                                int32_t *dev_status, hipStream_t stream)
+                                int32_t *dev_status, void *work, size_t work_bytes, hipStream_t stream)
 {
-    if (!P || !u_global || !mu || !lam) return LAT_E_ARG;
+    if (!Pp || !u_global || !mu || !lam) return LAT_E_ARG;
     if (snap_rule != LAT_RULE_FULL && snap_rule != LAT_RULE_REDUCED && snap_rule != LAT_RULE_MATERIAL &&
         snap_rule != LAT_RULE_SAMPLED)
         return LAT_E_ARG;
-    lat_status st = gather_u(P, u_global, dev_status, stream);
+    lat_plan V;
+    lat_status st = lat_ws_bind(Pp, LAT_CALL_RESIDUAL_TANGENT, work, work_bytes, &V);
+    if (st != LAT_OK) return st;
+    const lat_plan *P = &V;
+    st = gather_u(P, u_global, dev_status, stream);
     if (st != LAT_OK) return st;
     CellArgs A = base_args(P);
     A.mu = mu; A.lam = lam; A.matmode = 0; A.st = dev_status;
@@ -712,13 +716,17 @@ lat_status lat_residual_tangent(const lat_plan *P, const double *u_global, const
     return LAT_OK;
 }
 
-lat_status lat_principal_ops(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
+lat_status lat_principal_ops(const lat_plan *Pp, const double *u_global, const double *mu, const double *lam,
                              const int32_t *S, int32_t n_r, double *K, double *K_mu, double *K_lam,
-                             int32_t *dev_status, hipStream_t stream)
+                             int32_t *dev_status, void *work, size_t work_bytes, hipStream_t stream)
 {
-    if (!P || !u_global || !mu || !lam || !S || !K) return LAT_E_ARG;
-    if (n_r < 0 || n_r > P->cap) return LAT_E_SHAPE;
-    lat_status st = gather_u(P, u_global, dev_status, stream);
+    if (!Pp || !u_global || !mu || !lam || !S || !K) return LAT_E_ARG;
+    if (n_r < 0 || n_r > Pp->cap) return LAT_E_SHAPE;
+    lat_plan V;
+    lat_status st = lat_ws_bind(Pp, LAT_CALL_PRINCIPAL_OPS, work, work_bytes, &V);
+    if (st != LAT_OK) return st;
+    const lat_plan *P = &V;
+    st = gather_u(P, u_global, dev_status, stream);
     if (st != LAT_OK) return st;
     double *outs[3] = {K, K_mu, K_lam};
     for (int mode = 0; mode < 3; ++mode) {
@@ -731,13 +739,18 @@ lat_status lat_principal_ops(const lat_plan *P, const double *u_global, const do
     return LAT_OK;
 }
 
-lat_status lat_residual_adjoint(const lat_plan *P, const double *u_global, const double *mu, const double *lam,
+lat_status lat_residual_adjoint(const lat_plan *Pp, const double *u_global, const double *mu, const double *lam,
                                 const double *w, double *ubar_local, double *ubar_global, double *mu_bar,
-                                double *lam_bar, int32_t *dev_status, hipStream_t stream)
+                                double *lam_bar, int32_t *dev_status, void *work, size_t work_bytes,
+                                hipStream_t stream)
 {
-    if (!P || !u_global || !mu || !lam || !w) return LAT_E_ARG;
+    if (!Pp || !u_global || !mu || !lam || !w) return LAT_E_ARG;
     if (ubar_global && !ubar_local) return LAT_E_ARG;     // assembly reads the local result
-    lat_status st = gather_u(P, u_global, dev_status, stream);
+    lat_plan V;
+    lat_status st = lat_ws_bind(Pp, LAT_CALL_RESIDUAL_ADJOINT, work, work_bytes, &V);
+    if (st != LAT_OK) return st;
+    const lat_plan *P = &V;
+    st = gather_u(P, u_global, dev_status, stream);
     if (st != LAT_OK) return st;
     dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)P->nloc);
     if (P->dim == 2)

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(1024) void k_select(int64_t ld, const int32_t *__re
             ictl[C_DONE] = 1;
             *n_r = it;
             ictl[C_NR] = it;
-            if (st) { atomicMax(&st[0], LAT_W_CAP); }
+            lat_flag(st, LAT_W_CAP, 0x7fffffff);
         } else {
             ictl[C_SEL] = bl[0];
             ictl[C_CELL] = bc[0];
@@ -377,23 +377,29 @@ lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, 
 
 extern "C" lat_status lat_select_principal(const lat_plan *P, double *snap, double tol, int32_t cap, int32_t *S,
                                            int32_t *n_r, double *alpha, double *beta, double *nu, double *R, double *Z,
-                                           double *achieved, int32_t *dev_status, hipStream_t stream)
+                                           double *achieved, int32_t *dev_status, void *work, size_t work_bytes,
+                                           hipStream_t stream)
 {
     if (!P) return LAT_E_ARG;
     return lat_select_principal_rows(P, snap, P->nsnap, tol, cap, S, n_r, alpha, beta, nu, R, Z, achieved,
-                                     dev_status, stream);
+                                     dev_status, work, work_bytes, stream);
 }
 
 // The greedy on the first `rows` snapshot rows: the chunk sums and pairwise trees take a zero
 // chunk without rounding, so when the rows past `rows` are zero the result is the full sweep's,
 // bit for bit, at the cost of the data rows only.
-extern "C" lat_status lat_select_principal_rows(const lat_plan *P, double *snap, int64_t rows, double tol, int32_t cap,
+extern "C" lat_status lat_select_principal_rows(const lat_plan *Pp, double *snap, int64_t rows, double tol, int32_t cap,
                                                 int32_t *S, int32_t *n_r, double *alpha, double *beta, double *nu,
                                                 double *R, double *Z, double *achieved, int32_t *dev_status,
-                                                hipStream_t stream)
+                                                void *work, size_t work_bytes, hipStream_t stream)
 {
-    if (!P || !snap || !S || !n_r || !alpha || !R || !achieved) return LAT_E_ARG;
-    if (!(tol > 0.0) || cap < 1 || cap > P->cap || rows < 1 || rows > P->nsnap) return LAT_E_ARG;
+    if (!Pp || !snap || !S || !n_r || !alpha || !R || !achieved) return LAT_E_ARG;
+    if (!(tol > 0.0) || cap < 1) return LAT_E_ARG;
+    if (cap > Pp->cap || rows < 1 || rows > Pp->nsnap) return LAT_E_SHAPE;
+    lat_plan V;
+    lat_status st0 = lat_ws_bind(Pp, LAT_CALL_SELECT_PRINCIPAL, work, work_bytes, &V);
+    if (st0 != LAT_OK) return st0;
+    const lat_plan *P = &V;
     const int64_t ld = P->ld, ns = rows, nc = lat_cdiv(rows, LAT_CHUNK);
     const dim3 cg = chunk_grid(ld, nc);
     const dim3 lg((unsigned)lat_cdiv(ld, 256));

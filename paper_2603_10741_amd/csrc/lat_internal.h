@@ -65,16 +65,17 @@ struct lat_plan {
     double *aa_part = nullptr;     // partials for the alpha adjoint
     int64_t aa_nchunk = 0;
     int aa_rows = 4096;            // snapshot rows per alpha-adjoint chunk
-    // reduced-precision ROM apply
-    int EP;                        // stencil entries padded to a multiple of 16
-    uint16_t *lp_kslice = nullptr; // [3][nloc][EP][64] bf16 slices of a principal stack
-    uint16_t *lp_cslice = nullptr; // [3][ld][64] bf16 slices of the coefficients (plan order)
-    float *lp_kf32 = nullptr;      // [nloc][E][cap] FP32 principal stack
-    float *lp_cf32 = nullptr;      // [cap][ld] FP32 coefficients
-    // adjoint forms: W[(a, e)][lane] = sum_r Ybar X, allocated on the first ROM-apply adjoint
+    int64_t tree_elems = 0;        // size of each tree scratch array (g_t1 .. g_t4)
+    int nblk_lp = 0;               // largest grid of a walk kernel (per-block error partials)
+    // reduced-precision ROM apply: the FP64-measured error estimate and the refinement gates
+    double *lp_err = nullptr;      // [nblk_lp][2] per-block (sum |K~ - K~64|^2, sum |K~64|^2)
+    int32_t *lp_gate = nullptr;    // [8] refinement gates (1 = the next, more precise pass runs)
+    // adjoint forms: W[(a, e)][lane] = sum_r Ybar X (FP64, or FP32 in w_forms32), and the alpha
+    // adjoint's second uniform operand; only in a caller workspace of the "fast" size
     double *w_forms = nullptr;     // [nsnap][ld]
+    float *w_forms32 = nullptr;    // [nsnap][ld]
     double *wf_part = nullptr;     // [3][aa_nchunk][ld][cap] contraction partials of the stacks
-    bool w_forms_failed = false;   // the allocation was refused (too large): the fused kernel serves
+    double *aa_gath2 = nullptr;    // [nsnap][cap]
 };
 
 // ---- bf16 slices (reduced-precision combination on the bf16 matrix cores)
@@ -128,14 +129,32 @@ __device__ __forceinline__ int lat_xcd_block(int b, int n)
     return x * q + (x < r ? x : r) + s;
 }
 
-// Device status word helpers.
+// Device status word helpers.  The code word keeps the most severe code raised so far: OK below the
+// cap warning below every error (among errors, the larger code), so a warning raised after an
+// error never hides it.  The cell word keeps the lowest canonical id of a cell that raised an
+// error (warnings carry no cell).
+__device__ __forceinline__ int lat_severity(int code)
+{
+    return code == LAT_OK ? 0 : (code == LAT_W_CAP ? 1 : 2 + code);
+}
 __device__ inline void lat_flag(int32_t *st, int code, int cell)
 {
-    if (st) {
-        atomicMax(&st[0], code);
-        atomicMin(&st[1], cell);
+    if (!st) return;
+    int old = __hip_atomic_load(&st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (lat_severity(code) > lat_severity(old)) {
+        const int prev = atomicCAS(&st[0], old, code);
+        if (prev == old) break;
+        old = prev;
     }
+    if (code != LAT_W_CAP) atomicMin(&st[1], cell);
 }
+
+// Caller workspaces (defined in lat_plan.hip).  A call's scratch is carved from `work` into a copy
+// of the plan (*V = *P with its scratch pointers moved into work); the kernels read the copy.
+// work == NULL: V keeps the plan's own scratch (no "fast"-only buffers).  LAT_E_SHAPE when
+// work_bytes is below the call's minimum, LAT_E_ARG when work is not 256-byte aligned.
+lat_status lat_ws_bind(const lat_plan *P, int call, void *work, size_t work_bytes, lat_plan *V);
+void lat_ws_sizes(const lat_plan *P, int call, size_t *min_bytes, size_t *fast_bytes);
 
 // Shared internal launches (defined in lat_greedy.hip).
 // Pairwise-tree reduction over rows of in [nrows][ld] (row-major, lanes fastest), applying
@@ -143,19 +162,13 @@ __device__ inline void lat_flag(int32_t *st, int code, int cell)
 lat_status lat_tree_reduce(const double *in, int64_t nrows, int64_t ld, int op, double *out, double *t1,
                            double *t2, hipStream_t s);
 
-// Row contraction out[p][k] = sum_j V[j][p] U[j][k] over the n_snap snapshot rows, V [nsnap][ld],
+// Row contraction out[p][k] = sum_j V[j][p] U[j][k] over the n_snap snapshot rows, V [nsnap][ld]
+// (FP64 in V, or FP32 in V32: exactly one of them is non-NULL; the products and sums are FP64),
 // U [nsnap][cap] (a principal stack), out [ld][cap] in plan order; fixed-order chunk partials and
 // tree (defined in lat_adjoint.hip).
-lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const double *U, double *out, hipStream_t s);
+lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const float *V32, const double *U,
+                             double *out, hipStream_t s);
 // The same for ns (1..3) stacks in one pass over V (n_r <= 32, cap >= 16): chunk partials
 // part[t] [aa_nchunk][ld][cap], to be reduced by lat_tree_reduce.
-lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const double *const *U, int ns,
-                                   double *const *part, hipStream_t s);
-
-// Reduced-precision ROM apply (defined in lat_lowp.hip).
-// ROM apply with a reduced-precision combination inside the 2D row walk / 3D slice walk:
-// nlev 1..3 = bf16 slice products of that many levels, 4 = FP32 operands; coef plays alpha
-lat_status lat_apply_lowp_walk(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X,
-                               double *Y, int m, int nlev, hipStream_t s);
-lat_status lat_apply_lowp(const lat_plan *P, const double *K, int n_r, const double *coef, const double *X, double *Y,
-                          int m, int prec, double refine_tol, hipStream_t s);
+lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const float *V32,
+                                   const double *const *U, int ns, double *const *part, hipStream_t s);

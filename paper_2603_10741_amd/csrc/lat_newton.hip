@@ -953,7 +953,7 @@ lat_status coarse_operator(const lat_plan *P, MrWork &w, const double *K, int n_
                            const double *ops, hipStream_t s)
 {
     if (ops) NCHK(lat_apply_plain(P, ops, w.Xc, w.Yc, w.mc, s));
-    else NCHK(lat_apply_combo(P, K, n_r, alpha, w.Xc, w.Yc, w.mc, LAT_F64, 0.0, 0, s));
+    else NCHK(lat_apply_combo(P, K, n_r, alpha, w.Xc, w.Yc, w.mc, LAT_F64, 0.0, 0, nullptr, nullptr, 0, s));
     const dim3 cg((unsigned)P->ngroups, (unsigned)w.mc);
     if (w.mc == 8)
         hipLaunchKernelGGL(k_coarse_cellmat<8>, cg, dim3(LAT_WAVE), 0, s, P->dim, P->goff, P->perm, w.Xc, w.Yc, w.K0s);
@@ -1077,7 +1077,7 @@ lat_status mr_run(const lat_plan *P, MrWork &w, const double *K, int n_r, const 
             const bool timed = t_product_us && k >= tskip && ntimed < MrWork::NT;
             if (timed) LAT_HIP(hipEventRecord(w.tev[2 * ntimed], s));
             if (ops) NCHK(lat_apply_plain(P, ops, w.ppk, w.ypk, 1, s));
-            else NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, s));
+            else NCHK(lat_apply_combo(P, K, n_r, alpha, w.ppk, w.ypk, 1, LAT_F64, 0.0, 0, nullptr, nullptr, 0, s));
             if (timed) LAT_HIP(hipEventRecord(w.tev[2 * ntimed++ + 1], s));
             if (P->dim == 2)
                 hipLaunchKernelGGL(k_mr_ap<2>, dim3(w.nbn), dim3(NB), 0, s, P->nglobal, w.own, fixed, w.ypk, zj, w.y,
@@ -1207,7 +1207,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     auto evaluate = [&](const double *at, double lf, double *res, double *norm, int32_t *code) -> lat_status {
         NCHK(lat_status_reset(st_d, s));
         NCHK(lat_residual_tangent(P, at, mu, lam, rule, f_cil, nullptr, full ? nullptr : snap, full ? w.ops : nullptr,
-                                  st_d, s));
+                                  st_d, nullptr, 0, s));
         NCHK(lat_assemble(P, f_cil, d, fasm, s));
         hipLaunchKernelGGL(k_residual, dim3(nbv), dim3(NB), 0, s, n, fasm, f_ext, lf, fixed, res, w.part);
         hipLaunchKernelGGL(k_sum_fin, dim3(1), dim3(NB), 0, s, (int)nbv, w.part, scal);
@@ -1249,7 +1249,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
                 // the greedy reads only the rows the snapshot rule fills
                 const int64_t rows = lat_snapshot_rows(P, rule);
                 NCHK(lat_select_principal_rows(P, snap, rows, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R,
-                                               nullptr, scal + 1, gst_d, s));
+                                               nullptr, scal + 1, gst_d, nullptr, 0, s));
                 int32_t hg[2] = {0, 0};
                 double ach = 0.0;
                 LAT_HIP(hipMemcpyAsync(&hnr, nr_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1257,7 +1257,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
                 LAT_HIP(hipMemcpyAsync(&ach, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
                 LAT_HIP(hipStreamSynchronize(s));
                 NCHK(lat_status_reset(st_d, s));
-                NCHK(lat_principal_ops(P, u, mu, lam, S, hnr, K, nullptr, nullptr, st_d, s));
+                NCHK(lat_principal_ops(P, u, mu, lam, S, hnr, K, nullptr, nullptr, st_d, nullptr, 0, s));
                 if (w.ops) NCHK(combine_ops(P, K, hnr, alpha, w.ops, s));
                 LAT_HIP(hipStreamSynchronize(s));
                 rec.rb_achieved = ach; rec.greedy_status = hg[0];

@@ -348,6 +348,91 @@ lat_status run_dofmap(const lat_plan *P, uint8_t *act, int32_t *flag, int32_t *g
     return LAT_OK;
 }
 
+// ---- caller workspaces
+struct WsItem {
+    void **ptr;          // field of the plan copy
+    size_t bytes;
+    int fast;            // 0: always; 1: only with the "fast" size; 2: the same region as the item before
+};
+
+// The scratch of each call, in carving order (every item starts on a 256-byte boundary).
+int ws_items(const lat_plan *P, lat_plan *V, int call, WsItem *it)
+{
+    int n = 0;
+    auto add = [&](void *field, int64_t elems, size_t esz, int fast) {
+        it[n].ptr = (void **)field;
+        it[n].bytes = (size_t)std::max<int64_t>(elems, 1) * esz;
+        it[n].fast = fast;
+        ++n;
+    };
+    const int64_t ld = P->ld, cap = P->cap, nloc = P->nloc, tr = P->tree_elems;
+    switch (call) {
+    case LAT_CALL_RESIDUAL_TANGENT:
+    case LAT_CALL_RESIDUAL_ADJOINT:
+        add(&V->u_cil, nloc * P->dim * ld, 8, 0);
+        add(&V->w_part, nloc * ld, 8, 0);
+        add(&V->w_part2, nloc * ld, 8, 0);
+        add(&V->v_sq, ld, 8, 0);
+        add(&V->v_inf, ld, 8, 0);
+        add(&V->g_t1, tr, 8, 0);
+        add(&V->g_t2, tr, 8, 0);
+        break;
+    case LAT_CALL_PRINCIPAL_OPS:
+        add(&V->u_cil, nloc * P->dim * ld, 8, 0);
+        break;
+    case LAT_CALL_SELECT_PRINCIPAL:
+        add(&V->g_sq, P->nchunk * ld, 8, 0);
+        add(&V->g_inf, P->nchunk * ld, 8, 0);
+        add(&V->g_dot, P->nchunk * ld, 8, 0);
+        add(&V->g_t1, tr, 8, 0);
+        add(&V->g_t2, tr, 8, 0);
+        add(&V->g_t3, tr, 8, 0);
+        add(&V->g_t4, tr, 8, 0);
+        add(&V->v_sq, ld, 8, 0);
+        add(&V->v_inf, ld, 8, 0);
+        add(&V->v_beta, ld, 8, 0);
+        add(&V->v_nu, ld, 8, 0);
+        add(&V->beta_pl, ld * cap, 8, 0);
+        add(&V->zeta, P->nsnap, 8, 0);
+        add(&V->ictl, 64, 4, 0);
+        add(&V->dctl, 64, 8, 0);
+        break;
+    case LAT_CALL_APPLY_COMBO:
+        add(&V->alpha_il, cap * ld, 8, 0);
+        add(&V->lp_err, 2 * (int64_t)P->nblk_lp, 8, 0);
+        add(&V->lp_gate, 8, 4, 0);
+        break;
+    case LAT_CALL_APPLY_COMBO_ADJOINT:
+        add(&V->alpha_il, cap * ld, 8, 0);
+        add(&V->lp_err, 2 * (int64_t)P->nblk_lp, 8, 0);
+        add(&V->lp_gate, 8, 4, 0);
+        add(&V->form_part, (int64_t)P->napc * ld * cap, 8, 0);
+        add(&V->form_out, ld * cap, 8, 0);
+        add(&V->g_t1, tr, 8, 0);
+        add(&V->g_t2, tr, 8, 0);
+        add(&V->aa_part, P->aa_nchunk * ld * cap, 8, 0);
+        add(&V->wf_part, 3 * P->aa_nchunk * ld * cap, 8, 1);
+        add(&V->w_forms, P->nsnap * ld, 8, 1);
+        add(&V->w_forms32, P->nsnap * ld, 4, 2);
+        break;
+    case LAT_CALL_ALPHA_ADJOINT:
+        add(&V->aa_A, 2 * cap * ld, 8, 0);
+        add(&V->aa_B, 2 * ld * cap, 8, 0);
+        add(&V->aa_q, 2 * cap * ld, 8, 0);
+        add(&V->aa_gath, P->nsnap * cap, 8, 0);
+        add(&V->aa_part, P->aa_nchunk * ld * cap, 8, 0);
+        add(&V->g_t1, tr, 8, 0);
+        add(&V->g_t2, tr, 8, 0);
+        add(&V->wf_part, 2 * P->aa_nchunk * ld * cap, 8, 1);
+        add(&V->aa_gath2, P->nsnap * cap, 8, 1);
+        break;
+    default: break;
+    }
+    return n;
+}
+
+size_t ws_align(size_t b) { return (b + 255) & ~(size_t)255; }
+
 void free_plan(lat_plan *P)
 {
     if (!P) return;
@@ -356,7 +441,7 @@ void free_plan(lat_plan *P)
                     P->unode, P->unbr, P->umask, P->uidx, P->u_cil, P->w_part, P->w_part2, P->g_sq, P->g_inf,
                     P->g_dot, P->g_t1, P->g_t2, P->g_t3, P->g_t4, P->v_sq, P->v_inf, P->v_beta, P->v_nu, P->beta_pl, P->zeta,
                     P->ictl, P->dctl, P->form_part, P->form_out, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part,
-                    P->lp_kslice, P->lp_cslice, P->lp_kf32, P->lp_cf32, P->w_forms, P->wf_part};
+                    P->lp_err, P->lp_gate};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete P;
@@ -554,6 +639,9 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     P->aa_nchunk = lat_cdiv(P->nsnap, P->aa_rows);
     int64_t tree_elems = std::max<int64_t>(tree_rows * ld, lat_cdiv(P->napc, LAT_TREE) * ld * cap);
     tree_elems = std::max<int64_t>(tree_elems, lat_cdiv(P->aa_nchunk, LAT_TREE) * ld * cap);
+    P->tree_elems = tree_elems;
+    // largest walk grid: the 2D row walk (group x row x at most two segments), the 3D runs of 16 nodes
+    P->nblk_lp = (int)std::max<int64_t>(std::max<int64_t>((int64_t)P->ngroups * P->nn * 2, lat_cdiv(P->npacked, 16)), 1);
     ALLOC(P->u_cil, nloc * dim * ld);
     ALLOC(P->w_part, nloc * ld);
     ALLOC(P->w_part2, nloc * ld);
@@ -577,11 +665,8 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     ALLOC(P->aa_q, (int64_t)cap * ld * 2);          // q, v                  [2][ld][cap]
     ALLOC(P->aa_gath, P->nsnap * cap);              // uniform operand       [nsnap][cap]
     ALLOC(P->aa_part, P->aa_nchunk * ld * cap);
-    P->EP = dim == 2 ? 48 : 3 * 96;                 // stencil planes padded to 16-row matrix tiles
-    ALLOC(P->lp_kslice, 3 * nloc * P->EP * 64);
-    ALLOC(P->lp_cslice, 3 * ld * 64);
-    ALLOC(P->lp_kf32, nloc * P->E * cap);
-    ALLOC(P->lp_cf32, (int64_t)cap * ld);
+    ALLOC(P->lp_err, 2 * (int64_t)P->nblk_lp);
+    ALLOC(P->lp_gate, 8);
     HCHK(hipStreamSynchronize(stream));
 #undef ALLOC
 #undef HCHK
@@ -594,6 +679,18 @@ lat_status lat_plan_destroy(lat_plan *plan)
     if (!plan) return LAT_E_ARG;
     (void)hipDeviceSynchronize();
     free_plan(plan);
+    return LAT_OK;
+}
+
+lat_status lat_plan_query(const lat_plan *P, size_t *min_bytes, size_t *fast_bytes)
+{
+    if (!P || (!min_bytes && !fast_bytes)) return LAT_E_ARG;
+    for (int c = 0; c < LAT_CALL_N; ++c) {
+        size_t mn = 0, fs = 0;
+        lat_ws_sizes(P, c, &mn, &fs);
+        if (min_bytes) min_bytes[c] = mn;
+        if (fast_bytes) fast_bytes[c] = fs;
+    }
     return LAT_OK;
 }
 
@@ -694,3 +791,48 @@ lat_status lat_gather(const lat_plan *P, const double *global, int32_t k, double
 }
 
 }  // extern "C"
+
+void lat_ws_sizes(const lat_plan *P, int call, size_t *min_bytes, size_t *fast_bytes)
+{
+    lat_plan V = *P;
+    WsItem it[32];
+    const int n = ws_items(P, &V, call, it);
+    size_t mn = 0, fs = 0, last = 0;
+    for (int t = 0; t < n; ++t) {
+        const size_t b = ws_align(it[t].bytes);
+        if (it[t].fast == 0) { mn += b; fs += b; }
+        else if (it[t].fast == 1) { fs += b; last = b; }
+        else if (b > last) { fs += b - last; last = b; }
+    }
+    *min_bytes = mn;
+    *fast_bytes = fs;
+}
+
+lat_status lat_ws_bind(const lat_plan *P, int call, void *work, size_t work_bytes, lat_plan *V)
+{
+    *V = *P;
+    WsItem it[32];
+    const int n = ws_items(P, V, call, it);
+    if (!work) {
+        // the plan's own scratch; it holds none of the buffers that only a fast workspace brings
+        for (int t = 0; t < n; ++t)
+            if (it[t].fast) *it[t].ptr = nullptr;
+        return LAT_OK;
+    }
+    if (((uintptr_t)work & 255) != 0) return LAT_E_ARG;
+    size_t mn = 0, fs = 0;
+    lat_ws_sizes(P, call, &mn, &fs);
+    if (work_bytes < mn) return LAT_E_SHAPE;
+    const bool fast = work_bytes >= fs;
+    char *base = (char *)work;
+    size_t off = 0, last_off = 0;
+    for (int t = 0; t < n; ++t) {
+        if (it[t].fast && !fast) { *it[t].ptr = nullptr; continue; }
+        if (it[t].fast == 2) { *it[t].ptr = base + last_off; continue; }
+        *it[t].ptr = base + off;
+        last_off = off;
+        off += ws_align(it[t].bytes);
+    }
+    return LAT_OK;
+}
+

@@ -95,7 +95,8 @@ def test_greedy_end_to_end(case):
     pre = O.greedy(case.orc["T"], cfg.tol, k, keep_Z=False) if k > 0 else None
     D = pre["Delta"] if pre is not None else case.orc["T"] / np.linalg.norm(case.orc["T"], axis=1, keepdims=True)
     m = np.sort(np.abs(D).max(axis=1))[::-1]
-    assert (m[0] - m[1]) <= 1e-10 * m[0], f"principal cells differ at step {k} with margin {(m[0]-m[1])/m[0]:.3e}"
+    print(f"[greedy] {cfg.name}: principal cells differ at step {k}, margin {(m[0]-m[1])/m[0]:.3e}", flush=True)
+    assert (m[0] - m[1]) <= 1e-12 * m[0], f"principal cells differ at step {k} with margin {(m[0]-m[1])/m[0]:.3e}"
 
 
 def test_applies(case):
@@ -126,7 +127,9 @@ def test_applies(case):
     # outputs vanish at DOFs a cell does not own; round trip of the packed layout
     assert np.all(Y[case.l2g < 0] == 0)
     np.testing.assert_array_equal(case.unpack(Xp), case.masked(X))
-    # per-cell relative error (no cell is allowed to hide behind the global norm)
+    # element by element (no entry is allowed to hide behind the global norm) and per cell
+    for a, b in ((Y, Yo), (YT, YTo), (Yp, Ypo)):
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max()
     for c in range(0, case.cfg.n_cells, max(1, case.cfg.n_cells // 16)):
         assert rel(Y[c], Yo[c]) <= 1e-9
 
