@@ -245,6 +245,20 @@ lat_status lat_apply_combo(const lat_plan *plan, const double *K, int32_t n_r, c
                            const double *X, double *Y, int32_t m, lat_prec prec, double refine_tol,
                            int32_t transpose, double *err_est, void *work, size_t work_bytes, hipStream_t stream);
 
+/* lat_apply_combo for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same operation, arguments and results, with
+ * the call's scratch in a fixed device array of LAT_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends (no allocation, no workspace argument).  The
+ * current device must be the plan's (else LAT_E_ARG).  LAT_E_SHAPE when the call's scratch
+ * (lat_plan_query's minimum for LAT_CALL_APPLY_COMBO: 8 cap ld bytes of coefficients plus the
+ * refinement's per-block partials) exceeds the array.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other threads) race and must not
+ * be issued. */
+#define LAT_NOALLOC_SCRATCH_BYTES (16u << 20)
+lat_status lat_apply_combo_noalloc(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
+                                   const double *X, double *Y, int32_t m, lat_prec prec, double refine_tol,
+                                   int32_t transpose, double *err_est, hipStream_t stream);
+
 /* The greedy's orthonormal basis as a ROM stack: stack[(a E + e) cap + k] = Z[k][(a, e)] and
  * coefficients coef[s][k] = nu_s beta_k^s (the certified decomposition of Algorithm 1), k < n_r
  * (HOST value), zero beyond.  Z [cap][n_snap], nu [N_s], beta [N_s][cap] from

@@ -85,6 +85,7 @@ def _lib():
             "lat_select_principal": (ctypes.c_int, [P, P, F, I32, P, P, P, P, P, P, P, P, P, P, Z, P]),
             "lat_select_principal_rows": (ctypes.c_int, [P, P, I64, F, I32, P, P, P, P, P, P, P, P, P, P, Z, P]),
             "lat_apply_combo": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, F, I32, P, P, Z, P]),
+            "lat_apply_combo_noalloc": (ctypes.c_int, [P, P, I32, P, P, P, I32, ctypes.c_int, F, I32, P, P]),
             "lat_basis_stack": (ctypes.c_int, [P, P, P, P, I32, P, P, P]),
             "lat_apply_plain": (ctypes.c_int, [P, P, P, P, I32, P]),
             "lat_apply_combo_adjoint": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, I32, P, P, P, P, ctypes.c_int, F, P,
@@ -115,7 +116,7 @@ def exported_symbols():
     return ["lat_status_string", "lat_plan_create", "lat_plan_destroy", "lat_plan_info", "lat_plan_query",
             "lat_status_reset",
             "lat_dofmap", "lat_residual_tangent", "lat_snapshot_rows", "lat_principal_ops", "lat_select_principal", "lat_select_principal_rows",
-            "lat_apply_combo", "lat_basis_stack",
+            "lat_apply_combo", "lat_apply_combo_noalloc", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
             "lat_plain_ops_to_canon", "lat_rom_solve", "lat_coarse_operator", "lat_newton_solve"]
