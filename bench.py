@@ -45,21 +45,50 @@ def measured_traffic(workload):
     if workload != "hole2d_32x32_n32_graded" or not os.path.exists(TRAFFIC_PROFILE):
         return None
     text = open(TRAFFIC_PROFILE).read()
-    sha = re.search(r"row-walk source sha256: ([0-9a-f]{64})", text)
+    sha = re.search(r"apply source sha256: ([0-9a-f]{64})", text)
     val = re.search(r"rom_apply traffic bytes per launch: (\d+)", text)
-    if not sha or not val or rowwalk_source_sha() != sha.group(1):
+    if not sha or not val or apply_source_sha() != sha.group(1):
         return None
     return int(val.group(1))
 
 
-def rowwalk_source_sha():
-    """sha256 of the 2D row-walk kernel and its launcher (the code the traffic was measured on)."""
-    src = open(os.path.join(ROOT, "paper_2603_10741_amd", "csrc", "lat_apply.hip")).read()
-    k0 = src.index("// 2D row walk, software pipelined.")
-    k1 = src.index("// 3D ROM apply (and its transpose)")
-    l0 = src.index("lat_status launch_rowwalk_nr(")
-    l1 = src.index("lat_status launch_rowwalk_mode(")
-    return hashlib.sha256((src[k0:k1] + src[l0:l1]).encode()).hexdigest()
+def apply_source_sha():
+    """sha256 of the apply kernels' source and the internal header they include: any change to
+    the code the counters were taken on makes the recorded traffic stale."""
+    h = hashlib.sha256()
+    for f in ("lat_apply.hip", "lat_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2603_10741_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Sets the OpenMP thread count of the oracle's runtime (libgomp) for the calls that follow."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    except OSError:
+        pass
+
+
+def _oracle_rate(fn, dofs_rhs, budget_s):
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dofs_rhs * reps / el / 1e9, reps, el
 
 
 def cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=12.0):
@@ -74,17 +103,171 @@ def cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=12.0):
     Kp = np.ascontiguousarray(T[g["S"][:g["n_r"]]])
     del T
     dofs = int(nact.sum()) * cfg.dim * X.shape[-1]
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.combo_apply(cfg.dim, cfg.nel, Kp, g["alpha"], l2g, X)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": dofs * reps / el / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+    _omp_threads(threads)
+    rate, reps, el = _oracle_rate(lambda: O.combo_apply(cfg.dim, cfg.nel, Kp, g["alpha"], l2g, X), dofs, budget_s)
+    _omp_threads(1)
+    rate1, reps1, el1 = _oracle_rate(lambda: O.combo_apply(cfg.dim, cfg.nel, Kp, g["alpha"], l2g, X), dofs,
+                                     budget_s / 3)
+    _omp_threads(threads)
+    return {"value": rate, "unit": "GDOF/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "single_thread_value": rate1,
             "sample": f"full workload ({cfg.n_cells} cells, m={X.shape[-1]}), oracle ROM apply repeated "
-                      f"{reps}x in {el:.1f} s"}, {"S": g["S"], "n_r": g["n_r"]}
+                      f"{reps}x in {el:.1f} s on {threads} threads; {reps1}x in {el1:.1f} s on one thread"}, \
+        {"S": g["S"], "n_r": g["n_r"]}
+
+
+def apply_stage(index, m=16, reps=10, cpu_budget=4.0, sample_n=12, seed=7):
+    """Apply-stage record of one workload (outside the timed steps of the main line): after
+    snapshots, greedy and principal tangents, the ROM apply in FP64 and with bf16 slices (two
+    starting levels, FP64-measured refinement), the plain per-cell apply and the ROM apply's adjoint
+    (Xbar, alpha_bar and the Lame parts), each timed with HIP events on its stream (mean of `reps`
+    after two untimed calls); errors against the FP64 oracle on sampled cells; rooflines against
+    the bound each form has; the oracle's ROM apply on a 4 x 4 x 4-cell slice as CPU baseline."""
+    import numpy as np
+    import torch
+
+    import lattice as L
+    import oracle as O
+    from paper_2603_10741_amd import binding as B
+    dev = torch.device("cuda:0")
+    cfg = L.config(index)
+    log("apply stage", cfg.name)
+    keep = L.make_keep(cfg)
+    mu, lam = L.make_material(cfg)
+    u_bg = L.make_displacement(cfg)
+    P = B.Plan(cfg.dim, cfg.ncell, cfg.nel, keep, cap=cfg.cap)
+    _, nact, g2bg, _ = P.dofmap()
+    lane_nodes = int(nact.sum().item())
+    dofs_rhs = lane_nodes * cfg.dim * m
+    ug = torch.from_numpy(u_bg).to(dev)[g2bg].contiguous()
+    mu_t, lam_t = torch.from_numpy(mu).to(dev), torch.from_numpy(lam).to(dev)
+    P.reset_status()
+    r = P.residual_tangent(ug, mu_t, lam_t, f=False, energy=False, snap=True, plain=True)
+    g = P.select_principal(r["snap"], cfg.tol, keep_Z=True)
+    code, _ = P.check_status(allow_cap=True)
+    n_r = int(g["n_r"].item())
+    del r["snap"]
+    ops = P.principal_ops(ug, mu_t, lam_t, g["S"], n_r, parts=True)
+    bs = P.basis_stack(g["Z"], g["nu"], g["beta"], n_r)
+    del g["Z"]
+    torch.cuda.empty_cache()
+    gen = torch.Generator(dev).manual_seed(seed)
+    Xp = torch.randn(P.packed_size(m), dtype=torch.float64, device=dev, generator=gen)
+    Ybp = torch.randn(P.packed_size(m), dtype=torch.float64, device=dev, generator=gen)
+    Y64, Ylp, Ypl = (torch.empty_like(Xp) for _ in range(3))
+    err_t = torch.zeros(1, dtype=torch.float64, device=dev)
+    kw = dict(K_mu=ops["K_mu"], K_lam=ops["K_lam"], S=g["S"])
+    calls = {
+        "rom_f64": lambda: P.apply_combo(ops["K"], n_r, g["alpha"], Xp, m, out=Y64),
+        "rom_bf16": lambda: P.apply_combo(bs["stack"], n_r, bs["coef"], Xp, m, prec=B.BF16, refine_tol=LOWP_REFINE,
+                                          out=Ylp, err_est=err_t),
+        "plain_f64": lambda: P.apply_plain(r["plain"], Xp, m, out=Ypl),
+        "adjoint_f64": lambda: P.apply_combo_adjoint(ops["K"], n_r, g["alpha"], Xp, Ybp, m, **kw),
+    }
+    ms = {}
+    s = torch.cuda.current_stream()
+    for name, fn in calls.items():
+        for _ in range(2):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(s)
+            fn()
+            b.record(s)
+        torch.cuda.synchronize()
+        ms[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ad = calls["adjoint_f64"]()
+    torch.cuda.synchronize()
+    # oracle on sampled cells with the GPU's principal cells and coefficients
+    O.build(force=False)
+    l2g, _, g2bg_o = O.dofmap(cfg.dim, cfg.ncell, cfg.nel, keep)
+    S = g["S"].cpu().numpy()[:n_r]
+    rng = np.random.default_rng(seed)
+    sample = np.unique(np.concatenate([rng.choice(cfg.n_cells, sample_n, replace=False), S[:2]]))
+    cells = np.unique(np.concatenate([sample, S]))
+    uloc = dict(zip(cells.tolist(), O.gather_local(u_bg[g2bg_o], l2g[cells])))
+    Kp = np.stack([O.cell_eval(cfg.dim, cfg.nel, keep[c], uloc[c], mu[c], lam[c])["stencil"] for c in S])
+    Ks = np.stack([O.cell_eval(cfg.dim, cfg.nel, keep[c], uloc[c], mu[c], lam[c])["stencil"] for c in sample])
+    alpha = g["alpha"].cpu().numpy()
+    idx = torch.from_numpy(sample).to(dev).long()
+
+    def cells_of(packed):
+        return P.unpack(packed, m)[idx].cpu().numpy()
+    X, Yb = cells_of(Xp), cells_of(Ybp)
+    Yo = O.combo_apply(cfg.dim, cfg.nel, Kp, alpha[sample], l2g[sample], X)
+    Ypo = O.plain_apply(cfg.dim, cfg.nel, Ks, l2g[sample], X)
+    Xbo = O.combo_apply(cfg.dim, cfg.nel, Kp, alpha[sample], l2g[sample], Yb, transpose=True)
+    Go = O.combo_forms(cfg.dim, cfg.nel, Kp, P.cap, l2g[sample], X, Yb)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    err = {"rom_f64": rel(cells_of(Y64), Yo), "rom_bf16": rel(cells_of(Ylp), Yo), "plain_f64": rel(cells_of(Ypl), Ypo),
+           "adjoint_f64_xbar": rel(cells_of(ad["Xbar"]), Xbo),
+           "adjoint_f64_alpha_bar": rel(ad["alpha_bar"][idx].cpu().numpy(), Go)}
+    rom_vs_plain = float(torch.linalg.norm(Y64 - Ypl) / torch.linalg.norm(Ypl))
+    # rooflines: the FP64 combination against the FP64 matrix cores (2 E (N_r + m) flops per active
+    # lane-node: combine, then apply), the other forms against HBM (16 B per DOF and RHS, plus the
+    # stack and alpha; the plain apply its cells' stencils; the adjoint a third vector)
+    E = P.E
+    flops = 2.0 * E * (n_r + m) * lane_nodes
+    stack_b = 8.0 * P.nloc * E * n_r + 8.0 * P.ncells * n_r
+    b_rom = 16.0 * dofs_rhs + stack_b
+    b_plain = 16.0 * dofs_rhs + 8.0 * E * lane_nodes
+    b_adj = 24.0 * dofs_rhs + 3 * stack_b
+    t = {k: v * 1e-3 for k, v in ms.items()}
+    gd = {k: round(dofs_rhs / v / 1e9, 3) for k, v in t.items()}
+    roof = {
+        "rom_f64": {"bound": "mfma", "achieved": round(flops / t["rom_f64"] / 1e12, 2), "peak": FP64_MFMA_PEAK_TF,
+                    "unit": "TFLOP/s", "frac": round(flops / t["rom_f64"] / 1e12 / FP64_MFMA_PEAK_TF, 4),
+                    "algorithmic_flops": int(flops)},
+        "rom_bf16": {"bound": "hbm", "achieved": round(b_rom / t["rom_bf16"] / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(b_rom / t["rom_bf16"] / 1e9 / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes": int(b_rom)},
+        "plain_f64": {"bound": "hbm", "achieved": round(b_plain / t["plain_f64"] / 1e9, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(b_plain / t["plain_f64"] / 1e9 / HBM_PEAK_GBS, 4),
+                      "algorithmic_bytes": int(b_plain)},
+        "adjoint_f64": {"bound": "hbm", "achieved": round(b_adj / t["adjoint_f64"] / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(b_adj / t["adjoint_f64"] / 1e9 / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes": int(b_adj)},
+    }
+    # the oracle's ROM apply on the low 4 x 4 x 4 corner of the lattice, with the same S and alpha
+    sub = cfg.with_sub(tuple(min(4, c) for c in cfg.ncell))
+    sl_ids = np.array([c for c in range(cfg.n_cells)
+                       if all((c // int(np.prod(cfg.ncell[:ax]))) % cfg.ncell[ax] < sub.ncell_eff[ax]
+                              for ax in range(cfg.dim))])
+    Xs = np.random.default_rng(seed).standard_normal((len(sl_ids), P.nloc, cfg.dim, m))
+    sl_dofs = int((l2g[sl_ids] >= 0).sum()) * cfg.dim * m
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fn = lambda: O.combo_apply(cfg.dim, cfg.nel, Kp, alpha[sl_ids], l2g[sl_ids], Xs)
+    _omp_threads(threads)
+    rate, reps_c, el = _oracle_rate(fn, sl_dofs, cpu_budget)
+    # one thread on the first 8 cells of the corner
+    s8 = sl_ids[:8]
+    fn1 = lambda: O.combo_apply(cfg.dim, cfg.nel, Kp, alpha[s8], l2g[s8], Xs[:8])
+    _omp_threads(1)
+    rate1, reps1, el1 = _oracle_rate(fn1, int((l2g[s8] >= 0).sum()) * cfg.dim * m, cpu_budget / 2)
+    _omp_threads(threads)
+    out = {
+        "workload": cfg.name, "cells": P.ncells, "elements_per_cell": f"{cfg.nel}^{cfg.dim}", "right_hand_sides": m,
+        "principal_cap": cfg.cap, "tol": cfg.tol, "n_r": n_r, "capped": code == B.LAT_W_CAP,
+        "active_local_dofs": lane_nodes * cfg.dim, "inputs": "snapshots at the seeded displacement; X, Ybar i.i.d. "
+        "N(0,1) drawn on the device",
+        "ms": {k: round(v, 4) for k, v in ms.items()}, "gdofs": gd,
+        "rom_f64_over_plain": round(t["plain_f64"] / t["rom_f64"], 3),
+        "rom_bf16_over_plain": round(t["plain_f64"] / t["rom_bf16"], 3),
+        "bf16": {"refine_tol": LOWP_REFINE, "err_est": float(err_t.item())},
+        "rel_err_vs_fp64_oracle": err, "rom_vs_plain_operator_rel_diff": rom_vs_plain,
+        "oracle_sample_cells": len(sample), "roofline": roof,
+        "cpu_baseline": {"value": rate, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+                         "cpu_model": cpu_model(), "single_thread_value": rate1,
+                         "sample": f"oracle ROM apply on the {'x'.join(map(str, sub.ncell_eff))}-cell corner "
+                                   f"({len(sl_ids)} cells, m={m}) of the lattice: {reps_c}x in {el:.1f} s on "
+                                   f"{threads} threads; its first 8 cells {reps1}x in {el1:.1f} s on one thread"},
+    }
+    del P, r, g, ops, bs, Xp, Ybp, Y64, Ylp, Ypl, ad
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -96,6 +279,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--workload", type=int, default=WORKLOAD_INDEX,
                     help="workload index (default: the 32x32 graded-hole lattice; the others are parity cases)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the apply-stage records of the 3D lattices")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     ap.add_argument("--newton", action="store_true",
@@ -163,6 +347,7 @@ def main():
         "ops": {k: P._f64(P.nloc * P.E * P.cap) for k in ("K", "K_mu", "K_lam")},
         "Y": P._f64(P.packed_size(m)), "Yp": P._f64(P.packed_size(m)), "Ylp": P._f64(P.packed_size(m)),
         "basis": {"stack": P._f64(P.nloc * P.E * P.cap), "coef": P._f64(P.ncells, P.cap)},
+        "err": torch.zeros(1, dtype=torch.float64, device=dev),
     }
     greedy_out = {}
     stages = ["dofmap", "residual_tangent", "select_principal", "principal_ops", "rom_apply", "plain_apply",
@@ -201,7 +386,8 @@ def main():
         # reduced-precision combo: orthonormal-basis form, bf16 slice products (2 levels)
         bs = P.basis_stack(g["Z"], g["nu"], g["beta"], n_r, out=bufs["basis"])
         marks[8].record(s)
-        P.apply_combo(bs["stack"], n_r, bs["coef"], Xp, m, prec=B.BF16, refine_tol=LOWP_REFINE, out=bufs["Ylp"])
+        P.apply_combo(bs["stack"], n_r, bs["coef"], Xp, m, prec=B.BF16, refine_tol=LOWP_REFINE, out=bufs["Ylp"],
+                      err_est=bufs["err"])
         marks[9].record(s)
         if record:
             for i, st in enumerate(stages):
@@ -262,6 +448,7 @@ def main():
     Ylp = P.unpack(bufs["Ylp"], m).cpu().numpy()
     err_lp = float(np.linalg.norm(Ylp[sample] - Yo) / np.linalg.norm(Yo))
     t_lp = ms_stage["rom_apply_bf16"] * 1e-3
+    lp_est = float(bufs["err"].item())
     rom_vs_plain = float(np.linalg.norm(Y - Yp) / np.linalg.norm(Yp))
 
     def snapshot_variant(rule, tol):
@@ -296,6 +483,15 @@ def main():
         log("cpu baseline (oracle) ...")
         cpu, _ = cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=args.cpu_budget)
 
+    configs = {}
+    if not args.no_3d:
+        del bufs, greedy_out, state
+        torch.cuda.empty_cache()
+        for idx in (2, 4):                  # BCC 10^3 (12^3 hexes), mixed BCC/octet 20^3 (16^3 hexes)
+            rec = apply_stage(idx, cpu_budget=min(4.0, args.cpu_budget))
+            configs[rec["workload"]] = rec
+            log(f"apply stage {rec['workload']}: {rec['gdofs']}")
+
     out = {
         "metric": "GDOF/s of principal-combo apply vs plain per-cell apply at ≤1e-5 rel err",
         "value": round(value, 3),
@@ -325,8 +521,10 @@ def main():
         "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
         "rom_over_plain_speedup": round(t_plain / t_apply, 3),
         "reduced_precision": {"kernel": ("k_apply2d_rw" if cfg.dim == 2 else "k_apply3d_mfma")
-                              + " (bf16 slice products on the matrix cores, FP64 level sums and apply)",
-                              "refine_tol": LOWP_REFINE, "levels": 2,
+                              + " (bf16 slice products on the matrix cores, FP64 level sums and apply; one node per workgroup formed "
+                                "again in FP64 for the error estimate that decides further levels)",
+                              "refine_tol": LOWP_REFINE, "starting_levels": 2,
+                              "err_est": lp_est,
                               "gdofs": round(dofs_rhs / t_lp / 1e9, 3), "rel_err_vs_fp64_oracle": err_lp,
                               "over_fp64_plain_speedup": round(t_plain / t_lp, 3)},
         "rel_err_rom_apply_vs_fp64_oracle": err_rom,
@@ -335,6 +533,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in ms_stage.items()},
         "snapshot_variants": snap_variants,
         "device_status": {"code": code, "first_cell": cell},
+        "configs": configs,
     }
     print(json.dumps(out))
 
