@@ -279,11 +279,12 @@ lat_status lat_apply_plain(const lat_plan *plan, const double *plain_ops, const 
  *                               (written, not accumulated; zero for non-principal cells).
  *                               Requires K_mu / K_lam from lat_principal_ops and S.
  * prec / refine_tol / err_est: the precision of Xbar's combination, as for lat_apply_combo (its
- * transposed apply).  The forms <Ybar_i, K_k X_i> are sums of products of FP64 data; with a
- * workspace of the fast size they are taken from the cells' W[(a, e)] = sum_r Ybar X, held in FP64
- * (LAT_F64) or FP32 (LAT_F32 / LAT_BF16), by one contraction per stack on the FP64 matrix cores;
- * otherwise by a fused per-node kernel in FP64.  work: LAT_CALL_APPLY_COMBO_ADJOINT workspace or
- * NULL (no fast variant then). */
+ * transposed apply).  The forms <Ybar_i, K_k X_i> are sums of products of FP64 data; with room in
+ * the workspace past its minimum they are taken from the cells' W[(a, e)] = sum_r Ybar X, held in
+ * FP64 (LAT_F64) or FP32 (LAT_F32 / LAT_BF16), by one contraction per stack on the FP64 matrix
+ * cores, in batches of as many 64-lane groups as that room holds (the fast size holds every lane at
+ * once; below one group's worth, a fused per-node kernel in FP64 serves).
+ * work: LAT_CALL_APPLY_COMBO_ADJOINT workspace or NULL (the fused kernel then). */
 lat_status lat_apply_combo_adjoint(const lat_plan *plan, const double *K, const double *K_mu, const double *K_lam,
                                    const int32_t *S, int32_t n_r, const double *alpha, const double *X,
                                    const double *Ybar, int32_t m, double *Xbar, double *alpha_bar, double *mu_bar,

@@ -189,13 +189,16 @@ class Plan:
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
 
     def workspace(self, call, fast=None):
-        """The cached device workspace of a call (a uint8 tensor of the call's fast size when that is
-        at most WORK_FAST_LIMIT bytes, else of its minimum size): (pointer, bytes)."""
-        if fast is None:
-            fast = self.work_fast[call] <= WORK_FAST_LIMIT
-        key = (call, bool(fast))
+        """The cached device workspace of a call, a uint8 tensor: (pointer, bytes).  Default: the
+        call's fast size when that is at most WORK_FAST_LIMIT bytes, else that limit (the ROM
+        adjoint then takes its W in lane batches); fast=True the fast size, fast=False the minimum."""
+        key = (call, fast)
         if key not in self._work:
-            n = self.work_fast[call] if fast else self.work_min[call]
+            mn, fs = self.work_min[call], self.work_fast[call]
+            if fast is None:
+                n = fs if fs <= WORK_FAST_LIMIT else max(mn, WORK_FAST_LIMIT)
+            else:
+                n = fs if fast else mn
             self._work[key] = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
         t = self._work[key]
         return _ptr(t), ctypes.c_size_t(t.numel())

@@ -1020,21 +1020,24 @@ __global__ __launch_bounds__(512) void k_forms_mfma(ApplyArgs A, const int32_t *
 // for every local node a and plan lane p, Ybar counted at the cell's owned DOFs and X at its owned
 // neighbour DOFs, zero where the node is not in the lane's group union; then
 // <Ybar_p, K_k X_p> = sum_(a, e) K_k[a][e] W[(a, e)][p] is one row contraction per stack.
+// Lanes p0 .. p0 + ldw - 1 (a batch; W holds only these columns, row stride ldw).
 template <int DIM, class WT>
-__global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int nloc, int m, const int32_t *__restrict__ goff,
-                                                 const int32_t *__restrict__ uidx, const int32_t *__restrict__ unbr,
-                                                 const uint64_t *__restrict__ umask, const double *__restrict__ X,
-                                                 const double *__restrict__ Ybar, WT *__restrict__ W)
+__global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int64_t p0, int64_t ldw, int nloc, int m,
+                                                 const int32_t *__restrict__ goff, const int32_t *__restrict__ uidx,
+                                                 const int32_t *__restrict__ unbr, const uint64_t *__restrict__ umask,
+                                                 const double *__restrict__ X, const double *__restrict__ Ybar,
+                                                 WT *__restrict__ W)
 {
     constexpr int NO = DIM == 2 ? 9 : 27, E = NO * DIM * DIM, MM = 16;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t pb = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = p0 + pb;
     const int a = blockIdx.y;
-    if (p >= ld) return;
+    if (pb >= ldw || p >= ld) return;
     const int g = (int)(p / LAT_WAVE), l = (int)(p % LAT_WAVE);
     const int qi = uidx[(int64_t)g * nloc + a];
-    WT *wr = W + (int64_t)a * E * ld + p;
+    WT *wr = W + (int64_t)a * E * ldw + pb;
     if (qi < 0) {
-        for (int e = 0; e < E; ++e) wr[(int64_t)e * ld] = (WT)0;
+        for (int e = 0; e < E; ++e) wr[(int64_t)e * ldw] = (WT)0;
         return;
     }
     const int64_t q = (int64_t)goff[g] + qi;
@@ -1061,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_forms_W(int64_t ld, int nloc, int m, co
                 double v = 0.0;
 #pragma unroll
                 for (int r = 0; r < MM; ++r) v = fma(yb[i][r], xv[j][r], v);
-                wr[(int64_t)((o * DIM + i) * DIM + j) * ld] = (WT)v;
+                wr[(int64_t)((o * DIM + i) * DIM + j) * ldw] = (WT)v;
             }
     }
 }
@@ -1425,9 +1428,10 @@ lat_status run_forms(const lat_plan *P, const double *K, int n_r, const double *
 }
 
 // The adjoint forms of the requested stacks (ROM coefficients, Lame parts) with the plan copy V's
-// scratch.  With the caller's W buffer: one streaming W pass (FP64, or FP32 when prec != LAT_F64),
-// then one row contraction per stack (or one pass for all of them when n_r <= 32); without it the
-// fused per-node kernel (m <= 16), or one per-node pass per stack.
+// scratch.  With room for W past the workspace minimum: the cells' W (FP64, or FP32 when
+// prec != LAT_F64) in lane batches as large as that room allows (whole 64-lane groups), each batch
+// a streaming W pass followed by one row contraction per stack (one pass for all of them when
+// n_r <= 32); without it the fused per-node kernel (m <= 16), or one per-node pass per stack.
 lat_status run_adjoint_forms(const lat_plan *V, const double *K, const double *K_mu, const double *K_lam,
                              const int32_t *S, int n_r, const double *alpha, const double *X, const double *Ybar,
                              int m, double *alpha_bar, double *mu_bar, double *lam_bar, int prec, hipStream_t stream)
@@ -1440,16 +1444,17 @@ lat_status run_adjoint_forms(const lat_plan *V, const double *K, const double *K
     if (mu_bar) { stk[ns] = K_mu; role[ns++] = 1; }
     if (lam_bar) { stk[ns] = K_lam; role[ns++] = 2; }
     if (ns == 0) return LAT_OK;
-    auto finish = [&](int t) -> lat_status {      // form_out [ld][cap] -> the requested output
+    const int64_t ld = V->ld, cap = V->cap, ldc = ld * cap;
+    auto finish = [&](int t, const double *forms) -> lat_status {   // forms [ld][cap] -> the output
         if (role[t] == 0) {
-            hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, V->ld, V->cap, V->perm, V->form_out, alpha_bar);
+            hipLaunchKernelGGL(k_forms_scatter, lg, dim3(256), 0, stream, ld, V->cap, V->perm, forms, alpha_bar);
         } else {
             double *bar = role[t] == 1 ? mu_bar : lam_bar;
             hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)lat_cdiv(V->ncells, 256)), dim3(256), 0, stream, V->ncells,
                                bar);
             if (n_r > 0)
                 hipLaunchKernelGGL(k_direct_lame, dim3((unsigned)n_r), dim3(256), 0, stream, V->ncells, V->cap, S,
-                                   V->lane, alpha, V->form_out, bar);
+                                   V->lane, alpha, forms, bar);
         }
         LAT_LAUNCH_CHECK();
         return LAT_OK;
@@ -1458,49 +1463,72 @@ lat_status run_adjoint_forms(const lat_plan *V, const double *K, const double *K
         // one per-node pass per stack
         for (int t = 0; t < ns; ++t) {
             if ((st = run_forms(V, stk[t], n_r, X, Ybar, m, V->form_out, stream)) != LAT_OK) return st;
-            if ((st = finish(t)) != LAT_OK) return st;
+            if ((st = finish(t, V->form_out)) != LAT_OK) return st;
         }
         return LAT_OK;
     }
-    const bool low = prec != LAT_F64 && V->w_forms32;
-    const bool haveW = low || V->w_forms;
-    int cpg = 0;
-    if (haveW) {
-        const dim3 wg((unsigned)lat_cdiv(V->ld, 256), (unsigned)V->nloc);
+    // lanes per W batch from the workspace past its minimum (FP32 W: half the W bytes per lane)
+    const bool low = prec != LAT_F64;
+    const size_t esz = low ? 4 : 8;
+    auto batch_bytes = [&](int64_t lanes) {
+        return ((size_t)V->nsnap * lanes * esz + 255) / 256 * 256 + ((size_t)3 * V->aa_nchunk * lanes * cap * 8 + 255) / 256 * 256;
+    };
+    int64_t lanes = 0;
+    if (V->ws_rest) {
+        lanes = std::min<int64_t>(ld, (int64_t)(V->ws_rest_bytes / (V->nsnap * esz + 3 * V->aa_nchunk * cap * 8)) / 64 * 64);
+        while (lanes > 0 && batch_bytes(lanes) > V->ws_rest_bytes) lanes -= 64;
+    }
+    if (lanes < 64) {
+        int cpg = 0;
+        if ((st = run_forms_fused(V, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) return st;
+        for (int t = 0; t < ns; ++t) {
+            if ((st = lat_tree_reduce(V->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, V->form_out, V->g_t1,
+                                      V->g_t2, stream)) != LAT_OK)
+                return st;
+            if ((st = finish(t, V->form_out)) != LAT_OK) return st;
+        }
+        return LAT_OK;
+    }
+    char *wbase = V->ws_rest;
+    double *W64 = low ? nullptr : (double *)wbase;
+    float *W32 = low ? (float *)wbase : nullptr;
+    double *parts = (double *)(wbase + ((size_t)V->nsnap * lanes * esz + 255) / 256 * 256);
+    // n_r <= 32: the stacks' contractions share one pass over W (chunk partials per stack)
+    const bool multi = n_r <= 32;
+    for (int64_t p0 = 0; p0 < ld; p0 += lanes) {
+        const int64_t ldw = std::min<int64_t>(lanes, ld - p0);
+        const dim3 wg((unsigned)lat_cdiv(ldw, 256), (unsigned)V->nloc);
         if (low) {
             if (V->dim == 2)
-                hipLaunchKernelGGL((k_forms_W<2, float>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff, V->uidx,
-                                   V->unbr, V->umask, X, Ybar, V->w_forms32);
+                hipLaunchKernelGGL((k_forms_W<2, float>), wg, dim3(256), 0, stream, ld, p0, ldw, V->nloc, m, V->goff,
+                                   V->uidx, V->unbr, V->umask, X, Ybar, W32);
             else
-                hipLaunchKernelGGL((k_forms_W<3, float>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff, V->uidx,
-                                   V->unbr, V->umask, X, Ybar, V->w_forms32);
+                hipLaunchKernelGGL((k_forms_W<3, float>), wg, dim3(256), 0, stream, ld, p0, ldw, V->nloc, m, V->goff,
+                                   V->uidx, V->unbr, V->umask, X, Ybar, W32);
         } else {
             if (V->dim == 2)
-                hipLaunchKernelGGL((k_forms_W<2, double>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff,
-                                   V->uidx, V->unbr, V->umask, X, Ybar, V->w_forms);
+                hipLaunchKernelGGL((k_forms_W<2, double>), wg, dim3(256), 0, stream, ld, p0, ldw, V->nloc, m, V->goff,
+                                   V->uidx, V->unbr, V->umask, X, Ybar, W64);
             else
-                hipLaunchKernelGGL((k_forms_W<3, double>), wg, dim3(256), 0, stream, V->ld, V->nloc, m, V->goff,
-                                   V->uidx, V->unbr, V->umask, X, Ybar, V->w_forms);
+                hipLaunchKernelGGL((k_forms_W<3, double>), wg, dim3(256), 0, stream, ld, p0, ldw, V->nloc, m, V->goff,
+                                   V->uidx, V->unbr, V->umask, X, Ybar, W64);
         }
         LAT_LAUNCH_CHECK();
-    } else if ((st = run_forms_fused(V, stk, ns, n_r, X, Ybar, m, &cpg, stream)) != LAT_OK) {
-        return st;
+        // the batch as a plan of ldw lanes: contractions and trees write rows p0 .. p0 + ldw - 1
+        lat_plan Vb = *V;
+        Vb.ld = ldw;
+        const int64_t ldcb = ldw * cap;
+        double *bparts[3] = {parts, parts + V->aa_nchunk * ldcb, parts + 2 * V->aa_nchunk * ldcb};
+        if (multi && (st = lat_contract_rows_multi(&Vb, n_r, W64, W32, stk, ns, bparts, stream)) != LAT_OK) return st;
+        for (int t = 0; t < ns; ++t) {
+            double *out = V->form_out3 + t * ldc + p0 * cap;
+            if (multi) st = lat_tree_reduce(bparts[t], V->aa_nchunk, ldcb, 0, out, V->g_t1, V->g_t2, stream);
+            else st = lat_contract_rows(&Vb, n_r, W64, W32, stk[t], out, stream);
+            if (st != LAT_OK) return st;
+        }
     }
-    const int64_t ldc = V->ld * V->cap;
-    const double *W64 = low ? nullptr : V->w_forms;
-    const float *W32 = low ? V->w_forms32 : nullptr;
-    // n_r <= 32: the stacks' contractions share one pass over W (chunk partials per stack)
-    const bool multi = haveW && n_r <= 32;
-    double *wparts[3] = {V->wf_part, V->wf_part + V->aa_nchunk * ldc, V->wf_part + 2 * V->aa_nchunk * ldc};
-    if (multi && (st = lat_contract_rows_multi(V, n_r, W64, W32, stk, ns, wparts, stream)) != LAT_OK) return st;
-    for (int t = 0; t < ns; ++t) {
-        if (multi) st = lat_tree_reduce(wparts[t], V->aa_nchunk, ldc, 0, V->form_out, V->g_t1, V->g_t2, stream);
-        else if (haveW) st = lat_contract_rows(V, n_r, W64, W32, stk[t], V->form_out, stream);
-        else st = lat_tree_reduce(V->form_part + (int64_t)t * cpg * ldc, cpg, ldc, 0, V->form_out, V->g_t1, V->g_t2,
-                                  stream);
-        if (st != LAT_OK) return st;
-        if ((st = finish(t)) != LAT_OK) return st;
-    }
+    for (int t = 0; t < ns; ++t)
+        if ((st = finish(t, V->form_out3 + t * ldc)) != LAT_OK) return st;
     return LAT_OK;
 }
 

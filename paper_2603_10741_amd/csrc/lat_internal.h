@@ -57,6 +57,7 @@ struct lat_plan {
     double *dctl = nullptr;        // rho, achieved, ...
     double *form_part = nullptr;   // [napc][ld][cap] adjoint form partials
     double *form_out = nullptr;    // [ld][cap]
+    double *form_out3 = nullptr;   // [3][ld][cap] forms of up to three stacks (ROM adjoint)
     double *alpha_il = nullptr;    // [cap][ld] interleaved RB coefficients
     double *aa_A = nullptr;        // [cap][ld] alpha-adjoint products
     double *aa_B = nullptr;        // [ld][cap]
@@ -72,10 +73,12 @@ struct lat_plan {
     int32_t *lp_gate = nullptr;    // [8] refinement gates (1 = the next, more precise pass runs)
     // adjoint forms: W[(a, e)][lane] = sum_r Ybar X (FP64, or FP32 in w_forms32), and the alpha
     // adjoint's second uniform operand; only in a caller workspace of the "fast" size
-    double *w_forms = nullptr;     // [nsnap][ld]
-    float *w_forms32 = nullptr;    // [nsnap][ld]
-    double *wf_part = nullptr;     // [3][aa_nchunk][ld][cap] contraction partials of the stacks
+    double *wf_part = nullptr;     // alpha adjoint: [2][aa_nchunk][ld][cap] contraction partials
     double *aa_gath2 = nullptr;    // [nsnap][cap]
+    // the part of a caller workspace past the call's minimum (the ROM adjoint carves its W batches
+    // and their contraction partials from it)
+    char *ws_rest = nullptr;
+    size_t ws_rest_bytes = 0;
 };
 
 // ---- bf16 slices (reduced-precision combination on the bf16 matrix cores)
@@ -155,6 +158,8 @@ __device__ inline void lat_flag(int32_t *st, int code, int cell)
 // work_bytes is below the call's minimum, LAT_E_ARG when work is not 256-byte aligned.
 lat_status lat_ws_bind(const lat_plan *P, int call, void *work, size_t work_bytes, lat_plan *V);
 void lat_ws_sizes(const lat_plan *P, int call, size_t *min_bytes, size_t *fast_bytes);
+// bytes of the ROM adjoint's W (FP64) and three-stack contraction partials for `lanes` plan lanes
+size_t lat_forms_batch_bytes(const lat_plan *P, int64_t lanes);
 
 // Shared internal launches (defined in lat_greedy.hip).
 // Pairwise-tree reduction over rows of in [nrows][ld] (row-major, lanes fastest), applying

@@ -360,7 +360,7 @@ int ws_items(const lat_plan *P, lat_plan *V, int call, WsItem *it)
 {
     int n = 0;
     auto add = [&](void *field, int64_t elems, size_t esz, int fast) {
-        it[n].ptr = (void **)field;
+        it[n].ptr = (void **)field;          // NULL: a size only (carved by the call itself)
         it[n].bytes = (size_t)std::max<int64_t>(elems, 1) * esz;
         it[n].fast = fast;
         ++n;
@@ -408,12 +408,13 @@ int ws_items(const lat_plan *P, lat_plan *V, int call, WsItem *it)
         add(&V->lp_gate, 8, 4, 0);
         add(&V->form_part, (int64_t)P->napc * ld * cap, 8, 0);
         add(&V->form_out, ld * cap, 8, 0);
+        add(&V->form_out3, 3 * ld * cap, 8, 0);
         add(&V->g_t1, tr, 8, 0);
         add(&V->g_t2, tr, 8, 0);
         add(&V->aa_part, P->aa_nchunk * ld * cap, 8, 0);
-        add(&V->wf_part, 3 * P->aa_nchunk * ld * cap, 8, 1);
-        add(&V->w_forms, P->nsnap * ld, 8, 1);
-        add(&V->w_forms32, P->nsnap * ld, 4, 2);
+        // fast: the cells' W (FP64) for every lane and its contraction partials of three stacks; the
+        // call carves them from the rest of the workspace, in lane batches when less is given
+        add(nullptr, lat_forms_batch_bytes(P, ld), 1, 1);
         break;
     case LAT_CALL_ALPHA_ADJOINT:
         add(&V->aa_A, 2 * cap * ld, 8, 0);
@@ -440,7 +441,7 @@ void free_plan(lat_plan *P)
                     P->dm_gid, P->dm_bsum, P->goff,
                     P->unode, P->unbr, P->umask, P->uidx, P->u_cil, P->w_part, P->w_part2, P->g_sq, P->g_inf,
                     P->g_dot, P->g_t1, P->g_t2, P->g_t3, P->g_t4, P->v_sq, P->v_inf, P->v_beta, P->v_nu, P->beta_pl, P->zeta,
-                    P->ictl, P->dctl, P->form_part, P->form_out, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part,
+                    P->ictl, P->dctl, P->form_part, P->form_out, P->form_out3, P->alpha_il, P->aa_A, P->aa_B, P->aa_q, P->aa_gath, P->aa_part,
                     P->lp_err, P->lp_gate};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -659,6 +660,7 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     ALLOC(P->dctl, 64);
     ALLOC(P->form_part, (int64_t)P->napc * ld * cap);
     ALLOC(P->form_out, ld * cap);
+    ALLOC(P->form_out3, 3 * ld * cap);
     ALLOC(P->alpha_il, (int64_t)cap * ld);
     ALLOC(P->aa_A, (int64_t)cap * ld * 2);         // Z^T T_mu, Z^T T_lam   [2][ld][cap]
     ALLOC(P->aa_B, ld * cap * 2);                   // Delta^T T_S parts     [2][ld][cap]
@@ -808,15 +810,23 @@ void lat_ws_sizes(const lat_plan *P, int call, size_t *min_bytes, size_t *fast_b
     *fast_bytes = fs;
 }
 
+size_t lat_forms_batch_bytes(const lat_plan *P, int64_t lanes)
+{
+    return ((size_t)P->nsnap * lanes * 8 + 255) / 256 * 256 +
+           ((size_t)3 * P->aa_nchunk * lanes * P->cap * 8 + 255) / 256 * 256;
+}
+
 lat_status lat_ws_bind(const lat_plan *P, int call, void *work, size_t work_bytes, lat_plan *V)
 {
     *V = *P;
     WsItem it[32];
     const int n = ws_items(P, V, call, it);
+    V->ws_rest = nullptr;
+    V->ws_rest_bytes = 0;
     if (!work) {
         // the plan's own scratch; it holds none of the buffers that only a fast workspace brings
         for (int t = 0; t < n; ++t)
-            if (it[t].fast) *it[t].ptr = nullptr;
+            if (it[t].fast && it[t].ptr) *it[t].ptr = nullptr;
         return LAT_OK;
     }
     if (((uintptr_t)work & 255) != 0) return LAT_E_ARG;
@@ -827,11 +837,16 @@ lat_status lat_ws_bind(const lat_plan *P, int call, void *work, size_t work_byte
     char *base = (char *)work;
     size_t off = 0, last_off = 0;
     for (int t = 0; t < n; ++t) {
+        if (!it[t].ptr) continue;                      // carved by the call from the rest
         if (it[t].fast && !fast) { *it[t].ptr = nullptr; continue; }
         if (it[t].fast == 2) { *it[t].ptr = base + last_off; continue; }
         *it[t].ptr = base + off;
         last_off = off;
         off += ws_align(it[t].bytes);
+    }
+    if (work_bytes > off) {
+        V->ws_rest = base + off;
+        V->ws_rest_bytes = work_bytes - off;
     }
     return LAT_OK;
 }

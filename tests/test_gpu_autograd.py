@@ -73,6 +73,65 @@ def test_combo_lame_gradient(logmu):
         assert abs(fd - g[cell]) <= 1e-6 * abs(fd)
 
 
+@pytest.mark.timeout(600)
+def test_combo_lame_gradient_full_lattice():
+    # the full 8^3 log-uniform-mu lattice (512 cells, 12^3 hexes, cap 64): dJ/dmu of J = <X, Y(X)>
+    # against the scaling law on every cell, the oracle's assembled gradient on every cell, and
+    # central differences (h = 1e-6, principal set frozen) on two ordinary cells and one principal
+    from paper_2603_10741_amd import autograd as AG
+    c = Case(L.config(3), m=1)
+    P, cfg = c.P, c.cfg
+    st = AG.build_rom_state(P, c.ug, c.mu_t, c.lam_t, cfg.tol)
+    X, Xp = c.rhs(m=1)
+    mu = c.mu_t.clone().requires_grad_(True)
+    Y = AG.rom_apply(Xp, mu, 5.0 * mu, st, 1)
+    J = torch.sum(Y * Xp)
+    J.backward()
+    g = mu.grad.cpu().numpy()
+    Ns = cfg.n_cells
+    Xm = c.masked(X)
+    Ji = np.sum((c.unpack(Y.detach(), 1) * Xm).reshape(Ns, -1), axis=1)
+    np.testing.assert_allclose(g, Ji / c.mu, rtol=1e-8, atol=1e-12 * np.abs(Ji / c.mu).max())
+    S = st.S.cpu().numpy()[:st.n_r]
+    T = c.orc["T"]
+    alpha = np.linalg.lstsq(T[S].T, T.T, rcond=None)[0].T
+    Tm = O.cells_eval(3, cfg.nel, c.keep, c.uloc, np.ones(Ns), np.zeros(Ns), want_f=False, want_energy=False)["T"]
+    Tl = O.cells_eval(3, cfg.nel, c.keep, c.uloc, np.zeros(Ns), np.ones(Ns), want_f=False, want_energy=False)["T"]
+    nr = len(S)
+    abar = O.combo_forms(3, cfg.nel, T[S], nr, c.l2g, X, X)
+    Gm = O.combo_forms(3, cfg.nel, Tm[S], nr, c.l2g, X, X)
+    Gl = O.combo_forms(3, cfg.nel, Tl[S], nr, c.l2g, X, X)
+    mub = np.zeros(Ns); lamb = np.zeros(Ns)
+    for k, s_ in enumerate(S):
+        mub[s_] += np.sum(alpha[:, k] * Gm[:, k]); lamb[s_] += np.sum(alpha[:, k] * Gl[:, k])
+    tbar, TbarS = O.alpha_ls_adjoint(T[S].T, T, alpha, abar)
+    mub += np.sum(tbar * Tm, axis=1); lamb += np.sum(tbar * Tl, axis=1)
+    for k, s_ in enumerate(S):
+        mub[s_] += TbarS[:, k] @ Tm[s_]; lamb[s_] += TbarS[:, k] @ Tl[s_]
+    go = mub + 5.0 * lamb
+    assert rel(g, go) <= 1e-8
+    del Tm, Tl
+    h = 1e-6
+    ordinary = [int(x) for x in np.setdiff1d(np.arange(Ns), S)[[3, 200]]]
+    for cell in ordinary + [int(S[1])]:
+        vals = []
+        for sgn in (1, -1):
+            mu2 = c.mu.copy(); mu2[cell] += sgn * h
+            T2 = T.copy()
+            T2[cell] = O.cell_eval(3, cfg.nel, c.keep[cell], c.uloc[cell], mu2[cell], 5 * mu2[cell])["stencil"]
+            if cell in S:
+                a2 = np.linalg.lstsq(T2[S].T, T2.T, rcond=None)[0].T
+                Y2 = O.combo_apply(3, cfg.nel, T2[S], a2, c.l2g, X)
+                vals.append(np.sum(Y2 * Xm))
+            else:
+                a2 = np.linalg.lstsq(T2[S].T, T2[cell], rcond=None)[0]
+                Y2 = O.combo_apply(3, cfg.nel, T2[S], a2[None, :], c.l2g[[cell]], X[[cell]])
+                vals.append(np.sum(Y2 * Xm[[cell]]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print(f"[autograd] full 8^3 cell {cell} (principal {cell in S}): fd {fd:.6e} gpu {g[cell]:.6e}", flush=True)
+        assert abs(fd - g[cell]) <= 1e-6 * abs(fd)
+
+
 def test_combo_input_gradient_is_transpose(logmu):
     from paper_2603_10741_amd import autograd as AG
     c = logmu

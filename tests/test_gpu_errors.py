@@ -207,3 +207,34 @@ def test_caller_workspace_same_bits(c):
     for k in ("alpha_bar", "mu_bar", "lam_bar"):
         ref = a_fast[k]
         assert torch.max(torch.abs(a_min[k] - ref)).item() <= 1e-12 * torch.max(torch.abs(ref)).item()
+
+
+def test_adjoint_lane_batches_same_bits():
+    # a workspace with room for one 64-lane group of W past its minimum: the W pass and the
+    # contractions run in 16 batches on the 1024-cell lattice, with every lane's arithmetic unchanged
+    from paper_2603_10741_amd import binding as B
+    c = Case(L.config(1))
+    P, m = c.P, c.m
+    L_ = _lib()
+    r = P.residual_tangent(c.ug, c.mu_t, c.lam_t, f=False, energy=False, snap=True)
+    g = P.select_principal(r["snap"], c.cfg.tol)
+    n_r = int(g["n_r"].item())
+    parts = P.principal_ops(c.ug, c.mu_t, c.lam_t, g["S"], n_r, parts=True)
+    _, Xp = c.rhs()
+    _, Ybp = c.rhs(stream=1)
+    kw = dict(K_mu=parts["K_mu"], K_lam=parts["K_lam"], S=g["S"])
+    mn, fs = P.work_min[B.CALL_APPLY_COMBO_ADJOINT], P.work_fast[B.CALL_APPLY_COMBO_ADJOINT]
+    nbytes = mn + (fs - mn) * 64 // P.ld + 4096
+    assert nbytes < mn + (fs - mn) * 128 // P.ld          # room for one group, not two
+    work = torch.empty(nbytes, dtype=torch.uint8, device=c.dev)
+    for prec in (B.F64, B.BF16):
+        ref = P.apply_combo_adjoint(parts["K"], n_r, g["alpha"], Xp, Ybp, m, fast=True, prec=prec, **kw)
+        out = {k: torch.empty_like(v) for k, v in ref.items()}
+        st = L_.lat_apply_combo_adjoint(P._p, _p(parts["K"]), _p(parts["K_mu"]), _p(parts["K_lam"]), _p(g["S"]), n_r,
+                                        _p(g["alpha"]), _p(Xp), _p(Ybp), m, _p(out["Xbar"]), _p(out["alpha_bar"]),
+                                        _p(out["mu_bar"]), _p(out["lam_bar"]), prec, ctypes.c_double(1e-6), None,
+                                        _p(work), ctypes.c_size_t(nbytes), _s())
+        assert st == B.LAT_OK
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(out[k], ref[k]), (prec, k)
