@@ -322,6 +322,371 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs A)
     }
 }
 
+// 3D residual, energy and tangent with the quadrature-point data computed once per element and
+// node.  One workgroup of 9 waves per (group of 64 lanes, node a); wave w owns tangent row
+// i = w / 3 and offset plane pz = w % 3 of node a's stencil (27 entries).  For each of the up to 8
+// elements around a (a is the element's corner k), waves 0..NQ-1 take one quadrature point each:
+// F, H = F^{-T}, c2 = mu - lam ln J, the force row P g_a and, when a is the element's corner 0, the
+// energy (kept in registers); (H, c2, w) go to LDS, w the point's weight for lanes that keep the
+// element and 0 otherwise.  After a barrier every wave whose plane the element touches accumulates
+//   K[(a,i),(c,j)] += w [ mu d_ij (g_a . g_c) + c2 (p_a)_j (p_c)_i + lam (p_a)_i (p_c)_j ],  p = H g,
+// over the points and the element's four corners c in that plane.  Elements that no lane keeps
+// are skipped (a workgroup-uniform decision: every wave sees the same 64 lanes).  The force rows and
+// energies of the point-waves are summed in point order at the end.
+constexpr int CELL3_GPV = 11;        // per quadrature point: H (9), c2, w
+
+template <int RULE, bool PRINCIPAL>
+__global__ __launch_bounds__(576) void k_cell3(CellArgs A)
+{
+    using G = Geo<3>;
+    constexpr int NQ = RULE == LAT_RULE_REDUCED ? 1 : 8;
+    __shared__ double gp[NQ * CELL3_GPV * 64];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63;
+    const int row = w / 3, pz = w % 3;
+    const int nel = A.nel, nn = nel + 1;
+    const int64_t ld = A.ld;
+    const int arow = blockIdx.y;
+    int a = arow;
+    if (RULE == LAT_RULE_SAMPLED) {
+        const int nsa = A.nsa;
+        a = LAT_SAMPLE_STRIDE * ((arow % nsa) + nn * ((arow / nsa) % nsa) + nn * nn * (arow / (nsa * nsa)));
+    }
+    int64_t p;
+    int cell, slot = 0;
+    if (PRINCIPAL) {
+        slot = l;
+        cell = slot < A.n_r ? A.S[slot] : -1;
+        p = cell >= 0 ? A.lane[cell] : 0;
+    } else {
+        p = (int64_t)blockIdx.x * LAT_WAVE + l;
+        cell = A.perm[p];
+    }
+    const double h = 1.0 / nel, invh = (double)nel;
+    const double wq = (RULE == LAT_RULE_REDUCED ? 1.0 : 0.125) * h * h * h;
+    double mu = 0.0, lam = 0.0;
+    if (cell >= 0) {
+        mu = A.matmode == 0 ? A.mu[cell] : (A.matmode == 1 ? 1.0 : 0.0);
+        lam = A.matmode == 0 ? A.lam[cell] : (A.matmode == 2 ? 1.0 : 0.0);
+    }
+    const int ia[3] = {a % nn, (a / nn) % nn, a / (nn * nn)};
+    double acc[9][3];
+#pragma unroll
+    for (int o = 0; o < 9; ++o)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[o][j] = 0.0;
+    double facc[3] = {0.0, 0.0, 0.0}, en = 0.0;
+
+    auto element = [&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        int ie[3];
+        bool ok = true;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            ie[ax] = ia[ax] - ((k >> ax) & 1);
+            ok = ok && ie[ax] >= 0 && ie[ax] < nel;
+        }
+        if (!ok) return;                                        // the same for the whole workgroup
+        const int e = ie[0] + nel * (ie[1] + nel * ie[2]);
+        const bool kept = cell >= 0 && A.keep_il[(int64_t)e * ld + p];
+        if (__builtin_amdgcn_ballot_w64(kept) == 0) return;     // no lane keeps it (uniform)
+        // ---- quadrature-point phase: wave w < NQ takes point q = w
+        if (w < NQ) {
+            const int q = w;
+            double Hs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double c2 = 0.0, wgt = 0.0;
+            if (kept) {
+                double ue[8][3];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int b = (ie[0] + (c & 1)) + nn * ((ie[1] + ((c >> 1) & 1)) + nn * (ie[2] + ((c >> 2) & 1)));
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) ue[c][i] = A.u_cil[((int64_t)b * 3 + i) * ld + p];
+                }
+                double F[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) {
+                        const double g = shape_grad<3, RULE>(q, c, J, invh);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) F[i][J] += ue[c][i] * g;
+                    }
+                double C[3][3];                                     // cofactors
+                C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+                C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+                C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+                C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+                C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+                C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+                C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+                C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+                C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                const double Jd = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
+                const double r = 1.0 / Jd;
+                double lnJ = 0.0;
+                if (Jd > 0.0 && isfinite(Jd)) lnJ = log(Jd);
+                else lat_flag(A.st, isfinite(Jd) ? LAT_E_INVERTED : LAT_E_NONFINITE, cell);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) Hs[3 * i + J] = C[i][J] * r;
+                c2 = mu - lam * lnJ;
+                wgt = wq;
+                // force rows at node a (corner k): P g_a = mu (F g_a - p_a) + lam ln J p_a
+                double gk[3];
+#pragma unroll
+                for (int J = 0; J < 3; ++J) gk[J] = shape_grad<3, RULE>(q, k, J, invh);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    double pk = 0.0, Fg = 0.0;
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) {
+                        pk += Hs[3 * i + J] * gk[J];
+                        Fg += F[i][J] * gk[J];
+                    }
+                    facc[i] += wq * (mu * (Fg - pk) + lam * lnJ * pk);
+                }
+                if (k == 0) {                                       // element energy, owned by corner 0
+                    double I1 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int J = 0; J < 3; ++J) I1 += F[i][J] * F[i][J];
+                    en += wq * (0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 9; ++t) gp[(q * CELL3_GPV + t) * 64 + l] = Hs[t];
+            gp[(q * CELL3_GPV + 9) * 64 + l] = c2;
+            gp[(q * CELL3_GPV + 10) * 64 + l] = wgt;
+        }
+        __syncthreads();
+        // ---- accumulation phase: the element touches planes pz = 1 - k_z + {0, 1}
+        const int kz = (k >> 2) & 1;
+        if (pz == 1 || pz == 2 - 2 * kz) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double Hq[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) Hq[t] = gp[(q * CELL3_GPV + t) * 64 + l];
+                const double c2 = gp[(q * CELL3_GPV + 9) * 64 + l];
+                const double wgt = gp[(q * CELL3_GPV + 10) * 64 + l];
+                double gk[3], pk[3];
+#pragma unroll
+                for (int J = 0; J < 3; ++J) gk[J] = shape_grad<3, RULE>(q, k, J, invh);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) pk[i] = Hq[3 * i] * gk[0] + Hq[3 * i + 1] * gk[1] + Hq[3 * i + 2] * gk[2];
+                const double pk_row = row == 0 ? pk[0] : (row == 1 ? pk[1] : pk[2]);
+                double wc2pk[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) wc2pk[j] = wgt * c2 * pk[j];
+                const double wlpk = wgt * lam * pk_row, wmu = wgt * mu;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if ((((c >> 2) & 1) - kz + 1) != pz) continue;      // uniform per wave
+                    int oi = 0, sc = 1;                                 // in-plane offset index (x fastest)
+#pragma unroll
+                    for (int ax = 0; ax < 2; ++ax) { oi += (((c >> ax) & 1) - ((k >> ax) & 1) + 1) * sc; sc *= 3; }
+                    double gc[3], gkgc = 0.0;
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) { gc[J] = shape_grad<3, RULE>(q, c, J, invh); gkgc += gk[J] * gc[J]; }
+                    double pc[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) pc[i] = Hq[3 * i] * gc[0] + Hq[3 * i + 1] * gc[1] + Hq[3 * i + 2] * gc[2];
+                    const double pc_row = row == 0 ? pc[0] : (row == 1 ? pc[1] : pc[2]);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        double v = fma(wc2pk[j], pc_row, acc[oi][j]);
+                        v = fma(wlpk, pc[j], v);
+                        acc[oi][j] = (j == row) ? fma(wmu, gkgc, v) : v;
+                    }
+                }
+            }
+        }
+        __syncthreads();                                        // gp is rewritten by the next element
+    };
+    element(std::integral_constant<int, 0>{});
+    element(std::integral_constant<int, 1>{});
+    element(std::integral_constant<int, 2>{});
+    element(std::integral_constant<int, 3>{});
+    element(std::integral_constant<int, 4>{});
+    element(std::integral_constant<int, 5>{});
+    element(std::integral_constant<int, 6>{});
+    element(std::integral_constant<int, 7>{});
+
+    // ---- outputs
+    constexpr int E = G::E;
+    const int obase = 9 * pz;
+    if (PRINCIPAL) {
+        if (slot < A.cap) {
+#pragma unroll
+            for (int o = 0; o < 9; ++o)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    A.Kst[((int64_t)a * E + ((obase + o) * 3 + row) * 3 + j) * A.cap + slot] = acc[o][j];
+        }
+        return;
+    }
+    if (A.f || A.epart) {
+        // force rows and energy: the point-waves' partials through LDS, summed in point order
+        double *fr = gp;                                        // [NQ][4][64], gp is free now
+        if (w < NQ) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) fr[(w * 4 + i) * 64 + l] = facc[i];
+            fr[(w * 4 + 3) * 64 + l] = en;
+        }
+        __syncthreads();
+        if (w == 0) {
+            double fs[3] = {0.0, 0.0, 0.0}, es = 0.0;
+            for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) fs[i] += fr[(q * 4 + i) * 64 + l];
+                es += fr[(q * 4 + 3) * 64 + l];
+            }
+            if (A.f)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) A.f[((int64_t)a * 3 + i) * ld + p] = fs[i];
+            if (A.epart) A.epart[(int64_t)a * ld + p] = es;
+        }
+    }
+    if (A.T) {
+#pragma unroll
+        for (int o = 0; o < 9; ++o)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A.T[((int64_t)arow * E + ((obase + o) * 3 + row) * 3 + j) * ld + p] = acc[o][j];
+    }
+    if (A.ops) {
+        const int g = (int)(p / LAT_WAVE);
+        const int qi = A.uidx[(int64_t)g * A.nloc + a];
+        if (qi >= 0) {
+            const int64_t q = A.goff[g] + qi;
+#pragma unroll
+            for (int o = 0; o < 9; ++o)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) A.ops[(q * E + ((obase + o) * 3 + row) * 3 + j) * LAT_WAVE + l] = acc[o][j];
+        }
+    }
+}
+
+// Internal force and energy without the tangent (a residual evaluation, e.g. a line-search trial).
+// One thread per (lane, element) of one parity colour: the elements whose index along every axis
+// has the colour's parity share no node, so each thread adds its corner forces f_c = sum_q w P g_c
+// to f without atomics; the colours run in a fixed order (deterministic).  The element energy
+// goes to epart row e (every element is in exactly one colour).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_force_color(int nel, int64_t ld, int color, const double *__restrict__ u_cil,
+                                                     const uint8_t *__restrict__ keep_il,
+                                                     const int32_t *__restrict__ perm, const double *__restrict__ mu_a,
+                                                     const double *__restrict__ lam_a, double *__restrict__ f,
+                                                     double *__restrict__ epart, int32_t *st)
+{
+    using G = Geo<DIM>;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= ld) return;
+    const int nn = nel + 1;
+    int cnt[3] = {1, 1, 1}, ie[3] = {0, 0, 0};
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) cnt[ax] = (nel - ((color >> ax) & 1) + 1) / 2;
+    int rest = blockIdx.y;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        ie[ax] = 2 * (rest % cnt[ax]) + ((color >> ax) & 1);
+        rest /= cnt[ax];
+    }
+    if (rest > 0) return;                                       // past this colour's elements
+    const int e = ie[0] + nel * (ie[1] + nel * ie[2]);
+    const int cell = perm[p];
+    double en = 0.0;
+    if (cell >= 0 && keep_il[(int64_t)e * ld + p]) {
+        const double mu = mu_a[cell], lam = lam_a[cell];
+        const double h = 1.0 / nel, invh = (double)nel;
+        double hd = h;
+#pragma unroll
+        for (int ax = 1; ax < DIM; ++ax) hd *= h;
+        const double wq = (DIM == 2 ? 0.25 : 0.125) * hd;
+        int node[G::NC];
+        double ue[G::NC][DIM], fe[G::NC][DIM];
+#pragma unroll
+        for (int c = 0; c < G::NC; ++c) {
+            node[c] = (ie[0] + (c & 1)) + nn * ((ie[1] + ((c >> 1) & 1)) + nn * (DIM == 3 ? ie[2] + ((c >> 2) & 1) : 0));
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                ue[c][i] = u_cil[((int64_t)node[c] * DIM + i) * ld + p];
+                fe[c][i] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < (1 << DIM); ++q) {
+            double F[DIM][DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                for (int J = 0; J < DIM; ++J) F[i][J] = (i == J) ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < G::NC; ++c)
+#pragma unroll
+                for (int J = 0; J < DIM; ++J) {
+                    const double g = shape_grad<DIM, LAT_RULE_FULL>(q, c, J, invh);
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) F[i][J] += ue[c][i] * g;
+                }
+            double Jd, H[DIM][DIM];
+            if (DIM == 2) {
+                Jd = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                const double r = 1.0 / Jd;
+                H[0][0] = F[1][1] * r; H[0][1] = -F[1][0] * r;
+                H[1][0] = -F[0][1] * r; H[1][1] = F[0][0] * r;
+            } else {
+                double C[3][3];
+                C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+                C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+                C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+                C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+                C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+                C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+                C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+                C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+                C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+                Jd = F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
+                const double r = 1.0 / Jd;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) H[i][J] = C[i][J] * r;
+            }
+            double lnJ = 0.0;
+            if (Jd > 0.0 && isfinite(Jd)) lnJ = log(Jd);
+            else lat_flag(st, isfinite(Jd) ? LAT_E_INVERTED : LAT_E_NONFINITE, cell);
+            // P = mu (F - H) + lam ln J H
+            double Pm[DIM][DIM], I1 = DIM == 2 ? 1.0 : 0.0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                for (int J = 0; J < DIM; ++J) {
+                    Pm[i][J] = mu * (F[i][J] - H[i][J]) + lam * lnJ * H[i][J];
+                    I1 += F[i][J] * F[i][J];
+                }
+            en += wq * (0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+#pragma unroll
+            for (int c = 0; c < G::NC; ++c)
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int J = 0; J < DIM; ++J) s += Pm[i][J] * shape_grad<DIM, LAT_RULE_FULL>(q, c, J, invh);
+                    fe[c][i] += wq * s;
+                }
+        }
+        if (f)
+#pragma unroll
+            for (int c = 0; c < G::NC; ++c)
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) f[((int64_t)node[c] * DIM + i) * ld + p] += fe[c][i];
+    }
+    if (epart) epart[(int64_t)e * ld + p] = en;
+}
+
 // u^s = A^{sT} u gathered into the cell-interleaved layout (zero at nodes a cell does not own).
 __global__ void k_gather_u(int dim, int nloc, int64_t ld, const int32_t *__restrict__ l2g_il,
                            const int32_t *__restrict__ perm, const double *__restrict__ ug,
@@ -497,6 +862,12 @@ __global__ __launch_bounds__(256) void k_residual_adjoint(int nel, int64_t ld, c
 template <int DIM, int RULE, bool PRINCIPAL>
 lat_status launch_cell(const lat_plan *P, CellArgs &A, hipStream_t s)
 {
+    if (DIM == 3) {
+        dim3 grid(PRINCIPAL ? 1u : (unsigned)(P->ld / LAT_WAVE), (unsigned)P->nloc);
+        hipLaunchKernelGGL((k_cell3<RULE, PRINCIPAL>), grid, dim3(576), 0, s, A);
+        LAT_LAUNCH_CHECK();
+        return LAT_OK;
+    }
     if (PRINCIPAL) {
         dim3 grid(1, (unsigned)P->nloc, DIM == 3 ? 9 : 1);
         hipLaunchKernelGGL((k_cell<DIM, RULE, true>), grid, dim3(64), 0, s, A);
@@ -670,12 +1041,34 @@ lat_status lat_residual_tangent(const lat_plan *Pp, const double *u_global, cons
     CellArgs A = base_args(P);
     A.mu = mu; A.lam = lam; A.matmode = 0; A.st = dev_status;
     const bool full_snap = snap && snap_rule == LAT_RULE_FULL;
-    if (f_int || energy || plain_ops || full_snap) {
+    int64_t energy_rows = P->nloc;                   // rows of w_part holding energy partials
+    if (plain_ops || full_snap) {
         A.f = f_int;
         A.epart = energy ? P->w_part : nullptr;
         A.T = full_snap ? snap : nullptr;
         A.ops = plain_ops;
         if ((st = dispatch_cell<false>(P, LAT_RULE_FULL, A, stream)) != LAT_OK) return st;
+    } else if (f_int || energy) {
+        // residual and energy only: element-centric, colour by colour
+        if (f_int) {
+            const int64_t nf = (int64_t)P->nloc * P->dim * P->ld;
+            hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)std::min<int64_t>(lat_cdiv(nf, 256), 8192)), dim3(256), 0,
+                               stream, nf, f_int);
+            LAT_LAUNCH_CHECK();
+        }
+        const int half = (P->nel + 1) / 2;
+        const unsigned ecol = (unsigned)lat_ipow(half, P->dim);
+        for (int color = 0; color < (1 << P->dim); ++color) {
+            const dim3 grid((unsigned)lat_cdiv(P->ld, 256), ecol);
+            if (P->dim == 2)
+                hipLaunchKernelGGL(k_force_color<2>, grid, dim3(256), 0, stream, P->nel, P->ld, color, P->u_cil,
+                                   P->keep_il, P->perm, mu, lam, f_int, energy ? P->w_part : nullptr, dev_status);
+            else
+                hipLaunchKernelGGL(k_force_color<3>, grid, dim3(256), 0, stream, P->nel, P->ld, color, P->u_cil,
+                                   P->keep_il, P->perm, mu, lam, f_int, energy ? P->w_part : nullptr, dev_status);
+            LAT_LAUNCH_CHECK();
+        }
+        energy_rows = P->nelem;
     }
     if (snap && snap_rule == LAT_RULE_REDUCED) {
         CellArgs B = base_args(P);
@@ -699,16 +1092,17 @@ lat_status lat_residual_tangent(const lat_plan *Pp, const double *u_global, cons
         B.mu = mu; B.lam = lam; B.matmode = 0; B.st = dev_status; B.T = snap;
         B.nsa = P->nel / LAT_SAMPLE_STRIDE + 1;
         const int64_t nsamp = lat_snapshot_rows(P, LAT_RULE_SAMPLED) / P->E;
-        const dim3 grid((unsigned)lat_cdiv(P->ld, 256), (unsigned)nsamp, P->dim == 3 ? 9 : 1);
         if (P->dim == 2)
-            hipLaunchKernelGGL((k_cell<2, LAT_RULE_SAMPLED, false>), grid, dim3(256), 0, stream, B);
+            hipLaunchKernelGGL((k_cell<2, LAT_RULE_SAMPLED, false>), dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)nsamp),
+                               dim3(256), 0, stream, B);
         else
-            hipLaunchKernelGGL((k_cell<3, LAT_RULE_SAMPLED, false>), grid, dim3(256), 0, stream, B);
+            hipLaunchKernelGGL((k_cell3<LAT_RULE_SAMPLED, false>), dim3((unsigned)(P->ld / LAT_WAVE), (unsigned)nsamp),
+                               dim3(576), 0, stream, B);
         LAT_LAUNCH_CHECK();
         if ((st = zero_rows_past(P, nsamp * P->E, snap, stream)) != LAT_OK) return st;
     }
     if (energy) {
-        if ((st = lat_tree_reduce(P->w_part, P->nloc, P->ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
+        if ((st = lat_tree_reduce(P->w_part, energy_rows, P->ld, 0, P->v_sq, P->g_t1, P->g_t2, stream)) != LAT_OK) return st;
         hipLaunchKernelGGL(k_scatter_lanes, dim3((unsigned)lat_cdiv(P->ld, 256)), dim3(256), 0, stream, P->ld, P->perm,
                            P->v_sq, energy);
         LAT_LAUNCH_CHECK();

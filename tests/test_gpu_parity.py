@@ -57,6 +57,23 @@ def test_residual_energy_snapshot(case):
     assert np.abs(rg - ro).max() <= 1e-12 * scale_f
 
 
+def test_residual_only_path(case):
+    # force and energy without the tangent (element-centric colour passes) against the oracle and
+    # against the tangent kernel's own force
+    P = case.P
+    P.reset_status()
+    r1 = P.residual_tangent(case.ug, case.mu_t, case.lam_t, f=True, energy=True, snap=False, plain=False)
+    r2 = P.residual_tangent(case.ug, case.mu_t, case.lam_t, f=True, energy=True, snap=True, plain=False)
+    P.check_status()
+    o = case.orc
+    f1 = case.canon_field(r1["f"], case.dim)
+    f2 = case.canon_field(r2["f"], case.dim)
+    scale = np.abs(o["f"]).max()
+    assert np.abs(f1 - o["f"]).max() <= 1e-12 * scale
+    assert np.abs(f1 - f2).max() <= 1e-12 * scale
+    np.testing.assert_allclose(r1["energy"].cpu().numpy(), o["energy"], rtol=1e-12, atol=1e-15)
+
+
 def test_greedy_cross_fed_bit_exact(case):
     """GPU greedy on the oracle's snapshots reproduces the oracle bit for bit."""
     P, cfg = case.P, case.cfg
