@@ -373,6 +373,95 @@ lat_status lat_rom_solve(const lat_plan *plan, const double *K, int32_t n_r, con
 lat_status lat_coarse_operator(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha,
                                const uint8_t *fixed, int32_t materialize, double *K0, hipStream_t stream);
 
+/* ---- Inexact FETI-DP solve of the ROM tangent system (Sec. 3.3, eq. ifetidp_precond) ----
+ * Each cell is a subdomain.  Local nodes are primal (cell corners, plus `level` nodes per cell edge
+ * at the edge coordinates round(k n / (level + 1)), k = 1..level, halves rounded up), dual (the
+ * other cell-boundary nodes) or interior; the classes are those of the union of the cells' active
+ * nodes.  Primal nodes are assembled globally (ascending global id); a dual node shared by k >= 2
+ * cells (where active) carries k - 1 Lagrange multipliers chaining those cells in ascending id. */
+
+/* The partition at enrichment `level` (>= 0), for tests and tools: HOST outputs.
+ * counts [4]: primal global nodes, node-level multipliers, remaining (dual + interior) local
+ * nodes, dual local nodes.  node_class [(n+1)^d] (may be NULL): 0 interior, 1 dual, 2 primal, -1
+ * active in no cell.  primal_nodes [counts[0]] (may be NULL): their global ids, ascending.
+ * mult [counts[1]][4] (may be NULL): (cell_1, node_1, cell_2, node_2) per multiplier, by global
+ * node then chain position, cell_1 < cell_2 canonical ids.  Synchronises `stream`. */
+lat_status lat_feti_partition(const lat_plan *plan, int32_t level, int32_t *node_class, int64_t *counts,
+                              int64_t *primal_nodes, int32_t *mult, hipStream_t stream);
+
+/* Options of lat_feti_solve (HOST struct). */
+typedef struct {
+    int32_t n_delta;      /* principal cells in the local reduced models: 0 = all n_r, else min(n_delta, n_r) */
+    int32_t enrich;       /* enrichment level to start from (0 = corner primal nodes only) */
+    int32_t max_enrich;   /* highest enrichment level tried (>= enrich) */
+    int32_t inner_it;     /* PCG steps of the interface sub-solve F~^-pcg (0 = its Dirichlet preconditioner) */
+    int32_t restart;      /* FGMRES restart length, 1..512 */
+    int32_t maxit;        /* FGMRES iterations in total, >= 1 */
+    int32_t materialize;  /* products K~ u from the combined stencils (1) or from ROM applies (0) */
+    int32_t indefinite;   /* principal remaining blocks left indefinite after enrichment: 0 = shifted
+                             to definiteness; 1 = inverted by pivoted LU, the interface block by its
+                             Dirichlet preconditioner alone (see lat_feti_solve) */
+    double tol;           /* stop at ||res|| <= tol ||rhs|| (2-norms of the saddle-point system), > 0 */
+} lat_feti_opts;
+
+/* What a solve did (HOST struct). */
+typedef struct {
+    int32_t iters;        /* FGMRES iterations */
+    int32_t restarts;
+    int32_t enrich;       /* enrichment level used */
+    int32_t n_delta;      /* principal cells in the local reduced models */
+    int32_t n_shift;      /* principal remaining blocks not positive definite after enrichment */
+    int32_t reserved;
+    int64_t n_primal;     /* assembled primal DOFs */
+    int64_t n_mult;       /* multiplier rows: interface DOFs, then prescribed dual components */
+    int64_t n_rdofs;      /* remaining DOFs per cell (union layout) */
+    int64_t n_ddofs;      /* dual DOFs per cell */
+    double relres;        /* true relative residual of the saddle-point system at exit */
+    double max_shift;     /* largest diagonal shift s of those blocks (0 when none) */
+    double t_setup_ms;    /* partition, principal factorisations, coarse problem */
+    double t_solve_ms;    /* FGMRES */
+} lat_feti_info;
+
+/* Solve K~ x = b on the free components (eq. linsys with the ROM operator of eq.
+ * romstiffnessmatrix, as lat_rom_solve) by iterating on the FETI-DP saddle-point system
+ *     [K~  B^T] [u]   [f]      K~ the partially assembled ROM tangent, B the interface jumps,
+ *     [B   0  ] [l] = [0]      f = b split over the cells sharing a node (primal rows: b)
+ * with restarted FGMRES, right-preconditioned by the block factorisation of eq. ifetidp_precond.
+ * Its local operators are reduced models over the first n_delta principal cells r (Algorithm 1's
+ * order): the inverse remaining block G_r = (K_RR^r)^-1 (a Cholesky factor and inverse per
+ * principal cell, FP64), the primal harmonic extension -G_r K_RP^r, the local primal Schur
+ * complement and the local dual Schur complement F_dd^r = (G_r)_dd with its inverse; cell s uses
+ * sum_r delta_r^s (.)_r, delta^s the coordinates of its snapshot in the first n_delta principal
+ * snapshots (R[:nd,:nd] delta = nu_s beta^s[:nd], from the greedy; alpha when nd = n_r or R is
+ * NULL).  The assembled coarse problem is inverted in FP64 (LU); the interface block F^-1 is
+ * `inner_it` PCG steps on B K~rom^-1 B^T with the Dirichlet preconditioner
+ * B_D (sum_r delta_r (F_dd^r)^-1) B_D^T, B_D = (B B^T)^-1 B node by node.  A principal remaining
+ * block that is not positive definite (Cholesky failure or a pivot <= 1e-12 of its diagonal entry)
+ * raises the enrichment level and the setup restarts (Sec. 3.3.2), while the next level adds an
+ * active primal node and does not pass max_enrich; past that, a block that is not positive
+ * definite but nonsingular (pivoted LU, pivots > 1e-13 of the largest diagonal entry; info->n_shift
+ * counts them) enters the local models as (K_RR^r + s diag K_RR^r)^-1, s the smallest of 1e-6,
+ * 1e-5, ..., 1 that makes it positive definite (opts->indefinite = 0, info->max_shift), or is
+ * inverted by that LU with the interface block then its Dirichlet preconditioner alone
+ * (opts->indefinite = 1).  FGMRES iterates on the exact operator either way.  A ROM tangent that is
+ * itself indefinite (a lattice past buckling) is out of this preconditioner's reach: expect
+ * LAT_E_NOCONV (lat_rom_solve's MINRES handles it).
+ * K, n_r (HOST, 1..cap), alpha as for lat_apply_combo; S [cap] the principal cells
+ * (lat_select_principal); R [cap][cap], nu [N_s], beta [N_s][cap] from the greedy, or all NULL.
+ * fixed [n_global][d] (1 = prescribed): a prescribed component of a dual node is imposed by one more
+ * multiplier row (on its lowest-id owner), so boundary cells keep the local operators of free
+ * cells; prescribed primal components leave the coarse problem; those of interior nodes are
+ * removed.  b [n_global][d] (prescribed components ignored),
+ * x [n_global][d] out: primal nodes from u_P, others the mean of the owning cells' u_R, prescribed
+ * components 0; x starts from 0.  Device workspace is allocated for the call and freed before it
+ * returns; synchronises `stream`.  info (HOST, may be NULL) receives the statistics.  Returns LAT_OK
+ * when ||res|| <= tol ||rhs||, LAT_E_NOCONV at maxit (x holds the last iterate), LAT_E_SINGULAR
+ * when a principal remaining block, a dual block or the coarse matrix is singular, or the Krylov
+ * space breaks down, LAT_E_SHAPE when the coarse problem exceeds 40000 DOFs. */
+lat_status lat_feti_solve(const lat_plan *plan, const double *K, int32_t n_r, const double *alpha, const int32_t *S,
+                          const double *R, const double *nu, const double *beta, const uint8_t *fixed, const double *b,
+                          double *x, const lat_feti_opts *opts, lat_feti_info *info, hipStream_t stream);
+
 /* Options of lat_newton_solve (HOST struct). */
 typedef struct {
     int32_t n_inc;          /* load increments, >= 1 */

@@ -53,6 +53,26 @@ class NewtonRecord(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FetiOpts(ctypes.Structure):
+    """lat_feti_opts"""
+    _fields_ = [("n_delta", ctypes.c_int32), ("enrich", ctypes.c_int32), ("max_enrich", ctypes.c_int32),
+                ("inner_it", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("materialize", ctypes.c_int32), ("indefinite", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class FetiInfo(ctypes.Structure):
+    """lat_feti_info"""
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("enrich", ctypes.c_int32),
+                ("n_delta", ctypes.c_int32), ("n_shift", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_primal", ctypes.c_int64), ("n_mult", ctypes.c_int64),
+                ("n_rdofs", ctypes.c_int64), ("n_ddofs", ctypes.c_int64), ("relres", ctypes.c_double),
+                ("max_shift", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LatError(RuntimeError):
     def __init__(self, code, where=""):
         self.code = int(code)
@@ -102,6 +122,8 @@ def _lib():
             "lat_rom_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, F, I32, I32, I32, I32, P, P, P, P]),
             "lat_coarse_operator": (ctypes.c_int, [P, P, I32, P, P, I32, P, P]),
             "lat_newton_solve": (ctypes.c_int, [P, P, P, P, P, P, P, P, P, I32, P, P]),
+            "lat_feti_partition": (ctypes.c_int, [P, I32, P, P, P, P, P]),
+            "lat_feti_solve": (ctypes.c_int, [P, P, I32, P, P, P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -119,7 +141,8 @@ def exported_symbols():
             "lat_apply_combo", "lat_apply_combo_noalloc", "lat_basis_stack",
             "lat_apply_plain", "lat_apply_combo_adjoint", "lat_alpha_adjoint", "lat_residual_adjoint",
             "lat_assemble", "lat_gather", "lat_pack", "lat_unpack", "lat_cil_to_canon", "lat_canon_to_cil",
-            "lat_plain_ops_to_canon", "lat_rom_solve", "lat_coarse_operator", "lat_newton_solve"]
+            "lat_plain_ops_to_canon", "lat_rom_solve", "lat_coarse_operator", "lat_newton_solve",
+            "lat_feti_partition", "lat_feti_solve"]
 
 
 def _ptr(t):
@@ -442,6 +465,44 @@ class Plan:
         if info is not None:
             info["coarse_used"] = bool(cu.value)
         return x, st, it.value, rel.value
+
+    def feti_partition(self, level=0):
+        """FETI-DP partition tables at an enrichment level (lat_feti_partition): dict(cls [nloc],
+        primal [n_p] global node ids, mult [n_mult][4] (cell_1, node_1, cell_2, node_2))."""
+        import numpy as np
+        counts = (ctypes.c_int64 * 4)()
+        _ok(_lib().lat_feti_partition(self._p, int(level), None, counts, None, None, _stream()), "feti_partition")
+        cls = np.zeros(self.nloc, np.int32)
+        prim = np.zeros(max(counts[0], 1), np.int64)
+        mult = np.zeros((max(counts[1], 1), 4), np.int32)
+        _ok(_lib().lat_feti_partition(self._p, int(level), cls.ctypes.data_as(ctypes.c_void_p), counts,
+                                      prim.ctypes.data_as(ctypes.c_void_p), mult.ctypes.data_as(ctypes.c_void_p),
+                                      _stream()), "feti_partition")
+        return {"cls": cls, "primal": prim[:counts[0]], "mult": mult[:counts[1]], "n_remaining": int(counts[2]),
+                "n_dual": int(counts[3])}
+
+    def feti_solve(self, K, n_r, alpha, S, fixed, b, R=None, nu=None, beta=None, n_delta=0, enrich=0, max_enrich=3,
+                   inner_it=8, restart=60, maxit=600, tol=1e-8, materialize=True, indefinite=0, x=None):
+        """K~ x = b on the free components by the inexact FETI-DP iteration (lat_feti_solve).
+        Returns (x, status, info dict); status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other
+        codes raise."""
+        n = max(self.nglobal, 1) * self.dim
+        _need(b, n, torch.float64, "b")
+        _need(fixed, n, torch.uint8, "fixed")
+        _need(alpha, self.ncells * self.cap, torch.float64, "alpha")
+        _need(S, self.cap, torch.int32, "S")
+        _need(K, self.nloc * self.E * self.cap, torch.float64, "K")
+        for t, sz, nm in ((R, self.cap * self.cap, "R"), (nu, self.ncells, "nu"), (beta, self.ncells * self.cap, "beta")):
+            _need(t, sz, torch.float64, nm)
+        x = self._f64(n) if x is None else x
+        o = FetiOpts(int(n_delta), int(enrich), int(max_enrich), int(inner_it), int(restart), int(maxit),
+                     int(bool(materialize)), int(indefinite), float(tol))
+        inf = FetiInfo()
+        st = _lib().lat_feti_solve(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(S), _ptr(R), _ptr(nu), _ptr(beta),
+                                   _ptr(fixed), _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())
+        if st not in (LAT_OK, LAT_E_NOCONV, LAT_E_SINGULAR):
+            raise LatError(st, "feti_solve")
+        return x, st, inf.as_dict()
 
     def coarse_operator(self, K, n_r, alpha, fixed, materialize=True):
         """Dense K0 = P^T K~ P over the cell-corner nodes (lat_coarse_operator)."""

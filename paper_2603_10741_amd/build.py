@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblat.so")
 SOURCES = ["lat_plan.hip", "lat_cell.hip", "lat_greedy.hip", "lat_apply.hip", "lat_adjoint.hip", "lat_lowp.hip",
-           "lat_newton.hip", "lat_noalloc.hip"]
+           "lat_newton.hip", "lat_noalloc.hip", "lat_feti.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep packed-FP32 instructions out of the generated code

@@ -177,3 +177,7 @@ lat_status lat_contract_rows(const lat_plan *P, int n_r, const double *V, const 
 // part[t] [aa_nchunk][ld][cap], to be reduced by lat_tree_reduce.
 lat_status lat_contract_rows_multi(const lat_plan *P, int n_r, const double *V, const float *V32,
                                    const double *const *U, int ns, double *const *part, hipStream_t s);
+
+// Combined stencils of every cell, sum_k alpha_sk K_k, in lat_apply_plain's packed operator layout
+// (defined in lat_newton.hip).
+lat_status lat_combine_ops(const lat_plan *P, const double *K, int n_r, const double *alpha, double *ops, hipStream_t s);

@@ -1121,6 +1121,11 @@ double ms_since(std::chrono::steady_clock::time_point t0)
 
 }  // namespace
 
+lat_status lat_combine_ops(const lat_plan *P, const double *K, int n_r, const double *alpha, double *ops, hipStream_t s)
+{
+    return combine_ops(P, K, n_r, alpha, ops, s);
+}
+
 extern "C" {
 
 lat_status lat_rom_solve(const lat_plan *P, const double *K, int32_t n_r, const double *alpha, const uint8_t *fixed,

@@ -1,0 +1,258 @@
+"""GPU checks of the inexact FETI-DP tangent solve (Sec. 3.3, eq. ifetidp_precond) through the C ABI.
+
+* The partition (primal corner and edge nodes, dual nodes, chained multipliers) equals the
+  oracle's (oracle/feti.py) bit for bit, on 2D and 3D masked lattices and at several enrichment
+  levels.
+* The solve of K~ x = b on the free components against the oracle's sparse direct solve of the
+  same ROM tangent (oracle/newton.py's global matrix from the oracle's own principal tangents and
+  the GPU's coefficients).  FGMRES stops at ||res||_2 <= tol ||rhs||_2 of the saddle-point system;
+  with tol = 1e-11 the assembled residual b - K~ x of the owners' mean is below 1e-8 ||b|| here,
+  and the error against the direct solve is at most cond(K~) (5.6e4 on the 4x4 graded lattice at
+  1% compression) times that, hence the 1e-6 bound on the solution.
+* When every cell is principal and its own coordinates pick it alone, the local reduced models are
+  the exact local inverses: with enough interface PCG steps the preconditioner is the exact
+  inverse of the saddle-point operator and FGMRES stops within 3 iterations.
+* Adaptive enrichment (Sec. 3.3.2): with the cell corners removed from every cell the corner-only
+  partition leaves floating remaining blocks (singular); the solve raises the level, matches the
+  direct solve, and with max_enrich = 0 it reports LAT_E_SINGULAR.  On the 4x4 graded lattice at 1%
+  compression one corner-pinned block is indefinite (a ligament near buckling) and level 1 fixes it.
+* Blocks that stay indefinite (enrichment off, or no level adding an active primal node, as in BCC
+  voxel cells whose edges are void) are inverted by LU or shifted to definiteness; with a positive
+  definite ROM tangent the solve still matches the direct solve.  An indefinite ROM tangent (past
+  buckling: the graded lattice at 3% compression, a BCC lattice from 0.5% compression on) is out of
+  the preconditioner's reach: the solve reports LAT_E_NOCONV.  The 3D cases are at rest and in
+  tension.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import lattice as L
+import oracle as O
+from oracle import feti as OF
+from oracle import newton as ON
+from gpu_common import rel
+from test_gpu_newton import NCase, graded_cfg
+
+pytestmark = pytest.mark.gpu
+
+
+def _rom(nc, u_glob, tol, cap):
+    """GPU snapshots, greedy and principal tangents at u; the oracle's global ROM matrix from its
+    own principal tangents with the GPU's principal cells and coefficients."""
+    P = nc.P
+    u_t = torch.from_numpy(np.ascontiguousarray(u_glob)).to(nc.dev)
+    out = P.residual_tangent(u_t, nc.mu_t, nc.lam_t, f=False, energy=False, snap=True)
+    g = P.select_principal(out["snap"], tol, cap=cap)
+    n_r = int(g["n_r"].item())
+    K = P.principal_ops(u_t, nc.mu_t, nc.lam_t, g["S"], n_r)["K"]
+    P.check_status(allow_cap=True)
+    _, T, _, _ = nc.orc.evaluate(u_glob, 1.0)
+    S = g["S"].cpu().numpy()[:n_r]
+    Ko = ON.rom_matrix(nc.cfg.dim, nc.cfg.nel, T[S], g["alpha"].cpu().numpy(), nc.orc.l2g, nc.orc.ng)
+    return K, n_r, g, Ko
+
+
+def _direct(nc, Ko, b):
+    f = nc.orc.free
+    xo = np.zeros(b.size)
+    xo[f] = spla.spsolve(Ko[f][:, f].tocsc(), b.ravel()[f])
+    return xo
+
+
+def _check_solution(nc, Ko, b, x, xo, res_bound=1e-8, err_bound=1e-6):
+    f = nc.orc.free
+    x = x.reshape(-1).cpu().numpy()
+    assert np.all(x[~f] == 0.0)
+    bf = b.ravel()[f]
+    res = np.linalg.norm(Ko[f][:, f] @ x[f] - bf) / np.linalg.norm(bf)
+    err = rel(x, xo)
+    print(f"[feti] assembled residual {res:.2e}, error vs direct solve {err:.2e}", flush=True)
+    assert res <= res_bound
+    assert err <= err_bound
+
+
+@pytest.fixture(scope="module")
+def graded():
+    return NCase(graded_cfg(), L.LoadCase("compress_shear", 0.04, 0.01, 4))
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_partition_matches_oracle_2d(graded, level):
+    nc = graded
+    p = nc.P.feti_partition(level)
+    o = OF.partition(nc.cfg.dim, nc.cfg.nel, nc.orc.l2g, level)
+    assert np.array_equal(p["cls"], o["cls"])
+    assert np.array_equal(p["primal"], o["primal"])
+    assert np.array_equal(p["mult"], o["mult"])
+    assert p["n_dual"] == int((o["cls"] == OF.DUAL).sum())
+    assert p["n_remaining"] == int(((o["cls"] == OF.DUAL) | (o["cls"] == OF.INTERIOR)).sum())
+
+
+@pytest.mark.parametrize("idx,sub,level", [(2, (3, 3, 2), 0), (4, (2, 2, 2), 1)])
+def test_partition_matches_oracle_3d(idx, sub, level):
+    from paper_2603_10741_amd import binding as B
+    cfg = L.config(idx).with_sub(sub)
+    keep = L.make_keep(cfg)
+    P = B.Plan(cfg.dim, cfg.ncell_eff, cfg.nel, keep, cap=8)
+    l2g, _, _ = O.dofmap(cfg.dim, cfg.ncell_eff, cfg.nel, keep)
+    p = P.feti_partition(level)
+    o = OF.partition(cfg.dim, cfg.nel, l2g, level)
+    assert np.array_equal(p["cls"], o["cls"])
+    assert np.array_equal(p["primal"], o["primal"])
+    assert np.array_equal(p["mult"], o["mult"])
+
+
+@pytest.mark.parametrize("n_delta", [0, 4])
+def test_solve_matches_direct_solve(graded, n_delta):
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, g, Ko = _rom(nc, u, 1e-4, 16)
+    rng = np.random.default_rng(31)
+    b = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    b_t = torch.from_numpy(b).to(nc.dev)
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"], beta=g["beta"],
+                                  n_delta=n_delta, tol=1e-11, maxit=400)
+    print(f"[feti] n_r {n_r} n_delta {info['n_delta']}: {info}", flush=True)
+    assert st == nc.B.LAT_OK and info["relres"] <= 1e-11
+    assert info["n_delta"] == (n_r if n_delta == 0 else min(n_delta, n_r))
+    assert 0 < info["iters"] <= 200
+    _check_solution(nc, Ko, b, x, _direct(nc, Ko, b))
+    # a second solve gives the same bits (fixed-order reductions, rocBLAS without atomics)
+    x2, _, info2 = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"], beta=g["beta"],
+                                   n_delta=n_delta, tol=1e-11, maxit=400)
+    assert info2["iters"] == info["iters"] and torch.equal(x, x2)
+    # the interface block by its Dirichlet preconditioner alone still converges (more iterations)
+    x3, st3, info3 = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"],
+                                     beta=g["beta"], n_delta=n_delta, inner_it=0, tol=1e-11, maxit=800)
+    assert st3 == nc.B.LAT_OK
+    _check_solution(nc, Ko, b, x3, _direct(nc, Ko, b))
+
+
+def test_exact_local_models_when_every_cell_is_principal():
+    cfg = graded_cfg().with_sub((3, 3))
+    nc = NCase(cfg, L.LoadCase("compress_shear", 0.04, 0.01, 4), cap=16)
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, g, Ko = _rom(nc, u, 1e-15, 16)
+    assert n_r == cfg.n_cells
+    # every cell's coordinates pick its own principal slot
+    a = g["alpha"].cpu().numpy()[:, :n_r]
+    S = g["S"].cpu().numpy()[:n_r]
+    E = np.zeros_like(a)
+    E[S, np.arange(n_r)] = 1.0
+    assert np.abs(a - E).max() <= 1e-8
+    rng = np.random.default_rng(32)
+    b = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, torch.from_numpy(b).to(nc.dev),
+                                  inner_it=200, tol=1e-10, maxit=50)
+    print(f"[feti] exact local models: {info}", flush=True)
+    assert st == nc.B.LAT_OK and info["iters"] <= 3
+    _check_solution(nc, Ko, b, x, _direct(nc, Ko, b))
+
+
+def test_enrichment_when_the_corners_float():
+    cfg = L.config(0).with_(radius=(0.2, 0.2)).with_sub((3, 3))
+    keep = np.ones((cfg.n_cells, cfg.nel ** 2), np.uint8)
+    n = cfg.nel
+    for ex, ey in ((0, 0), (n - 1, 0), (0, n - 1), (n - 1, n - 1)):
+        keep[:, ex + n * ey] = 0                       # no cell owns its corner nodes
+    nc = NCase(cfg, L.LoadCase("compress_shear", 0.04, 0.01, 4), keep=keep, cap=16)
+    p0 = nc.P.feti_partition(0)
+    assert len(p0["primal"]) == 0                      # no corner node is active anywhere
+    u = np.zeros((nc.P.nglobal, cfg.dim))
+    K, n_r, g, Ko = _rom(nc, u, 1e-12, 16)
+    rng = np.random.default_rng(33)
+    b = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    b_t = torch.from_numpy(b).to(nc.dev)
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, enrich=0, max_enrich=3, tol=1e-11,
+                                  maxit=400)
+    print(f"[feti] enrichment: {info}", flush=True)
+    assert st == nc.B.LAT_OK and info["enrich"] >= 1
+    assert info["n_primal"] == len(nc.P.feti_partition(info["enrich"])["primal"]) * cfg.dim
+    _check_solution(nc, Ko, b, x, _direct(nc, Ko, b))
+    _, st0, info0 = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, enrich=0, max_enrich=0)
+    assert st0 == nc.B.LAT_E_SINGULAR and info0["enrich"] == 0
+
+
+@pytest.mark.parametrize("strain", [0.0, -0.01])
+def test_solve_3d_bcc_matches_direct_solve(strain):
+    # at rest and in 1% tension the BCC sub-lattice's tangent is positive definite, and so are the
+    # corner-pinned remaining blocks (Cholesky, no enrichment)
+    cfg = L.config(2).with_sub((3, 3, 2))
+    nc = NCase(cfg, L.LoadCase("compress_shear", 0.02, 0.005, 4), cap=16)
+    u = L.make_displacement(cfg.with_(strain=strain, pert_amp=1e-4))[nc.orc.g2bg] if strain else \
+        np.zeros((nc.P.nglobal, cfg.dim))
+    K, n_r, g, Ko = _rom(nc, u, 1e-4, 16)
+    rng = np.random.default_rng(34)
+    b = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, torch.from_numpy(b).to(nc.dev), R=g["R"],
+                                  nu=g["nu"], beta=g["beta"], n_delta=8, tol=1e-11, maxit=600)
+    print(f"[feti] 3D strain {strain}: n_r {n_r} {info}", flush=True)
+    assert st == nc.B.LAT_OK and info["n_shift"] == 0 and info["enrich"] == 0
+    assert info["iters"] <= 150
+    _check_solution(nc, Ko, b, x, _direct(nc, Ko, b), err_bound=1e-5)
+
+
+def test_indefinite_local_blocks_without_enrichment(graded):
+    # 1% compression of the graded lattice: the ROM tangent is positive definite but one principal
+    # cell's corner-pinned remaining block is not (a ligament near buckling).  With enrichment off
+    # that block is shifted to definiteness (mode 0) or inverted by LU with the interface block by
+    # its Dirichlet preconditioner (mode 1); both solves match the direct solve
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, g, Ko = _rom(nc, u, 1e-4, 16)
+    rng = np.random.default_rng(36)
+    b = rng.standard_normal((nc.P.nglobal, cfg.dim))
+    b_t = torch.from_numpy(b).to(nc.dev)
+    for mode in (0, 1):
+        x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"],
+                                      beta=g["beta"], max_enrich=0, indefinite=mode, tol=1e-11, maxit=600)
+        print(f"[feti] indefinite local blocks, mode {mode}: {info}", flush=True)
+        assert st == nc.B.LAT_OK and info["enrich"] == 0 and info["n_shift"] >= 1
+        assert (info["max_shift"] > 0) == (mode == 0)
+        _check_solution(nc, Ko, b, x, _direct(nc, Ko, b), err_bound=1e-5)
+
+
+def test_indefinite_tangent_reports_no_convergence(graded):
+    # 3% compression: the ROM tangent itself has a negative eigenvalue (the lattice is past its
+    # first buckling load); the FETI-DP preconditioner does not resolve that mode and the solve
+    # ends at maxit with LAT_E_NOCONV and a finite iterate (the Newton driver then takes MINRES)
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.03, pert_amp=2e-3))[nc.orc.g2bg]
+    K, n_r, g, _ = _rom(nc, u, 1e-4, 16)
+    rng = np.random.default_rng(37)
+    b_t = torch.from_numpy(rng.standard_normal((nc.P.nglobal, cfg.dim))).to(nc.dev)
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"], beta=g["beta"],
+                                  tol=1e-10, maxit=40)
+    print(f"[feti] indefinite tangent: {info}", flush=True)
+    assert st == nc.B.LAT_E_NOCONV and info["iters"] == 40
+    assert torch.isfinite(x).all()
+
+
+def test_solve_edge_cases(graded):
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.005, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, g, _ = _rom(nc, u, 1e-3, 16)
+    B = nc.B
+    zero = torch.zeros(nc.P.nglobal, cfg.dim, dtype=torch.float64, device=nc.dev)
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, zero)
+    assert st == B.LAT_OK and info["iters"] == 0 and torch.count_nonzero(x).item() == 0
+    # b supported on prescribed components only is the zero right-hand side
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, nc.fixed_t.to(torch.float64) * 3.0)
+    assert st == B.LAT_OK and info["iters"] == 0 and torch.count_nonzero(x).item() == 0
+    rng = np.random.default_rng(35)
+    bt = torch.from_numpy(rng.standard_normal((nc.P.nglobal, cfg.dim))).to(nc.dev)
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, bt, tol=1e-15, maxit=3, restart=2)
+    assert st == B.LAT_E_NOCONV and info["iters"] == 3 and info["restarts"] == 1
+    # argument checks on the host
+    with pytest.raises(B.LatError):
+        nc.P.feti_solve(K, 0, g["alpha"], g["S"], nc.fixed_t, bt)
+    with pytest.raises(B.LatError):
+        nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, bt, tol=0.0)
+    with pytest.raises(B.LatError):
+        nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, bt, enrich=2, max_enrich=1)
