@@ -320,7 +320,9 @@ def main():
     ap.add_argument("--radius", type=float, default=None, help="--newton: one hole radius for every cell")
     ap.add_argument("--matvec", choices=["stencils", "rom"], default="stencils",
                     help="--newton: ROM tangent products from stencils formed once per iteration, or ROM applies")
-    ap.add_argument("--precond", choices=["two-level", "diag"], default="two-level", help="--newton: preconditioner")
+    ap.add_argument("--precond", choices=["two-level", "diag", "feti"], default="two-level",
+                    help="--newton: tangent solve (MINRES two-level / diagonal, or the inexact FETI-DP solve)")
+    ap.add_argument("--feti-n-delta", type=int, default=8, help="--newton --precond feti: principal cells per local model")
     ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
                     help="--newton: ROM tangent, or every cell's own tangent (the standard method)")
     args = ap.parse_args()
@@ -628,7 +630,9 @@ def newton_main(args):
                               cg_check=64, verbose=True, tangent=1 if args.tangent == "full" else 0,
                               snap_rule={"full": B.RULE_FULL, "reduced": B.RULE_REDUCED,
                                          "material": B.RULE_MATERIAL, "sampled": B.RULE_SAMPLED}[args.snap_rule],
-                              matvec=1 if args.matvec == "rom" else 0, precond=0 if args.precond == "diag" else 1)
+                              matvec=1 if args.matvec == "rom" else 0,
+                              precond={"diag": 0, "two-level": 1, "feti": 2}[args.precond],
+                              feti_n_delta=args.feti_n_delta)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tot = {k: float(sum(r[k] for r in recs)) for k in ("t_init_ms", "t_solve_ms", "t_eval_ms")}
@@ -637,17 +641,6 @@ def newton_main(args):
     # by the driver with HIP events around up to 64 products of every solve (on its stream)
     tp = [r["t_product_us"] for r in recs if r["t_product_us"] > 0]
     t_mv = float(np.mean(tp)) * 1e-6 if tp else float("nan")
-    lane_nodes = int(nact.sum().item())
-    rom_products = args.matvec == "rom" and args.tangent == "rom"
-    if rom_products:
-        # ROM apply forming the stencils on the matrix cores: 2 E N_r flops per packed lane-node
-        # (combination) + 2 E per active lane-node (apply), against the FP64 matrix-core peak
-        nr_avg = float(np.mean([r["n_r"] for r in recs])) if recs else 0.0
-        mv_flops = 2.0 * P.E * nr_avg * P.npacked * 64 + 2.0 * P.E * lane_nodes
-        mv_bytes = 16.0 * lane_nodes * cfg.dim + 8.0 * (P.nloc * P.E + P.ncells) * nr_avg
-    else:
-        # per-cell stencils (8 B x E per active lane-node) + X read + Y written
-        mv_bytes = 8.0 * lane_nodes * P.E + 16.0 * lane_nodes * cfg.dim
     lane_nodes = int(nact.sum().item())
     rom_products = args.matvec == "rom" and args.tangent == "rom"
     if rom_products:
@@ -677,8 +670,12 @@ def newton_main(args):
                    "tangent": args.tangent, "snap_rule": args.snap_rule, "rb_tol": args.rb_tol, "cap": args.cap,
                    "newton_tol": 1e-6,
                    "armijo": [0.5, 1e-4],
-                   "tangent_solve": {"method": "MINRES", "preconditioner": args.precond, "products": args.matvec,
-                                     "tol": args.solve_tol}},
+                   "tangent_solve": ({"method": "inexact FETI-DP (FGMRES on the saddle-point system), MINRES "
+                                                "two-level on a step it does not converge on",
+                                      "n_delta": args.feti_n_delta, "products": args.matvec, "tol": args.solve_tol}
+                                     if args.precond == "feti" else
+                                     {"method": "MINRES", "preconditioner": args.precond, "products": args.matvec,
+                                      "tol": args.solve_tol})},
         "roofline": ({"bound": "mfma", "achieved": round(mv_flops / t_mv / 1e12, 2), "peak": FP64_MFMA_PEAK_TF,
                       "unit": "TFLOP/s", "frac": round(mv_flops / t_mv / 1e12 / FP64_MFMA_PEAK_TF, 4),
                       "algorithmic_flops_per_launch": int(mv_flops)} if rom_products else
@@ -699,11 +696,15 @@ def newton_main(args):
         "split_ms": {k[2:-3]: round(v, 2) for k, v in tot.items()},
         "iterations": [{"inc": r["increment"], "it": r["iteration"], "n_r": r["n_r"],
                         "rb_achieved": float("%.3g" % r["rb_achieved"]), "m": r["backtracks"],
-                        "solve_its": r["cg_iters"], "solve_status": r["cg_status"],
+                        "solve_its": r["cg_iters"], "solve_status": r["cg_status"], "solver": r["solver"],
+                        "feti_its": r["feti_iters"], "feti_enrich": r["feti_enrich"],
+                        "feti_setup_ms": round(r["t_feti_setup_ms"], 1),
                         "rel_res": float("%.3g" % (r["res_after"] / r["res0"])),
                         "ms": [round(r["t_init_ms"], 2), round(r["t_solve_ms"], 2), round(r["t_eval_ms"], 2)]}
                        for r in recs],
     }
+    if not tp:
+        out["roofline"] = None      # no MINRES product was timed (every step solved by FETI-DP)
     print(json.dumps(out))
 
 

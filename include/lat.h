@@ -401,6 +401,11 @@ typedef struct {
     int32_t indefinite;   /* principal remaining blocks left indefinite after enrichment: 0 = shifted
                              to definiteness; 1 = inverted by pivoted LU, the interface block by its
                              Dirichlet preconditioner alone (see lat_feti_solve) */
+    int32_t coords;       /* the cells' coordinates delta^s in the local models: 1 = one-hot on the
+                             nearest of the first n_delta principal cells in snapshot space (needs R,
+                             nu, beta; lanes are then grouped by principal cell and each group's
+                             products are one GEMM); 0 = least squares over them (see lat_feti_solve) */
+    int32_t reserved;     /* 0 */
     double tol;           /* stop at ||res|| <= tol ||rhs|| (2-norms of the saddle-point system), > 0 */
 } lat_feti_opts;
 
@@ -431,9 +436,12 @@ typedef struct {
  * order): the inverse remaining block G_r = (K_RR^r)^-1 (a Cholesky factor and inverse per
  * principal cell, FP64), the primal harmonic extension -G_r K_RP^r, the local primal Schur
  * complement and the local dual Schur complement F_dd^r = (G_r)_dd with its inverse; cell s uses
- * sum_r delta_r^s (.)_r, delta^s the coordinates of its snapshot in the first n_delta principal
- * snapshots (R[:nd,:nd] delta = nu_s beta^s[:nd], from the greedy; alpha when nd = n_r or R is
- * NULL).  The assembled coarse problem is inverted in FP64 (LU); the interface block F^-1 is
+ * sum_r delta_r^s (.)_r.  delta^s (opts->coords): one-hot on the principal cell r < n_delta whose
+ * snapshot is nearest to the cell's, ||t_s - t_{s_r}||^2 = nu_s^2 + nu_{s_r}^2 - 2 nu_s
+ * sum_j beta_j^s R[j][r] (exact from the greedy's outputs, ties to the lowest r); or the
+ * least-squares coordinates of its snapshot in the first n_delta principal snapshots
+ * (R[:nd,:nd] delta = nu_s beta^s[:nd]; alpha when nd = n_r or R is NULL), whose combinations of
+ * inverses extrapolate and converge far worse in practice.  The assembled coarse problem is inverted in FP64 (LU); the interface block F^-1 is
  * `inner_it` PCG steps on B K~rom^-1 B^T with the Dirichlet preconditioner
  * B_D (sum_r delta_r (F_dd^r)^-1) B_D^T, B_D = (B B^T)^-1 B node by node.  A principal remaining
  * block that is not positive definite (Cholesky failure or a pivot <= 1e-12 of its diagonal entry)
@@ -476,8 +484,10 @@ typedef struct {
                                1 = ROM apply forming them on the fly (see lat_rom_solve) */
     int32_t tangent;        /* 0 = ROM tangent (the method), 1 = every cell's own full-rule tangent
                                (the standard method, for comparison; no greedy) */
-    int32_t precond;        /* tangent-solve preconditioner, as lat_rom_solve's precond */
-    int32_t reserved;       /* 0 */
+    int32_t precond;        /* tangent solve: 0 / 1 = lat_rom_solve's MINRES with its precond 0 / 1;
+                               2 = the inexact FETI-DP solve (lat_feti_solve, ROM tangent only), with
+                               MINRES (two levels) taking over a step it does not converge on */
+    int32_t feti_n_delta;   /* precond 2: lat_feti_opts.n_delta (0 = every principal cell) */
     double rb_tol;          /* greedy tolerance (Algorithm 1), > 0 */
     double newton_tol;      /* stop an increment at ||r|| / ||r(u_0)|| <= newton_tol, > 0 */
     double armijo_beta;     /* step reduction factor, in (0, 1) */
@@ -507,6 +517,12 @@ typedef struct {
     double t_product_us;    /* mean duration of one tangent product (the per-cell or ROM apply),
                                HIP events around up to 64 products of the solve, taken from the
                                9th product of each host batch on (0 when none was timed) */
+    int32_t solver;         /* 0 MINRES, 1 FETI-DP, 2 FETI-DP stopped short and MINRES solved */
+    int32_t feti_iters;     /* FETI-DP FGMRES iterations (solver 1, 2) */
+    int32_t feti_enrich;    /* FETI-DP enrichment level used */
+    int32_t reserved;
+    double feti_relres;     /* FETI-DP saddle-point relative residual at its exit */
+    double t_feti_setup_ms; /* FETI-DP setup (partition, principal factorisations, coarse problem) */
 } lat_newton_record;
 
 /* Load-stepped Newton-Raphson with Armijo backtracking (Sec. 2.2.5) on the ROM tangent.
@@ -517,8 +533,8 @@ typedef struct {
  * (may be NULL).  u [n_global][d] device, in: the initial state, out: the final state.
  * Residual r(u) = sum_s A^s f^{int,s} - (t/n_inc) f_ext, zero on prescribed components.
  * Each iteration: snapshots at u (opts->snap_rule) -> greedy (rb_tol, cap) -> principal tangents
- * -> tangent solve K~ du = -r (lat_rom_solve's method; its status goes to the record and a
- * solve stopped early still provides the direction) -> the smallest m <= max_backtrack with
+ * -> tangent solve K~ du = -r (lat_rom_solve's MINRES, or lat_feti_solve by opts->precond; its
+ * status goes to the record and a solve stopped early still provides the direction) -> the smallest m <= max_backtrack with
  * ||r(u + beta^m du)|| <= (1 - c beta^m) ||r(u)|| (a trial with J <= 0 anywhere fails) ->
  * u += beta^m du; the increment ends when ||r|| <= newton_tol ||r(u_0)||.
  * records: HOST array of max_records entries (may be NULL), one per Newton iteration in order;

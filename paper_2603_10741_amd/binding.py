@@ -34,7 +34,7 @@ class NewtonOpts(ctypes.Structure):
     _fields_ = [("n_inc", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
                 ("cap", ctypes.c_int32), ("cg_maxit", ctypes.c_int32), ("cg_check", ctypes.c_int32),
                 ("snap_rule", ctypes.c_int32), ("verbose", ctypes.c_int32), ("matvec", ctypes.c_int32),
-                ("tangent", ctypes.c_int32), ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tangent", ctypes.c_int32), ("precond", ctypes.c_int32), ("feti_n_delta", ctypes.c_int32),
                 ("rb_tol", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("armijo_beta", ctypes.c_double), ("armijo_c", ctypes.c_double),
                 ("cg_tol", ctypes.c_double)]
@@ -47,7 +47,9 @@ class NewtonRecord(ctypes.Structure):
                 ("cg_status", ctypes.c_int32), ("coarse", ctypes.c_int32), ("step", ctypes.c_double),
                 ("res_before", ctypes.c_double), ("res_after", ctypes.c_double), ("res0", ctypes.c_double),
                 ("rb_achieved", ctypes.c_double), ("cg_relres", ctypes.c_double), ("t_init_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double), ("t_eval_ms", ctypes.c_double), ("t_product_us", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("t_eval_ms", ctypes.c_double), ("t_product_us", ctypes.c_double),
+                ("solver", ctypes.c_int32), ("feti_iters", ctypes.c_int32), ("feti_enrich", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("feti_relres", ctypes.c_double), ("t_feti_setup_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -57,7 +59,8 @@ class FetiOpts(ctypes.Structure):
     """lat_feti_opts"""
     _fields_ = [("n_delta", ctypes.c_int32), ("enrich", ctypes.c_int32), ("max_enrich", ctypes.c_int32),
                 ("inner_it", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
-                ("materialize", ctypes.c_int32), ("indefinite", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("materialize", ctypes.c_int32), ("indefinite", ctypes.c_int32), ("coords", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class FetiInfo(ctypes.Structure):
@@ -482,10 +485,13 @@ class Plan:
                 "n_dual": int(counts[3])}
 
     def feti_solve(self, K, n_r, alpha, S, fixed, b, R=None, nu=None, beta=None, n_delta=0, enrich=0, max_enrich=3,
-                   inner_it=8, restart=60, maxit=600, tol=1e-8, materialize=True, indefinite=0, x=None):
+                   inner_it=8, restart=60, maxit=600, tol=1e-8, materialize=True, indefinite=0, coords=None, x=None):
         """K~ x = b on the free components by the inexact FETI-DP iteration (lat_feti_solve).
+        coords: 1 = nearest principal cell (the default when R, nu, beta are given), 0 = least squares.
         Returns (x, status, info dict); status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other
         codes raise."""
+        if coords is None:
+            coords = 1 if R is not None else 0
         n = max(self.nglobal, 1) * self.dim
         _need(b, n, torch.float64, "b")
         _need(fixed, n, torch.uint8, "fixed")
@@ -496,7 +502,7 @@ class Plan:
             _need(t, sz, torch.float64, nm)
         x = self._f64(n) if x is None else x
         o = FetiOpts(int(n_delta), int(enrich), int(max_enrich), int(inner_it), int(restart), int(maxit),
-                     int(bool(materialize)), int(indefinite), float(tol))
+                     int(bool(materialize)), int(indefinite), int(coords), 0, float(tol))
         inf = FetiInfo()
         st = _lib().lat_feti_solve(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(S), _ptr(R), _ptr(nu), _ptr(beta),
                                    _ptr(fixed), _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())
@@ -517,13 +523,14 @@ class Plan:
     def newton_solve(self, mu, lam, fixed, ubar, u, f_ext=None, n_inc=4, max_newton=30, max_backtrack=30, cap=None,
                      rb_tol=3e-4, newton_tol=1e-6, armijo_beta=0.5, armijo_c=1e-4, cg_tol=1e-10, cg_maxit=20000,
                      cg_check=32, snap_rule=RULE_FULL, max_records=1024, verbose=False, matvec=0,
-                     tangent=0, precond=1):
+                     tangent=0, precond=1, feti_n_delta=0):
         """Load-stepped Newton-Raphson with Armijo backtracking (lat_newton_solve); u is updated in
         place.  Returns (status, records); status is LAT_OK, LAT_E_NOCONV, LAT_E_INVERTED or
         LAT_E_NONFINITE, other codes raise."""
         o = NewtonOpts(int(n_inc), int(max_newton), int(max_backtrack), int(cap if cap is not None else self.cap),
                        int(cg_maxit), int(cg_check), int(snap_rule), int(bool(verbose)), int(matvec), int(tangent),
-                       int(precond), 0, float(rb_tol), float(newton_tol), float(armijo_beta), float(armijo_c),
+                       int(precond), int(feti_n_delta), float(rb_tol), float(newton_tol), float(armijo_beta),
+                       float(armijo_c),
                        float(cg_tol))
         recs = (NewtonRecord * max(int(max_records), 1))()
         nrec = ctypes.c_int32(0)

@@ -785,6 +785,80 @@ __global__ void k_delta(int64_t ld, int nd, int n_r, int cap, const int32_t *__r
     }
 }
 
+// one-hot coordinates: delta^s = e_r for the principal cell r < nd nearest to cell s in snapshot
+// space, ||t_s - t_{s_r}||^2 = nu_s^2 + nu_{s_r}^2 - 2 nu_s sum_{j <= r} beta_j^s R[j][r] (the greedy's
+// final residual of s is orthogonal to every basis vector); ties go to the lowest r
+__global__ void k_delta_nearest(int64_t ld, int nd, int cap, const int32_t *__restrict__ perm,
+                                const int32_t *__restrict__ S, const double *__restrict__ R,
+                                const double *__restrict__ nu, const double *__restrict__ beta,
+                                double *__restrict__ delta)
+{
+    const int64_t lane = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (lane >= ld) return;
+    const int cell = perm[lane];
+    double *dl = delta + lane * nd;
+    for (int r = 0; r < nd; ++r) dl[r] = 0.0;
+    if (cell < 0) return;
+    const double ns = nu[cell];
+    int best = 0;
+    double bd = INFINITY;
+    for (int r = 0; r < nd; ++r) {
+        double dot = 0.0;
+        for (int j = 0; j <= r; ++j) dot = fma(beta[(int64_t)cell * cap + j], R[(int64_t)j * cap + r], dot);
+        const double nr = nu[S[r]];
+        const double d2 = ns * ns + nr * nr - 2.0 * ns * dot;
+        if (d2 < bd) { bd = d2; best = r; }
+    }
+    dl[best] = 1.0;
+}
+
+// lane gather / scatter of a local block vector [rows][ld] into the principal-cell order:
+// xg[j ld + k] = live ? x[j ld + order[k]] : 0 (k < nv), 0 past nv; x[j ld + order[k]] = xg[j ld + k]
+__global__ void k_gather_lanes(int64_t rows, int64_t ld, int64_t nv, const int32_t *__restrict__ order,
+                               const uint8_t *__restrict__ live, const double *__restrict__ x, double *__restrict__ xg)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= rows * ld) return;
+    const int64_t k = t % ld, j = t / ld;
+    double v = 0.0;
+    if (k < nv) {
+        const int64_t src = j * ld + order[k];
+        v = (!live || live[src]) ? x[src] : 0.0;
+    }
+    xg[t] = v;
+}
+
+__global__ void k_scatter_lanes(int64_t rows, int64_t ld, int64_t nv, const int32_t *__restrict__ order,
+                                const double *__restrict__ xg, double *__restrict__ x)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= rows * ld) return;
+    const int64_t k = t % ld, j = t / ld;
+    if (k < nv) x[j * ld + order[k]] = xg[t];
+}
+
+// local coarse matrices of the one-hot models: C[lane] = S_{sel[lane]} (zero for padding lanes)
+__global__ void k_select_spp(int64_t np2, int64_t ld, const int32_t *__restrict__ sel, const double *__restrict__ Spp,
+                             double *__restrict__ C)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= np2 * ld) return;
+    const int64_t lane = t / np2, e = t % np2;
+    const int r = sel[lane];
+    C[t] = r >= 0 ? Spp[(int64_t)r * np2 + e] : 0.0;
+}
+
+// principal cell of each lane under one-hot coordinates (-1 for padding lanes)
+__global__ void k_onehot_sel(int64_t ld, int nd, const double *__restrict__ delta, int32_t *__restrict__ sel)
+{
+    const int64_t lane = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (lane >= ld) return;
+    int r = -1;
+    for (int k = 0; k < nd; ++k)
+        if (delta[lane * nd + k] != 0.0) r = k;
+    sel[lane] = r;
+}
+
 // assembled coarse matrix (column-major, n = nPg d): row thread (G, i) sums its owners' local
 // matrices C[lane][(p2 d + j) nP + p1 d + i] in ascending cell id; identity on prescribed rows
 __global__ void k_coarse_asm(int d, int nPn, int64_t ld, int64_t nPg, const int32_t *__restrict__ pg_off,
@@ -997,6 +1071,13 @@ struct Feti {
     int n_shift = 0;        // principal remaining blocks that are not positive definite
     double max_shift = 0.0; // largest diagonal shift (indef_mode 0)
     int indef_mode = 0;     // 0: shift to definiteness; 1: pivoted-LU inverses, interface by its Dirichlet preconditioner
+    int coords = 0;         // 0: least-squares coordinates; 1: nearest principal cell
+    // one-hot coordinates: lanes grouped by principal cell (order[off[r] .. off[r+1]) use r)
+    bool onehot = false;
+    int32_t *order = nullptr;
+    std::vector<int64_t> off;
+    int64_t nv = 0;          // lanes with a principal cell (padding lanes excluded)
+    double *Xg = nullptr, *Yg = nullptr;
 };
 
 // GEMM wrapper (column-major, FP64)
@@ -1066,8 +1147,12 @@ lat_status op_apply(Feti &f, const double *w, double *out)
 // in f.T1 layout, h_P = base + assembled, u_P = Sc^-1 h_P, el = gathered u_P
 lat_status coarse_part(Feti &f, const double *base)
 {
-    hipLaunchKernelGGL(k_combine_delta, dim3(blocks(f.nPr * f.ld)), dim3(NB), 0, f.s, f.nPr, f.ld, f.nd, f.delta, f.T1,
-                       f.hl);
+    if (f.onehot)   // the per-group products were scattered back into lane order already
+        hipLaunchKernelGGL(k_scatter_lanes, dim3(blocks(f.nPr * f.ld)), dim3(NB), 0, f.s, f.nPr, f.ld, f.nv, f.order,
+                           (const double *)f.T1, f.hl);
+    else
+        hipLaunchKernelGGL(k_combine_delta, dim3(blocks(f.nPr * f.ld)), dim3(NB), 0, f.s, f.nPr, f.ld, f.nd, f.delta,
+                           f.T1, f.hl);
     hipLaunchKernelGGL(k_assemble_P, dim3(blocks(f.pt.nPg)), dim3(NB), 0, f.s, f.d, f.ld, f.pt.nPg, f.pd.pg_off,
                        f.pd.pg_lane, f.pd.pg_p, f.liveP, f.hl, base, f.hP);
     LAT_LAUNCH_CHECK();
@@ -1082,9 +1167,47 @@ lat_status coarse_part(Feti &f, const double *base)
     return LAT_OK;
 }
 
+// one-hot models: C_g[off_r .., :] (op) = X_g[off_r .., :] M_r (op(M_r)) for every principal cell r,
+// lanes in group order (column-major [ld x k] blocks, M_r [k x n] or its transpose)
+lat_status grouped(Feti &f, rocblas_operation tm, int64_t n, int64_t k, const double *Xg, const double *M,
+                   int64_t ldm, int64_t strideM, double beta, double *Cg)
+{
+    for (int r = 0; r < f.nd; ++r) {
+        const int64_t m = f.off[(size_t)r + 1] - f.off[(size_t)r];
+        if (m == 0) continue;
+        FCHK(gemm(f, rocblas_operation_none, tm, m, n, k, 1.0, Xg + f.off[(size_t)r], f.ld, M + (int64_t)r * strideM, ldm,
+                  beta, Cg + f.off[(size_t)r], f.ld));
+    }
+    return LAT_OK;
+}
+
+// K~rom^-1 with one-hot models: every cell's local operators are its principal cell's
+lat_status krom_onehot(Feti &f, const double *gR, const double *gP, double *zR, double *zP)
+{
+    const int64_t nR = f.nRr, ld = f.ld, nP = f.nPr;
+    hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nR * ld)), dim3(NB), 0, f.s, nR, ld, f.nv, f.order, f.liveR, gR, f.Xg);
+    LAT_LAUNCH_CHECK();
+    FCHK(grouped(f, rocblas_operation_none, nR, nR, f.Xg, f.G, nR, nR * nR, 0.0, f.Yg));
+    FCHK(grouped(f, rocblas_operation_none, nP, nR, f.Xg, f.Phi, nR, nR * nP, 0.0, f.T1));
+    FCHK(coarse_part(f, gP));
+    hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nP * ld)), dim3(NB), 0, f.s, nP, ld, f.nv, f.order,
+                       (const uint8_t *)nullptr, (const double *)f.el, f.As);
+    LAT_LAUNCH_CHECK();
+    FCHK(grouped(f, rocblas_operation_transpose, nR, nP, f.As, f.Phi, nR, nR * nP, 1.0, f.Yg));
+    hipLaunchKernelGGL(k_ffill, dim3(blocks(nR * ld)), dim3(NB), 0, f.s, nR * ld, 0.0, zR);
+    hipLaunchKernelGGL(k_scatter_lanes, dim3(blocks(nR * ld)), dim3(NB), 0, f.s, nR, ld, f.nv, f.order,
+                       (const double *)f.Yg, zR);
+    hipLaunchKernelGGL(k_identity_rows, dim3(blocks(nR * ld)), dim3(NB), 0, f.s, nR * ld, f.liveR, gR, zR);
+    if (zP != f.uP)
+        hipLaunchKernelGGL(k_copy, dim3(blocks(f.nPgd)), dim3(NB), 0, f.s, f.nPgd, (const double *)f.uP, zP);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
 // (zR, zP) = K~rom^-1 (gR, gP); identity on rows that do not exist
 lat_status krom(Feti &f, const double *gR, const double *gP, double *zR, double *zP)
 {
+    if (f.onehot) return krom_onehot(f, gR, gP, zR, zP);
     const int64_t nR = f.nRr, ld = f.ld, nd = f.nd, nP = f.nPr;
     hipLaunchKernelGGL(k_scale_stack, dim3(blocks(nR * ld)), dim3(NB), 0, f.s, nR, ld, f.nd, f.delta, f.liveR, gR,
                        f.xm, f.As);
@@ -1118,6 +1241,27 @@ lat_status fdual(Feti &f, const double *lam, double *out)
                        f.pd.set_m0, f.pd.mem_lane, f.pd.mem_dn, f.liveL, f.pd.bd, 0, lam, f.qd);
     hipLaunchKernelGGL(k_dir_bt, dim3(blocks(f.pt.ndir)), dim3(NB), 0, f.s, f.d, f.pt.ndir, ld, f.Lint, f.pd.dir_lane,
                        f.pd.dir_dn, f.pd.dir_i, lam, f.qd);
+    if (f.onehot) {
+        hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nv, f.order, f.liveD,
+                           (const double *)f.qd, f.Xg);
+        LAT_LAUNCH_CHECK();
+        FCHK(grouped(f, rocblas_operation_none, nD, nD, f.Xg, f.Fdd, nD, nD * nD, 0.0, f.Yg));
+        FCHK(grouped(f, rocblas_operation_none, nP, nD, f.Xg, f.Phid, nD, nD * nP, 0.0, f.T1));
+        FCHK(coarse_part(f, nullptr));
+        hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nP * ld)), dim3(NB), 0, f.s, nP, ld, f.nv, f.order,
+                           (const uint8_t *)nullptr, (const double *)f.el, f.As);
+        LAT_LAUNCH_CHECK();
+        FCHK(grouped(f, rocblas_operation_transpose, nD, nP, f.As, f.Phid, nD, nD * nP, 1.0, f.Yg));
+        hipLaunchKernelGGL(k_ffill, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD * ld, 0.0, f.vd);
+        hipLaunchKernelGGL(k_scatter_lanes, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nv, f.order,
+                           (const double *)f.Yg, f.vd);
+        hipLaunchKernelGGL(k_b_dual, dim3(blocks(f.pt.nsets)), dim3(NB), 0, f.s, f.d, f.pt.nsets, ld, f.pd.set_off,
+                           f.pd.set_m0, f.pd.mem_lane, f.pd.mem_dn, f.liveL, f.pd.bd, 0, (const double *)f.vd, lam, out);
+        hipLaunchKernelGGL(k_dir_b, dim3(blocks(f.pt.ndir)), dim3(NB), 0, f.s, f.d, f.pt.ndir, ld, f.Lint, f.pd.dir_lane,
+                           f.pd.dir_dn, f.pd.dir_i, (const double *)f.vd, out);
+        LAT_LAUNCH_CHECK();
+        return LAT_OK;
+    }
     hipLaunchKernelGGL(k_scale_stack, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nd, f.delta, f.liveD, f.qd,
                        f.xm, f.As);
     LAT_LAUNCH_CHECK();
@@ -1148,11 +1292,22 @@ lat_status dirichlet(Feti &f, const double *r, double *out)
                        f.pd.set_m0, f.pd.mem_lane, f.pd.mem_dn, f.liveL, f.pd.bd, 1, r, f.qd);
     hipLaunchKernelGGL(k_dir_bt, dim3(blocks(f.pt.ndir)), dim3(NB), 0, f.s, f.d, f.pt.ndir, ld, f.Lint, f.pd.dir_lane,
                        f.pd.dir_dn, f.pd.dir_i, r, f.qd);
-    hipLaunchKernelGGL(k_scale_stack, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nd, f.delta, f.liveD, f.qd,
-                       (double *)nullptr, f.As);
-    LAT_LAUNCH_CHECK();
-    FCHK(gemm(f, rocblas_operation_none, rocblas_operation_transpose, ld, nD, nd * nD, 1.0, f.As, ld, f.Sdd, nD, 0.0,
-              f.vd, ld));
+    if (f.onehot) {
+        hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nv, f.order, f.liveD,
+                           (const double *)f.qd, f.Xg);
+        LAT_LAUNCH_CHECK();
+        FCHK(grouped(f, rocblas_operation_none, nD, nD, f.Xg, f.Sdd, nD, nD * nD, 0.0, f.Yg));
+        hipLaunchKernelGGL(k_ffill, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD * ld, 0.0, f.vd);
+        hipLaunchKernelGGL(k_scatter_lanes, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nv, f.order,
+                           (const double *)f.Yg, f.vd);
+        LAT_LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL(k_scale_stack, dim3(blocks(nD * ld)), dim3(NB), 0, f.s, nD, ld, f.nd, f.delta, f.liveD, f.qd,
+                           (double *)nullptr, f.As);
+        LAT_LAUNCH_CHECK();
+        FCHK(gemm(f, rocblas_operation_none, rocblas_operation_transpose, ld, nD, nd * nD, 1.0, f.As, ld, f.Sdd, nD, 0.0,
+                  f.vd, ld));
+    }
     hipLaunchKernelGGL(k_b_dual, dim3(blocks(f.pt.nsets)), dim3(NB), 0, f.s, f.d, f.pt.nsets, ld, f.pd.set_off,
                        f.pd.set_m0, f.pd.mem_lane, f.pd.mem_dn, f.liveL, f.pd.bd, 1, (const double *)f.vd, r, out);
     hipLaunchKernelGGL(k_dir_b, dim3(blocks(f.pt.ndir)), dim3(NB), 0, f.s, f.d, f.pt.ndir, ld, f.Lint, f.pd.dir_lane,
@@ -1421,9 +1576,35 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
     }
     // coordinates of every cell
     FCHK(ar.get(&f.delta, f.ld * nd));
-    hipLaunchKernelGGL(k_delta, dim3(blocks(f.ld)), dim3(NB), 0, f.s, f.ld, nd, f.n_r, P->cap, P->perm, f.alpha, R, nu,
-                       beta, f.delta);
+    if (f.coords == 1)
+        hipLaunchKernelGGL(k_delta_nearest, dim3(blocks(f.ld)), dim3(NB), 0, f.s, f.ld, nd, P->cap, P->perm, S, R, nu,
+                           beta, f.delta);
+    else
+        hipLaunchKernelGGL(k_delta, dim3(blocks(f.ld)), dim3(NB), 0, f.s, f.ld, nd, f.n_r, P->cap, P->perm, f.alpha, R,
+                           nu, beta, f.delta);
     LAT_LAUNCH_CHECK();
+    int32_t *sel = nullptr;
+    FCHK(ar.get(&sel, f.ld));
+    f.onehot = f.coords == 1;
+    if (f.onehot) {
+        // lanes grouped by their principal cell (ascending lane within a group)
+        hipLaunchKernelGGL(k_onehot_sel, dim3(blocks(f.ld)), dim3(NB), 0, f.s, f.ld, nd, (const double *)f.delta, sel);
+        LAT_LAUNCH_CHECK();
+        std::vector<int32_t> hsel((size_t)f.ld);
+        LAT_HIP(hipMemcpyAsync(hsel.data(), sel, (size_t)f.ld * 4, hipMemcpyDeviceToHost, f.s));
+        LAT_HIP(hipStreamSynchronize(f.s));
+        f.off.assign((size_t)nd + 1, 0);
+        for (int32_t r : hsel)
+            if (r >= 0) ++f.off[(size_t)r + 1];
+        for (int r = 0; r < nd; ++r) f.off[(size_t)r + 1] += f.off[(size_t)r];
+        f.nv = f.off[(size_t)nd];
+        std::vector<int32_t> ord((size_t)std::max<int64_t>(f.nv, 1), 0);
+        std::vector<int64_t> fill(f.off.begin(), f.off.end() - 1);
+        for (int64_t l = 0; l < f.ld; ++l)
+            if (hsel[(size_t)l] >= 0) ord[(size_t)fill[(size_t)hsel[(size_t)l]]++] = (int32_t)l;
+        FCHK(ar.put(&f.order, ord, f.s));
+        LAT_HIP(hipStreamSynchronize(f.s));
+    }
     // masks
     FCHK(ar.get(&f.liveR, f.nRr * f.ld)); FCHK(ar.get(&f.liveP, f.nPgd)); FCHK(ar.get(&f.liveL, f.L));
     FCHK(ar.get(&f.liveD, f.nDr * f.ld));
@@ -1439,8 +1620,14 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
     if (f.nPgd > 0) {
         double *C = nullptr;
         FCHK(ar.get(&C, f.nPr * f.nPr * f.ld));
-        FCHK(gemm(f, rocblas_operation_none, rocblas_operation_none, f.nPr * f.nPr, f.ld, nd, 1.0, f.Spp, f.nPr * f.nPr,
-                  f.delta, nd, 0.0, C, f.nPr * f.nPr));
+        if (f.onehot) {
+            hipLaunchKernelGGL(k_select_spp, dim3(blocks(f.nPr * f.nPr * f.ld)), dim3(NB), 0, f.s, f.nPr * f.nPr, f.ld,
+                               (const int32_t *)sel, (const double *)f.Spp, C);
+            LAT_LAUNCH_CHECK();
+        } else {
+            FCHK(gemm(f, rocblas_operation_none, rocblas_operation_none, f.nPr * f.nPr, f.ld, nd, 1.0, f.Spp,
+                      f.nPr * f.nPr, f.delta, nd, 0.0, C, f.nPr * f.nPr));
+        }
         hipLaunchKernelGGL(k_ffill, dim3(blocks(f.nPgd * f.nPgd)), dim3(NB), 0, f.s, f.nPgd * f.nPgd, 0.0, f.Sc);
         hipLaunchKernelGGL(k_coarse_asm, dim3(blocks(f.nPgd)), dim3(NB), 0, f.s, d, pt.nPn, f.ld, pt.nPg, f.pd.pg_off,
                            f.pd.pg_lane, f.pd.pg_p, f.pd.prim_g, (const uint8_t *)f.liveP, (const double *)C, f.Sc);
@@ -1456,7 +1643,8 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
     }
     // scratch of the applies
     const int64_t stack_rows = std::max<int64_t>({f.nRr, f.nDr, f.nPr, 1});
-    FCHK(ar.get(&f.As, stack_rows * f.ld * nd));
+    FCHK(ar.get(&f.As, stack_rows * f.ld * (f.onehot ? 1 : nd)));
+    if (f.onehot) { FCHK(ar.get(&f.Xg, stack_rows * f.ld)); FCHK(ar.get(&f.Yg, stack_rows * f.ld)); }
     FCHK(ar.get(&f.xm, stack_rows * f.ld));
     FCHK(ar.get(&f.T1, f.nPr * nd * f.ld));
     FCHK(ar.get(&f.hl, f.nPr * f.ld)); FCHK(ar.get(&f.el, f.nPr * f.ld));
@@ -1507,7 +1695,7 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
     if (n_r < 1 || n_r > P->cap) return LAT_E_SHAPE;
     if (opts->enrich < 0 || opts->max_enrich < opts->enrich || opts->inner_it < 0 || opts->restart < 1 ||
         opts->restart > 512 || opts->maxit < 1 || !(opts->tol > 0.0) || opts->n_delta < 0 || opts->indefinite < 0 ||
-        opts->indefinite > 1)
+        opts->indefinite > 1 || opts->coords < 0 || opts->coords > 1 || (opts->coords == 1 && !R))
         return LAT_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     Feti f;
@@ -1515,6 +1703,7 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
     f.nd = opts->n_delta == 0 ? n_r : std::min<int>(opts->n_delta, n_r);
     f.inner_it = opts->inner_it;
     f.indef_mode = opts->indefinite;
+    f.coords = opts->coords;
     f.h = feti_handle();
     if (!f.h || rocblas_set_stream(f.h, stream) != rocblas_status_success) return LAT_E_DEVICE;
     FArena ar;

@@ -1180,7 +1180,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     if (!P || !mu || !lam || !fixed || !ubar || !o || !u) return LAT_E_ARG;
     if (o->n_inc < 1 || o->max_newton < 1 || o->max_backtrack < 0 || o->cap < 1 || o->cap > P->cap ||
         o->cg_maxit < 1 || o->cg_check < 1 || (o->matvec != 0 && o->matvec != 1) ||
-        (o->tangent != 0 && o->tangent != 1) || (o->precond != 0 && o->precond != 1) ||
+        (o->tangent != 0 && o->tangent != 1) || o->precond < 0 || o->precond > 2 ||
+        (o->precond == 2 && o->tangent == 1) || o->feti_n_delta < 0 ||
         (o->snap_rule != LAT_RULE_FULL && o->snap_rule != LAT_RULE_REDUCED && o->snap_rule != LAT_RULE_MATERIAL &&
          o->snap_rule != LAT_RULE_SAMPLED) ||
         !(o->rb_tol > 0.0) || !(o->newton_tol > 0.0) || !(o->armijo_beta > 0.0 && o->armijo_beta < 1.0) ||
@@ -1193,8 +1194,9 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     Arena ar;
     MrWork w;
     const bool full = o->tangent == 1;   // each cell's own tangent (the standard method)
-    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0, s, o->precond == 1, fixed));
-    double *u_try, *du, *rhs, *r, *r_try, *fasm, *f_cil, *snap, *K, *alpha, *R, *scal;
+    NCHK(mr_alloc(P, ar, w, full || o->matvec == 0, s, o->precond >= 1, fixed));
+    const bool feti = o->precond == 2;
+    double *u_try, *du, *rhs, *r, *r_try, *fasm, *f_cil, *snap, *K, *alpha, *R, *scal, *beta = nullptr, *nu = nullptr;
     int32_t *S, *nr_d, *st_d, *gst_d;
     NCHK(ar.get(&u_try, n)); NCHK(ar.get(&du, n)); NCHK(ar.get(&rhs, n)); NCHK(ar.get(&r, n));
     NCHK(ar.get(&r_try, n)); NCHK(ar.get(&fasm, n));
@@ -1204,6 +1206,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
     NCHK(ar.get(&alpha, P->ncells * P->cap));
     NCHK(ar.get(&R, (int64_t)P->cap * P->cap));
     NCHK(ar.get(&scal, 2));
+    if (feti) { NCHK(ar.get(&beta, P->ncells * P->cap)); NCHK(ar.get(&nu, P->ncells)); }
     NCHK(ar.get(&S, P->cap)); NCHK(ar.get(&nr_d, 1)); NCHK(ar.get(&st_d, 2)); NCHK(ar.get(&gst_d, 2));
     const unsigned nbv = w.nbv;
     const lat_rule rule = (lat_rule)o->snap_rule;
@@ -1253,8 +1256,8 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
                 NCHK(lat_status_reset(gst_d, s));
                 // the greedy reads only the rows the snapshot rule fills
                 const int64_t rows = lat_snapshot_rows(P, rule);
-                NCHK(lat_select_principal_rows(P, snap, rows, o->rb_tol, o->cap, S, nr_d, alpha, nullptr, nullptr, R,
-                                               nullptr, scal + 1, gst_d, nullptr, 0, s));
+                NCHK(lat_select_principal_rows(P, snap, rows, o->rb_tol, o->cap, S, nr_d, alpha, beta, nu, R, nullptr,
+                                               scal + 1, gst_d, nullptr, 0, s));
                 int32_t hg[2] = {0, 0};
                 double ach = 0.0;
                 LAT_HIP(hipMemcpyAsync(&hnr, nr_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1275,10 +1278,34 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             LAT_LAUNCH_CHECK();
             int cgit = 0;
             double cgrel = 0.0;
-            const lat_status cst = mr_run(P, w, K, hnr, alpha, w.ops, fixed, rhs, du, o->cg_tol, o->cg_maxit,
-                                          o->cg_check, &cgit, &cgrel, s, &rec.t_product_us);
-            if (cst != LAT_OK && cst != LAT_E_NOCONV && cst != LAT_E_SINGULAR) return cst;
-            rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst; rec.coarse = w.coarse_on;
+            lat_status cst = LAT_E_NOCONV;
+            bool need_mr = true;
+            if (feti && hnr > 0) {
+                // inexact FETI-DP (Sec. 3.3); a solve that stops short (an indefinite tangent) hands
+                // the step to MINRES
+                lat_feti_opts fo{};
+                fo.n_delta = o->feti_n_delta; fo.enrich = 0; fo.max_enrich = 3; fo.inner_it = 8; fo.restart = 60;
+                fo.maxit = std::min(o->cg_maxit, 600); fo.materialize = w.ops != nullptr; fo.indefinite = 0;
+                fo.coords = 1;
+                fo.tol = o->cg_tol;
+                lat_feti_info fi{};
+                const lat_status fst = lat_feti_solve(P, K, hnr, alpha, S, R, nu, beta, fixed, rhs, du, &fo, &fi, s);
+                if (fst != LAT_OK && fst != LAT_E_NOCONV && fst != LAT_E_SINGULAR) return fst;
+                rec.solver = 1; rec.feti_iters = fi.iters; rec.feti_relres = fi.relres;
+                rec.feti_enrich = fi.enrich; rec.t_feti_setup_ms = fi.t_setup_ms;
+                if (fst == LAT_OK) {
+                    need_mr = false;
+                    cst = LAT_OK; cgit = fi.iters; cgrel = fi.relres;
+                } else {
+                    rec.solver = 2;
+                }
+            }
+            if (need_mr) {
+                cst = mr_run(P, w, K, hnr, alpha, w.ops, fixed, rhs, du, o->cg_tol, o->cg_maxit, o->cg_check, &cgit,
+                             &cgrel, s, &rec.t_product_us);
+                if (cst != LAT_OK && cst != LAT_E_NOCONV && cst != LAT_E_SINGULAR) return cst;
+            }
+            rec.cg_iters = cgit; rec.cg_relres = cgrel; rec.cg_status = cst; rec.coarse = need_mr && w.coarse_on;
             rec.t_solve_ms = ms_since(t0);
             // Armijo backtracking on ||r||
             t0 = std::chrono::steady_clock::now();
@@ -1297,10 +1324,10 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
             if (records && nrec < max_records) records[nrec] = rec;
             ++nrec;
             if (o->verbose) {
-                std::fprintf(stderr, "newton inc %d it %d: n_r %d, solve %d its (status %d, coarse %d), m %d, "
-                             "|r|/|r0| %.3e, ms init %.1f solve %.1f eval %.1f\n", t, it, rec.n_r, rec.cg_iters,
-                             rec.cg_status, rec.coarse, rec.backtracks, (ok ? rt : rn) / r0, rec.t_init_ms,
-                             rec.t_solve_ms, rec.t_eval_ms);
+                std::fprintf(stderr, "newton inc %d it %d: n_r %d, solve %d its (status %d, coarse %d, solver %d, "
+                             "feti %d its), m %d, |r|/|r0| %.3e, ms init %.1f solve %.1f eval %.1f\n", t, it, rec.n_r,
+                             rec.cg_iters, rec.cg_status, rec.coarse, rec.solver, rec.feti_iters, rec.backtracks,
+                             (ok ? rt : rn) / r0, rec.t_init_ms, rec.t_solve_ms, rec.t_eval_ms);
                 std::fflush(stderr);
             }
             if (!ok) { result = LAT_E_NOCONV; break; }

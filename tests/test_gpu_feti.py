@@ -104,8 +104,8 @@ def test_partition_matches_oracle_3d(idx, sub, level):
     assert np.array_equal(p["mult"], o["mult"])
 
 
-@pytest.mark.parametrize("n_delta", [0, 4])
-def test_solve_matches_direct_solve(graded, n_delta):
+@pytest.mark.parametrize("n_delta,coords", [(0, 1), (4, 1), (0, 0), (4, 0)])
+def test_solve_matches_direct_solve(graded, n_delta, coords):
     nc = graded
     cfg = nc.cfg
     u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
@@ -114,19 +114,20 @@ def test_solve_matches_direct_solve(graded, n_delta):
     b = rng.standard_normal((nc.P.nglobal, cfg.dim))
     b_t = torch.from_numpy(b).to(nc.dev)
     x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"], beta=g["beta"],
-                                  n_delta=n_delta, tol=1e-11, maxit=400)
-    print(f"[feti] n_r {n_r} n_delta {info['n_delta']}: {info}", flush=True)
+                                  n_delta=n_delta, coords=coords, tol=1e-11, maxit=400)
+    print(f"[feti] n_r {n_r} n_delta {info['n_delta']} coords {coords}: {info}", flush=True)
     assert st == nc.B.LAT_OK and info["relres"] <= 1e-11
     assert info["n_delta"] == (n_r if n_delta == 0 else min(n_delta, n_r))
     assert 0 < info["iters"] <= 200
     _check_solution(nc, Ko, b, x, _direct(nc, Ko, b))
     # a second solve gives the same bits (fixed-order reductions, rocBLAS without atomics)
     x2, _, info2 = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"], beta=g["beta"],
-                                   n_delta=n_delta, tol=1e-11, maxit=400)
+                                   n_delta=n_delta, coords=coords, tol=1e-11, maxit=400)
     assert info2["iters"] == info["iters"] and torch.equal(x, x2)
     # the interface block by its Dirichlet preconditioner alone still converges (more iterations)
     x3, st3, info3 = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"],
-                                     beta=g["beta"], n_delta=n_delta, inner_it=0, tol=1e-11, maxit=800)
+                                     beta=g["beta"], n_delta=n_delta, coords=coords, inner_it=0, tol=1e-11,
+                                     maxit=800)
     assert st3 == nc.B.LAT_OK
     _check_solution(nc, Ko, b, x3, _direct(nc, Ko, b))
 
