@@ -322,7 +322,8 @@ def main():
                     help="--newton: ROM tangent products from stencils formed once per iteration, or ROM applies")
     ap.add_argument("--precond", choices=["two-level", "diag", "feti"], default="two-level",
                     help="--newton: tangent solve (MINRES two-level / diagonal, or the inexact FETI-DP solve)")
-    ap.add_argument("--feti-n-delta", type=int, default=8, help="--newton --precond feti: principal cells per local model")
+    ap.add_argument("--feti-n-delta", type=int, default=0,
+                    help="--newton --precond feti: principal cells the local models choose from (0 = all)")
     ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
                     help="--newton: ROM tangent, or every cell's own tangent (the standard method)")
     args = ap.parse_args()

@@ -837,6 +837,71 @@ __global__ void k_scatter_lanes(int64_t rows, int64_t ld, int64_t nv, const int3
     if (k < nv) x[j * ld + order[k]] = xg[t];
 }
 
+// Grouped product for the one-hot models, one launch for every principal cell:
+//   C[k, n] = beta C[k, n] + sum_j X[k, j] op(M_r)[j, n]   for the lanes k of group r,
+// X, C column-major [ld x ...] in group order, op(M_r) = M_r (K x N, ldm) or M_r^T (M_r N x K).
+// A workgroup of 256 threads computes a 64-lane x 64-column tile of one group (tiles listed in
+// `tiles` as (group, first lane, end lane)); K is staged through LDS 32 at a time, each thread
+// accumulates a 4 x 4 block in FP64.  The principal block is read once per 64 lanes of its group.
+constexpr int GT = 64, GK = 32;
+constexpr int64_t GBIG = 192;   // groups this large go to rocBLAS (matrix-core GEMMs)
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_grouped_gemm(int64_t ld, int64_t N, int64_t K, const int32_t *__restrict__ tiles,
+                                                      const double *__restrict__ X, const double *__restrict__ M,
+                                                      int64_t ldm, int64_t strideM, double beta, double *__restrict__ C)
+{
+    __shared__ double xs[GK][GT + 1];
+    __shared__ double ms[GK][GT + 1];
+    const int r = tiles[3 * blockIdx.y], k0 = tiles[3 * blockIdx.y + 1], k1 = tiles[3 * blockIdx.y + 2];
+    const int64_t n0 = (int64_t)blockIdx.x * GT;
+    const double *Mr = M + (int64_t)r * strideM;
+    const int t = threadIdx.x;
+    const int tr = (t % 16) * 4, tc = (t / 16) * 4;     // this thread's 4 x 4 block
+    double acc[4][4] = {};
+    for (int64_t j0 = 0; j0 < K; j0 += GK) {
+        // X tile [GK][GT]: lanes fastest (coalesced)
+        for (int e = t; e < GK * GT; e += 256) {
+            const int kk = e / GT, row = e % GT;
+            const int64_t j = j0 + kk, k = k0 + row;
+            xs[kk][row] = (j < K && k < k1) ? X[j * ld + k] : 0.0;
+        }
+        // op(M) tile [GK][GT]
+        for (int e = t; e < GK * GT; e += 256) {
+            int kk, c;
+            if (TRANS) { kk = e / GT; c = e % GT; }      // M[(j) ldm + n]: n fastest
+            else { c = e / GK; kk = e % GK; }             // M[(n) ldm + j]: j fastest
+            const int64_t j = j0 + kk, n = n0 + c;
+            double v = 0.0;
+            if (j < K && n < N) v = TRANS ? Mr[j * ldm + n] : Mr[n * ldm + j];
+            ms[kk][c] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < GK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { a[u] = xs[kk][tr + u]; b[u] = ms[kk][tc + u]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t n = n0 + tc + v;
+        if (n >= N) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + tr + u;
+            if (k >= k1) continue;
+            const int64_t idx = n * ld + k;
+            C[idx] = beta == 0.0 ? acc[u][v] : fma(beta, C[idx], acc[u][v]);
+        }
+    }
+}
+
 // local coarse matrices of the one-hot models: C[lane] = S_{sel[lane]} (zero for padding lanes)
 __global__ void k_select_spp(int64_t np2, int64_t ld, const int32_t *__restrict__ sel, const double *__restrict__ Spp,
                              double *__restrict__ C)
@@ -1075,6 +1140,9 @@ struct Feti {
     // one-hot coordinates: lanes grouped by principal cell (order[off[r] .. off[r+1]) use r)
     bool onehot = false;
     int32_t *order = nullptr;
+    int32_t *tiles = nullptr;       // (group, first lane, end lane) per 64-lane tile of the small groups
+    int64_t ntiles = 0;
+    std::vector<int> big;           // groups of at least GBIG lanes: one rocBLAS GEMM each
     std::vector<int64_t> off;
     int64_t nv = 0;          // lanes with a principal cell (padding lanes excluded)
     double *Xg = nullptr, *Yg = nullptr;
@@ -1172,12 +1240,21 @@ lat_status coarse_part(Feti &f, const double *base)
 lat_status grouped(Feti &f, rocblas_operation tm, int64_t n, int64_t k, const double *Xg, const double *M,
                    int64_t ldm, int64_t strideM, double beta, double *Cg)
 {
-    for (int r = 0; r < f.nd; ++r) {
+    if (n == 0) return LAT_OK;
+    for (int r : f.big) {
         const int64_t m = f.off[(size_t)r + 1] - f.off[(size_t)r];
-        if (m == 0) continue;
         FCHK(gemm(f, rocblas_operation_none, tm, m, n, k, 1.0, Xg + f.off[(size_t)r], f.ld, M + (int64_t)r * strideM, ldm,
                   beta, Cg + f.off[(size_t)r], f.ld));
     }
+    if (f.ntiles == 0) return LAT_OK;
+    const dim3 grid((unsigned)lat_cdiv(n, GT), (unsigned)f.ntiles);
+    if (tm == rocblas_operation_none)
+        hipLaunchKernelGGL(k_grouped_gemm<false>, grid, dim3(256), 0, f.s, f.ld, n, k, (const int32_t *)f.tiles, Xg, M,
+                           ldm, strideM, beta, Cg);
+    else
+        hipLaunchKernelGGL(k_grouped_gemm<true>, grid, dim3(256), 0, f.s, f.ld, n, k, (const int32_t *)f.tiles, Xg, M,
+                           ldm, strideM, beta, Cg);
+    LAT_LAUNCH_CHECK();
     return LAT_OK;
 }
 
@@ -1603,6 +1680,18 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
         for (int64_t l = 0; l < f.ld; ++l)
             if (hsel[(size_t)l] >= 0) ord[(size_t)fill[(size_t)hsel[(size_t)l]]++] = (int32_t)l;
         FCHK(ar.put(&f.order, ord, f.s));
+        std::vector<int32_t> tl;
+        f.big.clear();
+        for (int r = 0; r < nd; ++r) {
+            if (f.off[(size_t)r + 1] - f.off[(size_t)r] >= GBIG) { f.big.push_back(r); continue; }
+            for (int64_t k0 = f.off[(size_t)r]; k0 < f.off[(size_t)r + 1]; k0 += GT) {
+                tl.push_back(r);
+                tl.push_back((int32_t)k0);
+                tl.push_back((int32_t)std::min<int64_t>(k0 + GT, f.off[(size_t)r + 1]));
+            }
+        }
+        f.ntiles = (int64_t)tl.size() / 3;
+        FCHK(ar.put(&f.tiles, tl, f.s));
         LAT_HIP(hipStreamSynchronize(f.s));
     }
     // masks
