@@ -322,6 +322,14 @@ def main():
                     help="--newton: ROM tangent products from stencils formed once per iteration, or ROM applies")
     ap.add_argument("--precond", choices=["two-level", "diag", "feti"], default="two-level",
                     help="--newton: tangent solve (MINRES two-level / diagonal, or the inexact FETI-DP solve)")
+    ap.add_argument("--feti", action="store_true",
+                    help="time one FETI-DP tangent solve against MINRES (two levels) on the ROM tangent at the "
+                         "affine state of half the --strain load, or after --feti-newton-steps Newton steps")
+    ap.add_argument("--feti-newton-steps", type=int, default=0, help="--feti: Newton steps (MINRES) before the solve")
+    ap.add_argument("--feti-inner", type=int, default=8, help="--feti: interface PCG steps")
+    ap.add_argument("--feti-enrich", type=int, default=0, help="--feti: enrichment level to start from")
+    ap.add_argument("--feti-f32", action="store_true", help="--feti: FP32 local-solve blocks in the preconditioner")
+    ap.add_argument("--feti-max-enrich", type=int, default=3, help="--feti: highest enrichment level")
     ap.add_argument("--feti-n-delta", type=int, default=0,
                     help="--newton --precond feti: principal cells the local models choose from (0 = all)")
     ap.add_argument("--tangent", choices=["rom", "full"], default="rom",
@@ -332,6 +340,9 @@ def main():
         sys.exit(2)
     if args.newton:
         newton_main(args)
+        return
+    if args.feti:
+        feti_main(args)
         return
 
     import numpy as np
@@ -594,6 +605,82 @@ def newton_cpu_baseline(cfg, case, args, budget_s=12.0):
             "sample": f"{n} Newton iteration(s) of the first increment on the {sub[0]} x {sub[1]}-cell corner of the "
                       f"workload ({P.ng * c2.dim} DOFs; the full lattice is {int(np.prod(cfg.ncell))} cells), "
                       f"SuperLU (one thread) tangent solve, element loops on the OpenMP threads"}
+
+
+def feti_main(args):
+    """One inexact FETI-DP solve (Sec. 3.3) of the ROM tangent system and the two-level MINRES solve of
+    the same system, timed on the GPU; one JSON line with iterations, times, their agreement and the
+    saddle-point residual."""
+    import numpy as np
+    import torch
+
+    import lattice as L
+    from paper_2603_10741_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = L.config(args.workload)
+    case = L.LoadCase("compress_shear", args.strain, args.shear, 2)
+    keep = L.make_keep(cfg)
+    mu, lam = L.make_material(cfg)
+    bvp = L.make_bvp(cfg, case)
+    P = B.Plan(cfg.dim, cfg.ncell, cfg.nel, keep, cap=args.cap)
+    _, nact, g2bg, _ = P.dofmap()
+    g2bg = g2bg.cpu().numpy()
+    fixed = torch.from_numpy(np.ascontiguousarray(bvp["fixed"][g2bg])).to(dev)
+    ubar = torch.from_numpy(np.ascontiguousarray(bvp["ubar"][g2bg])).to(dev)
+    mu_t, lam_t = torch.from_numpy(mu).to(dev), torch.from_numpy(lam).to(dev)
+    if args.feti_newton_steps > 0:
+        u = torch.zeros(P.nglobal, cfg.dim, dtype=torch.float64, device=dev)
+        P.newton_solve(mu_t, lam_t, fixed, ubar, u, n_inc=2, max_newton=args.feti_newton_steps, cap=args.cap,
+                       rb_tol=args.rb_tol, cg_tol=1e-8, cg_maxit=args.solve_maxit, cg_check=64, precond=1)
+        state = f"after {args.feti_newton_steps} Newton step(s) of the first of 2 increments"
+    else:
+        u = (0.5 * ubar).contiguous()
+        state = "affine, half the load"
+    r = P.residual_tangent(u, mu_t, lam_t, f=False, energy=False, snap=True)
+    g = P.select_principal(r["snap"], args.rb_tol, cap=args.cap)
+    n_r = int(g["n_r"].item())
+    K = P.principal_ops(u, mu_t, lam_t, g["S"], n_r)["K"]
+    P.check_status(allow_cap=True)
+    b = torch.from_numpy(np.random.default_rng(7).standard_normal((P.nglobal, cfg.dim))).to(dev)
+    runs = []
+    for _ in range(2):           # the second solve is the timed one (rocBLAS / rocSOLVER warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, info = P.feti_solve(K, n_r, g["alpha"], g["S"], fixed, b, R=g["R"], nu=g["nu"], beta=g["beta"],
+                                   n_delta=args.feti_n_delta, inner_it=args.feti_inner, tol=args.solve_tol,
+                                   maxit=600, enrich=args.feti_enrich, prec=B.F32 if args.feti_f32 else B.F64,
+                                   max_enrich=max(args.feti_max_enrich, args.feti_enrich))
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0, x, st, info))
+    wall, x, st, info = runs[-1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xm, stm, its, rr = P.rom_solve(K, n_r, g["alpha"], fixed, b, tol=args.solve_tol, maxit=args.solve_maxit, check=64)
+    torch.cuda.synchronize()
+    wall_m = time.perf_counter() - t0
+    agree = (torch.linalg.norm(x - xm) / torch.linalg.norm(xm)).item()
+    out = {
+        "metric": "time of one tangent solve K~ x = b (inexact FETI-DP against two-level MINRES)",
+        "value": round(wall, 4), "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "cells": P.ncells, "global_dofs": P.nglobal * cfg.dim,
+                   "load": {"kind": case.kind, "strain": case.strain, "shear": case.shear}, "state": state,
+                   "rb_tol": args.rb_tol, "n_r": n_r, "tol": args.solve_tol, "inner_it": args.feti_inner,
+                   "enrich_start": args.feti_enrich, "local_blocks": "f32" if args.feti_f32 else "f64",
+                   "n_delta": info["n_delta"], "rhs": "i.i.d. N(0,1)"},
+        "feti": {"status": int(st), "iters": info["iters"], "restarts": info["restarts"], "enrich": info["enrich"],
+                 "n_shift": info["n_shift"], "relres": info["relres"], "setup_ms": round(info["t_setup_ms"], 2),
+                 "solve_ms": round(info["t_solve_ms"], 2),
+                 "ms_per_iteration": round(info["t_solve_ms"] / max(info["iters"], 1), 3),
+                 "primal_dofs": info["n_primal"], "multipliers": info["n_mult"], "remaining_rows": info["n_rdofs"],
+                 "dual_rows": info["n_ddofs"]},
+        "minres": {"status": int(stm), "iters": its, "relres_Minv": rr, "s": round(wall_m, 4)},
+        "rel_diff_feti_vs_minres": agree,
+    }
+    print(json.dumps(out))
 
 
 def newton_main(args):

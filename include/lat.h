@@ -405,7 +405,9 @@ typedef struct {
                              nearest of the first n_delta principal cells in snapshot space (needs R,
                              nu, beta; lanes are then grouped by principal cell and each group's
                              products are one GEMM); 0 = least squares over them (see lat_feti_solve) */
-    int32_t reserved;     /* 0 */
+    int32_t prec;         /* precision of the local solves' blocks G_r in the preconditioner: LAT_F64, or
+                             LAT_F32 (coords = 1; halves their bytes; the operator, the residual and
+                             everything else stay FP64) */
     double tol;           /* stop at ||res|| <= tol ||rhs|| (2-norms of the saddle-point system), > 0 */
 } lat_feti_opts;
 

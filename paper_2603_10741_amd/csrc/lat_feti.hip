@@ -840,66 +840,97 @@ __global__ void k_scatter_lanes(int64_t rows, int64_t ld, int64_t nv, const int3
 // Grouped product for the one-hot models, one launch for every principal cell:
 //   C[k, n] = beta C[k, n] + sum_j X[k, j] op(M_r)[j, n]   for the lanes k of group r,
 // X, C column-major [ld x ...] in group order, op(M_r) = M_r (K x N, ldm) or M_r^T (M_r N x K).
-// A workgroup of 256 threads computes a 64-lane x 64-column tile of one group (tiles listed in
-// `tiles` as (group, first lane, end lane)); K is staged through LDS 32 at a time, each thread
-// accumulates a 4 x 4 block in FP64.  The principal block is read once per 64 lanes of its group.
+// A workgroup of 4 waves computes a 64-lane x 64-column tile of one group (tiles listed in `tiles`
+// as (group, first lane, end lane)); K is staged through LDS 32 at a time and contracted on the FP64
+// matrix cores: wave w owns lanes 16w..16w+15, four 16 x 16 output tiles, one v_mfma_f64_16x16x4
+// per tile and k-step (A = the lanes' X from LDS, B = the block's columns).  The principal block
+// is read once per 64 lanes of its group; FP32 blocks are widened on the way into LDS.
 constexpr int GT = 64, GK = 32;
-constexpr int64_t GBIG = 192;   // groups this large go to rocBLAS (matrix-core GEMMs)
-template <bool TRANS>
-__global__ __launch_bounds__(256) void k_grouped_gemm(int64_t ld, int64_t N, int64_t K, const int32_t *__restrict__ tiles,
-                                                      const double *__restrict__ X, const double *__restrict__ M,
-                                                      int64_t ldm, int64_t strideM, double beta, double *__restrict__ C)
+constexpr int64_t GBIG = 192;   // groups this large go to rocBLAS (FP64 blocks only)
+typedef double feti_v4d __attribute__((ext_vector_type(4)));
+template <bool TRANS, class MT>
+__global__ __launch_bounds__(256) void k_grouped_gemm(int64_t ld, int64_t N, int64_t K, int64_t Kc,
+                                                      const int32_t *__restrict__ tiles, const double *__restrict__ X,
+                                                      const MT *__restrict__ M, int64_t ldm, int64_t strideM,
+                                                      double beta, double *__restrict__ C, double *__restrict__ part)
 {
     __shared__ double xs[GK][GT + 1];
     __shared__ double ms[GK][GT + 1];
     const int r = tiles[3 * blockIdx.y], k0 = tiles[3 * blockIdx.y + 1], k1 = tiles[3 * blockIdx.y + 2];
     const int64_t n0 = (int64_t)blockIdx.x * GT;
-    const double *Mr = M + (int64_t)r * strideM;
+    const int64_t jb = (int64_t)blockIdx.z * Kc, je = min(K, jb + Kc);   // this split's share of K
+    const MT *Mr = M + (int64_t)r * strideM;
     const int t = threadIdx.x;
-    const int tr = (t % 16) * 4, tc = (t / 16) * 4;     // this thread's 4 x 4 block
-    double acc[4][4] = {};
-    for (int64_t j0 = 0; j0 < K; j0 += GK) {
-        // X tile [GK][GT]: lanes fastest (coalesced)
-        for (int e = t; e < GK * GT; e += 256) {
-            const int kk = e / GT, row = e % GT;
-            const int64_t j = j0 + kk, k = k0 + row;
-            xs[kk][row] = (j < K && k < k1) ? X[j * ld + k] : 0.0;
-        }
-        // op(M) tile [GK][GT]
-        for (int e = t; e < GK * GT; e += 256) {
+    const int w = t >> 6, l = t & 63;
+    constexpr int PT = GK * GT / 256;                    // staged values per thread and operand
+    double xr[PT], mr[PT];
+    // the next k-stage's operands into registers (issued before the current stage's products)
+    auto gload = [&](int64_t j0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            const int e = t + 256 * q;
+            {
+                const int kk = e / GT, row = e % GT;
+                const int64_t j = j0 + kk, k = k0 + row;
+                xr[q] = (j < je && k < k1) ? X[j * ld + k] : 0.0;
+            }
             int kk, c;
             if (TRANS) { kk = e / GT; c = e % GT; }      // M[(j) ldm + n]: n fastest
             else { c = e / GK; kk = e % GK; }             // M[(n) ldm + j]: j fastest
             const int64_t j = j0 + kk, n = n0 + c;
-            double v = 0.0;
-            if (j < K && n < N) v = TRANS ? Mr[j * ldm + n] : Mr[n * ldm + j];
-            ms[kk][c] = v;
+            mr[q] = (j < je && n < N) ? (double)(TRANS ? Mr[j * ldm + n] : Mr[n * ldm + j]) : 0.0;
+        }
+    };
+    feti_v4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = feti_v4d{0.0, 0.0, 0.0, 0.0};
+    if (jb < je) gload(jb);
+    for (int64_t j0 = jb; j0 < je; j0 += GK) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            const int e = t + 256 * q;
+            xs[e / GT][e % GT] = xr[q];
+            if (TRANS) ms[e / GT][e % GT] = mr[q];
+            else ms[e % GK][e / GK] = mr[q];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < GK; ++kk) {
-            double a[4], b[4];
+        if (j0 + GK < je) gload(j0 + GK);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { a[u] = xs[kk][tr + u]; b[u] = ms[kk][tc + u]; }
+        for (int kk = 0; kk < GK; kk += 4) {
+            const double a = xs[kk + (l >> 4)][16 * w + (l & 15)];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+            for (int c = 0; c < 4; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ms[kk + (l >> 4)][16 * c + (l & 15)], acc[c], 0, 0, 0);
         }
         __syncthreads();
     }
+    // output element (row (l / 16) + 4 q, column l % 16) of each 16 x 16 tile; a split writes its
+    // partial sums, reduced in split order by k_split_sum
+    double *out = gridDim.z > 1 ? part + (int64_t)blockIdx.z * N * ld : C;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int64_t n = n0 + tc + v;
+    for (int c = 0; c < 4; ++c) {
+        const int64_t n = n0 + 16 * c + (l & 15);
         if (n >= N) continue;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = k0 + tr + u;
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = k0 + 16 * w + (l >> 4) + 4 * q;
             if (k >= k1) continue;
             const int64_t idx = n * ld + k;
-            C[idx] = beta == 0.0 ? acc[u][v] : fma(beta, C[idx], acc[u][v]);
+            out[idx] = (gridDim.z > 1 || beta == 0.0) ? acc[c][q] : fma(beta, C[idx], acc[c][q]);
         }
     }
+}
+
+// C = beta C + sum_z part[z] over the lanes in group order (z ascending), rows < nv
+__global__ void k_split_sum(int64_t ld, int64_t N, int64_t nv, int nz, const double *__restrict__ part, double beta,
+                            double *__restrict__ C)
+{
+    const int64_t t = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (t >= N * ld) return;
+    if (t % ld >= nv) return;
+    double acc = 0.0;
+    for (int z = 0; z < nz; ++z) acc += part[(int64_t)z * N * ld + t];
+    C[t] = beta == 0.0 ? acc : fma(beta, C[t], acc);
 }
 
 // local coarse matrices of the one-hot models: C[lane] = S_{sel[lane]} (zero for padding lanes)
@@ -914,6 +945,11 @@ __global__ void k_select_spp(int64_t np2, int64_t ld, const int32_t *__restrict_
 }
 
 // principal cell of each lane under one-hot coordinates (-1 for padding lanes)
+__global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restrict__ y)
+{
+    for (int64_t j = (int64_t)blockIdx.x * NB + threadIdx.x; j < n; j += (int64_t)gridDim.x * NB) y[j] = (float)x[j];
+}
+
 __global__ void k_onehot_sel(int64_t ld, int nd, const double *__restrict__ delta, int32_t *__restrict__ sel)
 {
     const int64_t lane = (int64_t)blockIdx.x * NB + threadIdx.x;
@@ -1123,6 +1159,10 @@ struct Feti {
     double *Xpk = nullptr, *Ypk = nullptr;
     uint8_t *liveR = nullptr, *liveP = nullptr, *liveL = nullptr, *liveD = nullptr;
     // reduced models over the principal cells
+    float *G32 = nullptr;            // FP32 copy of the G_r (reduced-precision local solves)
+    double *split = nullptr;         // split-K partial sums of the grouped products
+    int64_t split_rows = 0;          // their capacity, in output columns x splits
+    bool g32 = false;
     double *G = nullptr, *Phi = nullptr, *Spp = nullptr, *Fdd = nullptr, *Sdd = nullptr, *Phid = nullptr;
     double *delta = nullptr, *Sc = nullptr;   // [ld][nd], coarse inverse [nPgd]^2
     // scratch
@@ -1237,6 +1277,32 @@ lat_status coarse_part(Feti &f, const double *base)
 
 // one-hot models: C_g[off_r .., :] (op) = X_g[off_r .., :] M_r (op(M_r)) for every principal cell r,
 // lanes in group order (column-major [ld x k] blocks, M_r [k x n] or its transpose)
+template <class MT>
+lat_status grouped_launch(Feti &f, rocblas_operation tm, int64_t n, int64_t k, const double *Xg, const MT *M,
+                          int64_t ldm, int64_t strideM, double beta, double *Cg)
+{
+    // split K when the output tiles alone would leave the chip idle (narrow products)
+    const int64_t ct = lat_cdiv(n, GT);
+    int64_t nz = 1;
+    // (only without rocBLAS-served groups: the partial sums cover every lane of the small groups)
+    while (f.big.empty() && nz < 64 && ct * f.ntiles * nz < 1024 && lat_cdiv(k, GK) >= 4 * nz &&
+           (nz * 2) * n <= f.split_rows)
+        nz *= 2;
+    const int64_t Kc = lat_cdiv(lat_cdiv(k, nz), GK) * GK;
+    const dim3 grid((unsigned)ct, (unsigned)f.ntiles, (unsigned)nz);
+    if (tm == rocblas_operation_none)
+        hipLaunchKernelGGL((k_grouped_gemm<false, MT>), grid, dim3(256), 0, f.s, f.ld, n, k, Kc, (const int32_t *)f.tiles,
+                           Xg, M, ldm, strideM, beta, Cg, f.split);
+    else
+        hipLaunchKernelGGL((k_grouped_gemm<true, MT>), grid, dim3(256), 0, f.s, f.ld, n, k, Kc, (const int32_t *)f.tiles,
+                           Xg, M, ldm, strideM, beta, Cg, f.split);
+    if (nz > 1)
+        hipLaunchKernelGGL(k_split_sum, dim3(blocks(n * f.ld)), dim3(NB), 0, f.s, f.ld, n, f.nv, (int)nz,
+                           (const double *)f.split, beta, Cg);
+    LAT_LAUNCH_CHECK();
+    return LAT_OK;
+}
+
 lat_status grouped(Feti &f, rocblas_operation tm, int64_t n, int64_t k, const double *Xg, const double *M,
                    int64_t ldm, int64_t strideM, double beta, double *Cg)
 {
@@ -1247,15 +1313,16 @@ lat_status grouped(Feti &f, rocblas_operation tm, int64_t n, int64_t k, const do
                   beta, Cg + f.off[(size_t)r], f.ld));
     }
     if (f.ntiles == 0) return LAT_OK;
-    const dim3 grid((unsigned)lat_cdiv(n, GT), (unsigned)f.ntiles);
-    if (tm == rocblas_operation_none)
-        hipLaunchKernelGGL(k_grouped_gemm<false>, grid, dim3(256), 0, f.s, f.ld, n, k, (const int32_t *)f.tiles, Xg, M,
-                           ldm, strideM, beta, Cg);
-    else
-        hipLaunchKernelGGL(k_grouped_gemm<true>, grid, dim3(256), 0, f.s, f.ld, n, k, (const int32_t *)f.tiles, Xg, M,
-                           ldm, strideM, beta, Cg);
-    LAT_LAUNCH_CHECK();
-    return LAT_OK;
+    return grouped_launch<double>(f, tm, n, k, Xg, M, ldm, strideM, beta, Cg);
+}
+
+// the local solves' blocks G_r, in FP32 when the reduced-precision inner apply is on (every group
+// then goes through the grouped kernel)
+lat_status grouped_G(Feti &f, int64_t nR, const double *Xg, double beta, double *Cg)
+{
+    if (f.g32) return f.ntiles ? grouped_launch<float>(f, rocblas_operation_none, nR, nR, Xg, f.G32, nR, nR * nR, beta, Cg)
+                               : LAT_OK;
+    return grouped(f, rocblas_operation_none, nR, nR, Xg, f.G, nR, nR * nR, beta, Cg);
 }
 
 // K~rom^-1 with one-hot models: every cell's local operators are its principal cell's
@@ -1264,7 +1331,7 @@ lat_status krom_onehot(Feti &f, const double *gR, const double *gP, double *zR, 
     const int64_t nR = f.nRr, ld = f.ld, nP = f.nPr;
     hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nR * ld)), dim3(NB), 0, f.s, nR, ld, f.nv, f.order, f.liveR, gR, f.Xg);
     LAT_LAUNCH_CHECK();
-    FCHK(grouped(f, rocblas_operation_none, nR, nR, f.Xg, f.G, nR, nR * nR, 0.0, f.Yg));
+    FCHK(grouped_G(f, nR, f.Xg, 0.0, f.Yg));
     FCHK(grouped(f, rocblas_operation_none, nP, nR, f.Xg, f.Phi, nR, nR * nP, 0.0, f.T1));
     FCHK(coarse_part(f, gP));
     hipLaunchKernelGGL(k_gather_lanes, dim3(blocks(nP * ld)), dim3(NB), 0, f.s, nP, ld, f.nv, f.order,
@@ -1683,7 +1750,7 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
         std::vector<int32_t> tl;
         f.big.clear();
         for (int r = 0; r < nd; ++r) {
-            if (f.off[(size_t)r + 1] - f.off[(size_t)r] >= GBIG) { f.big.push_back(r); continue; }
+            if (!f.g32 && f.off[(size_t)r + 1] - f.off[(size_t)r] >= GBIG) { f.big.push_back(r); continue; }
             for (int64_t k0 = f.off[(size_t)r]; k0 < f.off[(size_t)r + 1]; k0 += GT) {
                 tl.push_back(r);
                 tl.push_back((int32_t)k0);
@@ -1733,7 +1800,18 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
     // scratch of the applies
     const int64_t stack_rows = std::max<int64_t>({f.nRr, f.nDr, f.nPr, 1});
     FCHK(ar.get(&f.As, stack_rows * f.ld * (f.onehot ? 1 : nd)));
-    if (f.onehot) { FCHK(ar.get(&f.Xg, stack_rows * f.ld)); FCHK(ar.get(&f.Yg, stack_rows * f.ld)); }
+    if (f.onehot) {
+        FCHK(ar.get(&f.Xg, stack_rows * f.ld)); FCHK(ar.get(&f.Yg, stack_rows * f.ld));
+        f.split_rows = 2 * stack_rows;
+        FCHK(ar.get(&f.split, f.split_rows * f.ld));
+    }
+    if (f.g32) {
+        FCHK(ar.get(&f.G32, f.nRr * f.nRr * nd));
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks(std::min<int64_t>(f.nRr * f.nRr * nd, (int64_t)1 << 26))), dim3(NB), 0,
+                           f.s, f.nRr * f.nRr * nd, (const double *)f.G, f.G32);
+        LAT_LAUNCH_CHECK();
+    }
+
     FCHK(ar.get(&f.xm, stack_rows * f.ld));
     FCHK(ar.get(&f.T1, f.nPr * nd * f.ld));
     FCHK(ar.get(&f.hl, f.nPr * f.ld)); FCHK(ar.get(&f.el, f.nPr * f.ld));
@@ -1784,7 +1862,8 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
     if (n_r < 1 || n_r > P->cap) return LAT_E_SHAPE;
     if (opts->enrich < 0 || opts->max_enrich < opts->enrich || opts->inner_it < 0 || opts->restart < 1 ||
         opts->restart > 512 || opts->maxit < 1 || !(opts->tol > 0.0) || opts->n_delta < 0 || opts->indefinite < 0 ||
-        opts->indefinite > 1 || opts->coords < 0 || opts->coords > 1 || (opts->coords == 1 && !R))
+        opts->indefinite > 1 || opts->coords < 0 || opts->coords > 1 || (opts->coords == 1 && !R) ||
+        (opts->prec != LAT_F64 && opts->prec != LAT_F32) || (opts->prec == LAT_F32 && opts->coords != 1))
         return LAT_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     Feti f;
@@ -1793,6 +1872,7 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
     f.inner_it = opts->inner_it;
     f.indef_mode = opts->indefinite;
     f.coords = opts->coords;
+    f.g32 = opts->prec == LAT_F32;
     f.h = feti_handle();
     if (!f.h || rocblas_set_stream(f.h, stream) != rocblas_status_success) return LAT_E_DEVICE;
     FArena ar;

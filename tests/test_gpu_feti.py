@@ -132,6 +132,24 @@ def test_solve_matches_direct_solve(graded, n_delta, coords):
     _check_solution(nc, Ko, b, x3, _direct(nc, Ko, b))
 
 
+def test_fp32_local_blocks(graded):
+    # the reduced-precision inner apply: FP32 G_r in the preconditioner, FP64 operator and residual;
+    # the solution still meets the FP64 tolerance
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, g, Ko = _rom(nc, u, 1e-4, 16)
+    b = np.random.default_rng(38).standard_normal((nc.P.nglobal, cfg.dim))
+    b_t = torch.from_numpy(b).to(nc.dev)
+    x, st, info = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, R=g["R"], nu=g["nu"], beta=g["beta"],
+                                  prec=nc.B.F32, tol=1e-11, maxit=400)
+    print(f"[feti] FP32 local blocks: {info}", flush=True)
+    assert st == nc.B.LAT_OK and info["relres"] <= 1e-11
+    _check_solution(nc, Ko, b, x, _direct(nc, Ko, b))
+    with pytest.raises(nc.B.LatError):        # FP32 blocks need the one-hot models
+        nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, prec=nc.B.F32)
+
+
 def test_exact_local_models_when_every_cell_is_principal():
     cfg = graded_cfg().with_sub((3, 3))
     nc = NCase(cfg, L.LoadCase("compress_shear", 0.04, 0.01, 4), cap=16)
