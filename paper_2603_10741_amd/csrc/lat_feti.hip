@@ -837,7 +837,8 @@ __global__ void k_scatter_lanes(int64_t rows, int64_t ld, int64_t nv, const int3
     if (k < nv) x[j * ld + order[k]] = xg[t];
 }
 
-// Grouped product for the one-hot models, one launch for every principal cell:
+// Grouped product for the one-hot models, one launch for every principal cell (groups of 512+
+// lanes, where a matrix-core library GEMM per group pays, go to rocBLAS):
 //   C[k, n] = beta C[k, n] + sum_j X[k, j] op(M_r)[j, n]   for the lanes k of group r,
 // X, C column-major [ld x ...] in group order, op(M_r) = M_r (K x N, ldm) or M_r^T (M_r N x K).
 // A workgroup of 4 waves computes a 64-lane x 64-column tile of one group (tiles listed in `tiles`
@@ -846,7 +847,7 @@ __global__ void k_scatter_lanes(int64_t rows, int64_t ld, int64_t nv, const int3
 // per tile and k-step (A = the lanes' X from LDS, B = the block's columns).  The principal block
 // is read once per 64 lanes of its group; FP32 blocks are widened on the way into LDS.
 constexpr int GT = 64, GK = 32;
-constexpr int64_t GBIG = 192;   // groups this large go to rocBLAS (FP64 blocks only)
+constexpr int64_t GBIG = 512;   // groups this large go to rocBLAS (FP64 blocks only)
 typedef double feti_v4d __attribute__((ext_vector_type(4)));
 template <bool TRANS, class MT>
 __global__ __launch_bounds__(256) void k_grouped_gemm(int64_t ld, int64_t N, int64_t K, int64_t Kc,
@@ -1968,17 +1969,21 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
                 FCHK(precond(f, vj, zj));
                 FCHK(op_apply(f, zj, w));
                 const double one = 1.0, zero = 0.0, mone = -1.0;
+                // classical Gram-Schmidt; a second pass only when the first one cancelled most of w
+                // (its norm fell below 0.7 of the norm before: the Kahan-Parlett criterion)
+                double wb2 = 0.0, wn2 = 0.0;
+                FCHK(dot_host(f, N, w, w, &wb2));
                 for (int pass = 0; pass < 2; ++pass) {
                     RBCHK(rocblas_dgemv(f.h, rocblas_operation_transpose, (rocblas_int)N, j + 1, &one, V, (rocblas_int)N,
                                         w, 1, &zero, hcol, 1));
                     RBCHK(rocblas_dgemv(f.h, rocblas_operation_none, (rocblas_int)N, j + 1, &mone, V, (rocblas_int)N,
                                         hcol, 1, &one, w, 1));
                     LAT_HIP(hipMemcpyAsync(hh.data(), hcol, (size_t)(j + 1) * 8, hipMemcpyDeviceToHost, stream));
-                    LAT_HIP(hipStreamSynchronize(stream));
+                    FCHK(dot_host(f, N, w, w, &wn2));
                     for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] += hh[(size_t)i];
+                    if (wn2 >= 0.49 * wb2) break;
+                    wb2 = wn2;
                 }
-                double wn2 = 0.0;
-                FCHK(dot_host(f, N, w, w, &wn2));
                 const double wn = std::sqrt(wn2);
                 H[(size_t)j * (m + 1) + j + 1] = wn;
                 ++iters;
