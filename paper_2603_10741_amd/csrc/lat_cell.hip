@@ -569,6 +569,373 @@ __global__ __launch_bounds__(576) void k_cell3(CellArgs A)
     }
 }
 
+// Trilinear shape-function gradients at the 2 x 2 x 2 Gauss points of the unit cube (before the 1/h
+// scaling): g[q][c][J], q = qx + 2 qy + 4 qz, c = cx + 2 cy + 4 cz; and L[m] = sum_q g_a(q) . g_b(q)
+// for corners with a ^ b = m (the sum depends on which axes the corners differ in only: reflecting
+// the cube in an axis maps the Gauss points onto themselves).
+struct G3Table {
+    double g[8][8][3];
+    double L[8];
+};
+constexpr G3Table make_g3()
+{
+    G3Table t{};
+    const double x[2] = {0.21132486540518711775, 0.78867513459481288225};   // 1/2 -+ 1/(2 sqrt 3)
+    for (int q = 0; q < 8; ++q)
+        for (int c = 0; c < 8; ++c)
+            for (int J = 0; J < 3; ++J) {
+                double v = 1.0;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int kq = (q >> ax) & 1, bit = (c >> ax) & 1;
+                    if (ax == J) v *= bit ? 1.0 : -1.0;
+                    else v *= bit ? x[kq] : 1.0 - x[kq];
+                }
+                t.g[q][c][J] = v;
+            }
+    for (int m = 0; m < 8; ++m) {
+        double s = 0.0;
+        for (int q = 0; q < 8; ++q)
+            for (int J = 0; J < 3; ++J) s += t.g[q][0][J] * t.g[q][m][J];
+        t.L[m] = s;
+    }
+    return t;
+}
+__constant__ G3Table c_g3 = make_g3();
+
+// Full-rule 3D residual and tangent by node lines.  A workgroup owns the node line (y0, z0) of 64 cell
+// lanes and sweeps it in x: at step ex the (up to) four elements (ex, y0 - 1 + dy, z0 - 1 + dz) touch
+// the line's nodes x = ex (their corner with x-bit 0) and x = ex + 1 (x-bit 1).  Each kept element's
+// eight Gauss points are formed once per line, four at a time: the corner vectors p_c = F^{-T} g_c of
+// all eight corners, w (mu - lam ln J), the points' force terms w P g_a of the two line nodes and
+// the point's energy go to LDS.  The node rows follow from
+//   K[(a,i),(b,j)] += w [ (mu - lam ln J) (p_a)_j (p_b)_i + lam (p_a)_i (p_b)_j ]
+// summed over the points, plus mu d_ij sum_q w g_a . g_b = mu d_ij (h/8) L[a ^ b] once per element.
+//
+// Two roles of four waves each.  The point waves form one chunk (four points of one element) into
+// one of two LDS buffers and meet the barrier; the accumulation waves meet the same barrier and then
+// sum that chunk while the point waves form the next one into the other buffer.  Accumulation wave
+// (s, t) holds the 81 entries (oy, oz, i, j) of one x-offset block of one node row: when ex + s is
+// even its node is x = ex, else x = ex + 1; t = 0 takes the corners b at the node's own x (offset 0,
+// summed over the two steps that touch the node, then written), t = 1 those at the other x (offset
+// +1 or -1, complete after one step).  Every entry of every node row is written once, by one wave:
+// no atomics.  Wave (0, 0) also sums the force rows and element energies (owned by the element's
+// corner 0) in point order.  Lanes that do not keep an element form F = I at its points and give it
+// zero weight.  The roles are separate branches, so the accumulators are not live where the points
+// are formed and two waves fit on a SIMD.
+constexpr int LAT_TAN3_MAX_NEL = 16;     // element slots of a line fit one 64-bit mask (k_cell3 above)
+
+template <bool PRINCIPAL, bool SAMPLED>
+__global__ __launch_bounds__(512) void k_tan3(CellArgs A)
+{
+    constexpr int E = Geo<3>::E;
+    // per point: p_c [cx][cy + 2 cz][i] (24), w (mu - lam ln J), w P g of x = ex (3) and x = ex + 1 (3),
+    // w W (energy)
+    constexpr int PV = 32;
+    __shared__ double pd[8 * PV * 64];           // the eight points of one element
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = threadIdx.x & 63;
+    const int nel = A.nel, nn = nel + 1;
+    const int64_t ld = A.ld;
+    // sampled entries: the lines through the sub-grid nodes, whose rows are stored alone, in sub-grid
+    // order (the same arithmetic as the full sweep, so the same bits)
+    constexpr int SS = LAT_SAMPLE_STRIDE;
+    const int nsa = A.nsa;
+    const int y0 = SAMPLED ? SS * ((int)blockIdx.y % nsa) : (int)blockIdx.y % nn;
+    const int z0 = SAMPLED ? SS * ((int)blockIdx.y / nsa) : (int)blockIdx.y / nn;
+    const int line = nn * (y0 + nn * z0);         // node index of x = 0 on the line
+    int64_t p;
+    int cell, slot = 0;
+    if (PRINCIPAL) {
+        slot = l;
+        cell = slot < A.n_r ? A.S[slot] : -1;
+        p = cell >= 0 ? A.lane[cell] : 0;
+    } else {
+        p = (int64_t)blockIdx.x * LAT_WAVE + l;
+        cell = A.perm[p];
+    }
+    const double h = 1.0 / nel, invh = (double)nel;
+    const double wq = 0.125 * h * h * h;
+    double mu = 0.0, lam = 0.0;
+    if (cell >= 0) {
+        mu = A.matmode == 0 ? A.mu[cell] : (A.matmode == 1 ? 1.0 : 0.0);
+        lam = A.matmode == 0 ? A.lam[cell] : (A.matmode == 2 ? 1.0 : 0.0);
+    }
+    const bool forces = !PRINCIPAL && !SAMPLED && (A.f || A.epart);
+    const uint32_t poff0 = (uint32_t)p * 8u;
+    // the line's element slots 4 ex + dy + 2 dz (ex < nel <= 16): bit set in `pmask` when the element
+    // (ex, y0 - 1 + dy, z0 - 1 + dz) exists and some lane keeps it (uniform over the workgroup: every
+    // wave holds the same 64 lanes), in `kmask` when this lane keeps it
+    uint64_t pmask = 0, kmask = 0;
+    for (int sl = 0; sl < 4 * nel; ++sl) {
+        const int ex = sl >> 2, ey = y0 - 1 + (sl & 1), ez = z0 - 1 + ((sl >> 1) & 1);
+        bool kept = false;
+        if (ey >= 0 && ey < nel && ez >= 0 && ez < nel && cell >= 0)
+            kept = *((const uint8_t *)(A.keep_il + (int64_t)(ex + nel * (ey + nel * ez)) * ld) + (poff0 >> 3));
+        if (kept) kmask |= 1ull << sl;
+        if (__builtin_amdgcn_ballot_w64(kept) != 0) pmask |= 1ull << sl;
+    }
+
+    if (w >= 4) {
+        // ================= point role =================
+        // Points gw and gw + 4 of each kept element (in slot order), formed together in registers while
+        // the accumulation waves read the previous element from LDS; between two barriers they are
+        // written to LDS.  The next element's corner displacements are loaded before that.
+        const int gw = w - 4;
+        uint64_t m = pmask;
+        double u[8][3];
+        auto load_u = [&](int sl) __attribute__((always_inline)) {
+            const int ex = sl >> 2, ey = y0 - 1 + (sl & 1), ez = z0 - 1 + ((sl >> 1) & 1);
+            const int nb0 = ex + nn * (ey + nn * ez);
+            const bool kept = (kmask >> sl) & 1;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int b = nb0 + (c & 1) + nn * (((c >> 1) & 1) + nn * ((c >> 2) & 1));
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    u[c][i] = kept ? *(const double *)((const char *)(A.u_cil + ((int64_t)b * 3 + i) * ld) + poff0) : 0.0;
+            }
+        };
+        int sl = m ? __builtin_ctzll(m) : -1;
+        if (sl >= 0) load_u(sl);
+        while (sl >= 0) {
+            m &= m - 1;
+            const int dy = sl & 1, dz = (sl >> 1) & 1;
+            const int kA = 2 * (1 - dy) + 4 * (1 - dz);          // corner of node x = ex (x = ex + 1: kA + 1)
+            const double wk = ((kmask >> sl) & 1) ? wq : 0.0;
+            double out[2][PV];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int q = gw + 4 * h2;
+                double F[3][3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) {
+                        double g = 0.0;
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) g = fma(u[c][i], c_g3.g[q][c][J], g);
+                        F[i][J] = i == J ? fma(invh, g, 1.0) : invh * g;
+                    }
+                // cofactors and J with every product-sum fused explicitly: the full and the sampled sweeps
+                // then round identically whatever else the compiler sees around them
+                double C[3][3];
+                C[0][0] = fma(F[1][1], F[2][2], -(F[1][2] * F[2][1]));
+                C[0][1] = fma(F[1][2], F[2][0], -(F[1][0] * F[2][2]));
+                C[0][2] = fma(F[1][0], F[2][1], -(F[1][1] * F[2][0]));
+                C[1][0] = fma(F[0][2], F[2][1], -(F[0][1] * F[2][2]));
+                C[1][1] = fma(F[0][0], F[2][2], -(F[0][2] * F[2][0]));
+                C[1][2] = fma(F[0][1], F[2][0], -(F[0][0] * F[2][1]));
+                C[2][0] = fma(F[0][1], F[1][2], -(F[0][2] * F[1][1]));
+                C[2][1] = fma(F[0][2], F[1][0], -(F[0][0] * F[1][2]));
+                C[2][2] = fma(F[0][0], F[1][1], -(F[0][1] * F[1][0]));
+                const double Jd = fma(F[0][0], C[0][0], fma(F[0][1], C[0][1], F[0][2] * C[0][2]));
+                double lnJ = 0.0;
+                if (Jd > 0.0 && isfinite(Jd)) lnJ = log(Jd);
+                else if (wk != 0.0) lat_flag(A.st, isfinite(Jd) ? LAT_E_INVERTED : LAT_E_NONFINITE, cell);
+                const double rh = invh / Jd;                            // p_c = (C / J)(ghat_c / h)
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        out[h2][(c & 1) * 12 + (c >> 1) * 3 + i] =
+                            fma(C[i][0], c_g3.g[q][c][0], fma(C[i][1], c_g3.g[q][c][1], C[i][2] * c_g3.g[q][c][2])) * rh;
+                out[h2][24] = wk * fma(-lam, lnJ, mu);
+                if (forces) {
+                    // force terms of the two line nodes: w P g_a = w (mu (F g_a - p_a) + lam ln J p_a)
+#pragma unroll
+                    for (int x = 0; x < 2; ++x) {
+                        const int ka = kA + x;
+                        const double g0 = c_g3.g[q][ka][0], g1 = c_g3.g[q][ka][1], g2 = c_g3.g[q][ka][2];
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            const double pa = fma(C[i][0], g0, fma(C[i][1], g1, C[i][2] * g2)) * rh;   // p of corner ka
+                            const double Fg = invh * fma(F[i][0], g0, fma(F[i][1], g1, F[i][2] * g2));
+                            out[h2][25 + 3 * x + i] = wk * fma(mu, Fg - pa, lam * lnJ * pa);
+                        }
+                    }
+                    double I1 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int J = 0; J < 3; ++J) I1 += F[i][J] * F[i][J];
+                    out[h2][31] = wk * (0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+                } else {
+#pragma unroll
+                    for (int v = 25; v < PV; ++v) out[h2][v] = 0.0;
+                }
+            }
+            sl = m ? __builtin_ctzll(m) : -1;
+            if (sl >= 0) load_u(sl);                             // the next element, during the write phase
+            __syncthreads();                                     // the previous element has been read
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                for (int v = 0; v < PV; ++v) pd[((gw + 4 * h2) * PV + v) * 64 + l] = out[h2][v];
+            __syncthreads();                                     // this element is in LDS
+        }
+        return;
+    }
+
+    // ================= accumulation role =================
+    const int s = w & 1, t = w >> 1;
+    const bool fwave = forces && w == 0;
+    const double muL = mu * 0.125 * h;            // mu sum_q w g_a . g_b = mu (h/8) L
+    const double lw0 = wq * lam;
+    double acc[9][9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[k][e] = 0.0;
+    double fc[3] = {0.0, 0.0, 0.0}, fn[3] = {0.0, 0.0, 0.0}, en = 0.0;
+    // entries k9 = 3 (oz + 1) + oy + 1 in `mask` (a constant) of block ox of node x:
+    // rows 9 (ox + 1) + 27 k9 + 3 i + j
+    auto store = [&](auto maskc, int x, int ox, uint32_t poff) __attribute__((always_inline)) {
+        constexpr int mask = decltype(maskc)::value;
+        const int node = line + x;
+        const uint32_t loff = (uint32_t)l * 8u;
+        if (PRINCIPAL) {
+            if (slot < A.cap) {
+                const int64_t cap = A.cap;
+                char *base = (char *)(A.Kst + ((int64_t)node * E + 9 * (ox + 1)) * cap);
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    if ((mask >> k) & 1)
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) *(double *)(base + (int64_t)(27 * k + e) * cap * 8 + loff) = acc[k][e];
+            }
+            return;
+        }
+        if (A.T) {
+            int64_t orow = node;
+            if (SAMPLED) {
+                if (x % SS != 0 || x / SS >= nsa) return;
+                orow = x / SS + nsa * (y0 / SS + nsa * (z0 / SS));
+            }
+            char *base = (char *)(A.T + (orow * E + 9 * (ox + 1)) * ld);
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                if ((mask >> k) & 1)
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) *(double *)(base + (int64_t)(27 * k + e) * ld * 8 + poff) = acc[k][e];
+        }
+        if (A.ops) {
+            const int g = (int)blockIdx.x;
+            const int qi = A.uidx[(int64_t)g * A.nloc + node];
+            if (qi >= 0) {
+                const int64_t q = (int64_t)A.goff[g] + qi;         // packed node (64-bit: beyond 2^31 / (E 64))
+                char *base = (char *)(A.ops + (q * E + 9 * (ox + 1)) * LAT_WAVE);
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    if ((mask >> k) & 1)
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) *(double *)(base + (int64_t)(27 * k + e) * LAT_WAVE * 8 + loff) = acc[k][e];
+            }
+        }
+    };
+    for (int ex = -1; ex <= nel; ++ex) {
+        // the lane offset is made opaque at every step, so that no per-lane address is formed once
+        // outside the sweep and kept live across it
+        uint32_t poff = poff0;
+        asm volatile("" : "+v"(poff));
+        const int r = (ex + s) & 1;                            // my node: x = ex + r
+        const int bx = r ^ t;                                  // x-bit of my block's corners b
+        auto element = [&](auto dyc, auto dzc) __attribute__((always_inline)) {
+            constexpr int dy = decltype(dyc)::value, dz = decltype(dzc)::value;
+            constexpr int ay = 1 - dy, az = 1 - dz;            // the line's corner bits in the element
+            const int sl = 4 * ex + dy + 2 * dz;
+            if (ex >= 0 && ex < nel && ((pmask >> sl) & 1)) {
+            const bool kept = (kmask >> sl) & 1;
+            const double lw = kept ? lw0 : 0.0;
+            {
+                __syncthreads();                               // the point waves start writing
+                __syncthreads();                               // the element's eight points are in LDS
+                const double *buf = pd + l;
+                const double *pa_base = buf + (r * 12 + (ay + 2 * az) * 3) * 64;
+                const double *pb_base = buf + bx * 12 * 64;
+#pragma unroll 1
+                for (int qq = 0; qq < 8; ++qq) {
+                    double c2pa[3], lpa[3];
+                    const double c2w = buf[(qq * PV + 24) * 64];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const double pa = pa_base[(qq * PV + i) * 64];
+                        c2pa[i] = c2w * pa;
+                        lpa[i] = lw * pa;
+                    }
+#pragma unroll
+                    for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+                        for (int by = 0; by < 2; ++by) {
+                            const int k9 = (by - ay + 1) + 3 * (bz - az + 1);
+                            double pb[3];
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) pb[j] = pb_base[(qq * PV + (by + 2 * bz) * 3 + j) * 64];
+#pragma unroll
+                            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                                for (int j = 0; j < 3; ++j)
+                                    acc[k9][3 * i + j] = fma(c2pa[j], pb[i], fma(lpa[i], pb[j], acc[k9][3 * i + j]));
+                        }
+                }
+                if (fwave) {
+                    for (int qq = 0; qq < 8; ++qq) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            fc[i] += buf[(qq * PV + 25 + i) * 64];
+                            fn[i] += buf[(qq * PV + 28 + i) * 64];
+                        }
+                        if (dy == 1 && dz == 1) en += buf[(qq * PV + 31) * 64];
+                    }
+                }
+            }
+            // mu d_ij (h/8) L[a ^ b], once per element; a ^ b = t + 2 (ay ^ by) + 4 (az ^ bz)
+            const double mk = kept ? muL : 0.0;
+#pragma unroll
+            for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+                for (int by = 0; by < 2; ++by) {
+                    const int k9 = (by - ay + 1) + 3 * (bz - az + 1);
+                    const double L = c_g3.L[t + 2 * (ay ^ by) + 4 * (az ^ bz)];
+                    acc[k9][0] = fma(mk, L, acc[k9][0]);
+                    acc[k9][4] = fma(mk, L, acc[k9][4]);
+                    acc[k9][8] = fma(mk, L, acc[k9][8]);
+                }
+            }
+            // Blocks that are complete after this step (t = 1 always: offset +1 of x = ex or -1 of
+            // x = ex + 1; t = 0 when its node is x = ex: offset 0; steps -1 and nel write the line's zero
+            // end blocks) are written in four parts, each as soon as no later element of the step
+            // touches it: after element (0, 0) the entries (oy, oz) = (-1, -1), after (1, 0) the rest
+            // of oz = -1, after (0, 1) the rest of oy = -1, after (1, 1) the others.  The stores are
+            // spread over the step instead of queueing at its end.
+            constexpr int gmask = dy == 0 && dz == 0 ? 0x001 : dz == 0 ? 0x006 : dy == 0 ? 0x048 : 0x1b0;
+            const int x = ex + (t == 1 ? r : 0);
+            if ((t == 1 || r == 0) && x >= 0 && x <= nel) {
+                store(std::integral_constant<int, gmask>{}, x, t == 0 ? 0 : (r ? -1 : 1), poff);
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    if ((gmask >> k) & 1)
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) acc[k][e] = 0.0;
+            }
+        };
+        element(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+        element(std::integral_constant<int, 1>{}, std::integral_constant<int, 0>{});
+        element(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+        element(std::integral_constant<int, 1>{}, std::integral_constant<int, 1>{});
+        // node x = ex is complete: its force row and energy; the next node's partials move up
+        if (fwave && ex >= 0) {
+            const int node = line + ex;
+            if (A.f)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) *(double *)((char *)(A.f + ((int64_t)node * 3 + i) * ld) + poff) = fc[i];
+            if (A.epart) *(double *)((char *)(A.epart + (int64_t)node * ld) + poff) = en;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { fc[i] = fn[i]; fn[i] = 0.0; }
+        en = 0.0;
+    }
+}
+
 // Internal force and energy without the tangent (a residual evaluation, e.g. a line-search trial).
 // One thread per (lane, element) of one parity colour: the elements whose index along every axis
 // has the colour's parity share no node, so each thread adds its corner forces f_c = sum_q w P g_c
@@ -862,6 +1229,13 @@ __global__ __launch_bounds__(256) void k_residual_adjoint(int nel, int64_t ld, c
 template <int DIM, int RULE, bool PRINCIPAL>
 lat_status launch_cell(const lat_plan *P, CellArgs &A, hipStream_t s)
 {
+    if (DIM == 3 && RULE == LAT_RULE_FULL && P->nel <= LAT_TAN3_MAX_NEL) {
+        const int nn = P->nel + 1;
+        dim3 grid(PRINCIPAL ? 1u : (unsigned)(P->ld / LAT_WAVE), (unsigned)(nn * nn));
+        hipLaunchKernelGGL((k_tan3<PRINCIPAL, false>), grid, dim3(512), 0, s, A);
+        LAT_LAUNCH_CHECK();
+        return LAT_OK;
+    }
     if (DIM == 3) {
         dim3 grid(PRINCIPAL ? 1u : (unsigned)(P->ld / LAT_WAVE), (unsigned)P->nloc);
         hipLaunchKernelGGL((k_cell3<RULE, PRINCIPAL>), grid, dim3(576), 0, s, A);
@@ -1096,8 +1470,12 @@ lat_status lat_residual_tangent(const lat_plan *Pp, const double *u_global, cons
             hipLaunchKernelGGL((k_cell<2, LAT_RULE_SAMPLED, false>), dim3((unsigned)lat_cdiv(P->ld, 256), (unsigned)nsamp),
                                dim3(256), 0, stream, B);
         else
-            hipLaunchKernelGGL((k_cell3<LAT_RULE_SAMPLED, false>), dim3((unsigned)(P->ld / LAT_WAVE), (unsigned)nsamp),
-                               dim3(576), 0, stream, B);
+            if (P->nel <= LAT_TAN3_MAX_NEL)
+                hipLaunchKernelGGL((k_tan3<false, true>), dim3((unsigned)(P->ld / LAT_WAVE), (unsigned)(B.nsa * B.nsa)),
+                                   dim3(512), 0, stream, B);
+            else
+                hipLaunchKernelGGL((k_cell3<LAT_RULE_SAMPLED, false>), dim3((unsigned)(P->ld / LAT_WAVE), (unsigned)nsamp),
+                                   dim3(576), 0, stream, B);
         LAT_LAUNCH_CHECK();
         if ((st = zero_rows_past(P, nsamp * P->E, snap, stream)) != LAT_OK) return st;
     }
