@@ -20,6 +20,9 @@ CASES = {
     "bcc_sub": lambda: L.config(2).with_sub((3, 3, 2)),
     "mixed_sub": lambda: L.config(4).with_sub((2, 2, 2)),
     "logmu_sub": lambda: L.config(3).with_sub((2, 2, 2)),
+    # cells of more than 16 elements per edge: the per-node 3D tangent kernel instead of the
+    # node-line sweep (whose kept-element masks hold 4 x 16 slots)
+    "bcc_n18_sub": lambda: L.config(2).with_(nel=18).with_sub((2, 2, 1)),
 }
 
 
