@@ -326,7 +326,9 @@ def main():
                     help="time one FETI-DP tangent solve against MINRES (two levels) on the ROM tangent at the "
                          "affine state of half the --strain load, or after --feti-newton-steps Newton steps")
     ap.add_argument("--feti-newton-steps", type=int, default=0, help="--feti: Newton steps (MINRES) before the solve")
-    ap.add_argument("--feti-inner", type=int, default=8, help="--feti: interface PCG steps")
+    ap.add_argument("--feti-inner", type=int, default=32, help="--feti: interface PCG steps (the cap with --feti-inner-tol)")
+    ap.add_argument("--feti-inner-tol", type=float, default=1e-2,
+                    help="--feti: relative reduction at which the interface PCG stops early (0: fixed steps)")
     ap.add_argument("--feti-enrich", type=int, default=0, help="--feti: enrichment level to start from")
     ap.add_argument("--feti-f32", action="store_true", help="--feti: FP32 local-solve blocks in the preconditioner")
     ap.add_argument("--feti-max-enrich", type=int, default=3, help="--feti: highest enrichment level")
@@ -651,6 +653,7 @@ def feti_main(args):
         t0 = time.perf_counter()
         x, st, info = P.feti_solve(K, n_r, g["alpha"], g["S"], fixed, b, R=g["R"], nu=g["nu"], beta=g["beta"],
                                    n_delta=args.feti_n_delta, inner_it=args.feti_inner, tol=args.solve_tol,
+                                   inner_tol=args.feti_inner_tol,
                                    maxit=600, enrich=args.feti_enrich, prec=B.F32 if args.feti_f32 else B.F64,
                                    max_enrich=max(args.feti_max_enrich, args.feti_enrich))
         torch.cuda.synchronize()
@@ -668,7 +671,7 @@ def feti_main(args):
         "data": "synthetic",
         "config": {"workload": cfg.name, "cells": P.ncells, "global_dofs": P.nglobal * cfg.dim,
                    "load": {"kind": case.kind, "strain": case.strain, "shear": case.shear}, "state": state,
-                   "rb_tol": args.rb_tol, "n_r": n_r, "tol": args.solve_tol, "inner_it": args.feti_inner,
+                   "rb_tol": args.rb_tol, "n_r": n_r, "tol": args.solve_tol, "inner_it": args.feti_inner, "inner_tol": args.feti_inner_tol,
                    "enrich_start": args.feti_enrich, "local_blocks": "f32" if args.feti_f32 else "f64",
                    "n_delta": info["n_delta"], "rhs": "i.i.d. N(0,1)"},
         "feti": {"status": int(st), "iters": info["iters"], "restarts": info["restarts"], "enrich": info["enrich"],

@@ -409,6 +409,10 @@ typedef struct {
                              LAT_F32 (coords = 1; halves their bytes; the operator, the residual and
                              everything else stay FP64) */
     double tol;           /* stop at ||res|| <= tol ||rhs|| (2-norms of the saddle-point system), > 0 */
+    double inner_tol;     /* > 0: the interface sub-solve also stops once its preconditioned residual
+                             r.z has fallen below inner_tol^2 times its start (a relative reduction of
+                             inner_tol), inner_it steps being the cap (one 4-byte host read per step);
+                             0: always inner_it steps.  FGMRES accepts the varying inner solve. */
 } lat_feti_opts;
 
 /* What a solve did (HOST struct). */
@@ -444,7 +448,7 @@ typedef struct {
  * least-squares coordinates of its snapshot in the first n_delta principal snapshots
  * (R[:nd,:nd] delta = nu_s beta^s[:nd]; alpha when nd = n_r or R is NULL), whose combinations of
  * inverses extrapolate and converge far worse in practice.  The assembled coarse problem is inverted in FP64 (LU); the interface block F^-1 is
- * `inner_it` PCG steps on B K~rom^-1 B^T with the Dirichlet preconditioner
+ * `inner_it` PCG steps (fewer when `inner_tol` is met) on B K~rom^-1 B^T with the Dirichlet preconditioner
  * B_D (sum_r delta_r (F_dd^r)^-1) B_D^T, B_D = (B B^T)^-1 B node by node.  A principal remaining
  * block that is not positive definite (Cholesky failure or a pivot <= 1e-12 of its diagonal entry)
  * raises the enrichment level and the setup restarts (Sec. 3.3.2), while the next level adds an
@@ -487,7 +491,8 @@ typedef struct {
     int32_t tangent;        /* 0 = ROM tangent (the method), 1 = every cell's own full-rule tangent
                                (the standard method, for comparison; no greedy) */
     int32_t precond;        /* tangent solve: 0 / 1 = lat_rom_solve's MINRES with its precond 0 / 1;
-                               2 = the inexact FETI-DP solve (lat_feti_solve, ROM tangent only), with
+                               2 = the inexact FETI-DP solve (lat_feti_solve, ROM tangent only; interface
+                               sub-solve to a relative reduction of 1e-2, at most 32 PCG steps), with
                                MINRES (two levels) taking over a step it does not converge on */
     int32_t feti_n_delta;   /* precond 2: lat_feti_opts.n_delta (0 = every principal cell) */
     double rb_tol;          /* greedy tolerance (Algorithm 1), > 0 */

@@ -60,7 +60,7 @@ class FetiOpts(ctypes.Structure):
     _fields_ = [("n_delta", ctypes.c_int32), ("enrich", ctypes.c_int32), ("max_enrich", ctypes.c_int32),
                 ("inner_it", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
                 ("materialize", ctypes.c_int32), ("indefinite", ctypes.c_int32), ("coords", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("prec", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
 
 
 class FetiInfo(ctypes.Structure):
@@ -486,7 +486,7 @@ class Plan:
 
     def feti_solve(self, K, n_r, alpha, S, fixed, b, R=None, nu=None, beta=None, n_delta=0, enrich=0, max_enrich=3,
                    inner_it=8, restart=60, maxit=600, tol=1e-8, materialize=True, indefinite=0, coords=None,
-                   prec=F64, x=None):
+                   prec=F64, x=None, inner_tol=0.0):
         """K~ x = b on the free components by the inexact FETI-DP iteration (lat_feti_solve).
         coords: 1 = nearest principal cell (the default when R, nu, beta are given), 0 = least squares.
         Returns (x, status, info dict); status is LAT_OK, LAT_E_NOCONV or LAT_E_SINGULAR, other
@@ -503,7 +503,7 @@ class Plan:
             _need(t, sz, torch.float64, nm)
         x = self._f64(n) if x is None else x
         o = FetiOpts(int(n_delta), int(enrich), int(max_enrich), int(inner_it), int(restart), int(maxit),
-                     int(bool(materialize)), int(indefinite), int(coords), int(prec), float(tol))
+                     int(bool(materialize)), int(indefinite), int(coords), int(prec), float(tol), float(inner_tol))
         inf = FetiInfo()
         st = _lib().lat_feti_solve(self._p, _ptr(K), int(n_r), _ptr(alpha), _ptr(S), _ptr(R), _ptr(nu), _ptr(beta),
                                    _ptr(fixed), _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(inf), _stream())

@@ -1080,8 +1080,9 @@ __device__ double sum_part(int nb, const double *__restrict__ part)
 
 // PCG scalars of the interface sub-solve
 struct PcgCtl {
-    double rz, alpha, beta;
-    int32_t stop;
+    double rz, alpha, beta, rz0;
+    int32_t stop;     // breakdown (r.z or p.q not positive and finite): no further updates
+    int32_t conv;     // r.z has fallen below tol2 rz0 (the relative inner tolerance)
 };
 
 __global__ void k_pcg_init(int nb, const double *__restrict__ part, PcgCtl *c)
@@ -1089,7 +1090,9 @@ __global__ void k_pcg_init(int nb, const double *__restrict__ part, PcgCtl *c)
     const double rz = sum_part(nb, part);
     if (threadIdx.x == 0) {
         c->rz = rz;
+        c->rz0 = rz;
         c->stop = !(rz > 0.0) || !isfinite(rz);
+        c->conv = 0;
         c->alpha = c->beta = 0.0;
     }
 }
@@ -1103,12 +1106,13 @@ __global__ void k_pcg_alpha(int nb, const double *__restrict__ part, PcgCtl *c)
     }
 }
 
-__global__ void k_pcg_beta(int nb, const double *__restrict__ part, PcgCtl *c)
+__global__ void k_pcg_beta(int nb, const double *__restrict__ part, double tol2, PcgCtl *c)
 {
     const double rz = sum_part(nb, part);
     if (threadIdx.x == 0 && !c->stop) {
         if (!(rz > 0.0) || !isfinite(rz)) { c->stop = 1; c->beta = 0.0; }
         else { c->beta = rz / c->rz; c->rz = rz; }
+        if (tol2 > 0.0 && !(rz > tol2 * c->rz0)) c->conv = 1;
     }
 }
 
@@ -1174,6 +1178,7 @@ struct Feti {
     double *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;
     double *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;   // full-length work vectors
     int inner_it = 0;
+    double inner_tol2 = 0.0;        // squared relative tolerance of the interface sub-solve (0: fixed steps)
     int n_shift = 0;        // principal remaining blocks that are not positive definite
     double max_shift = 0.0; // largest diagonal shift (indef_mode 0)
     int indef_mode = 0;     // 0: shift to definiteness; 1: pivoted-LU inverses, interface by its Dirichlet preconditioner
@@ -1489,7 +1494,16 @@ lat_status fpcg(Feti &f, const double *g, double *x)
         FCHK(dirichlet(f, f.pr, f.pz));
         hipLaunchKernelGGL(k_dot_part, dim3(DOT_BLOCKS), dim3(NB), 0, f.s, n, (const double *)f.pr,
                            (const double *)f.pz, f.part);
-        hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(NB), 0, f.s, DOT_BLOCKS, (const double *)f.part, f.pc);
+        hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(NB), 0, f.s, DOT_BLOCKS, (const double *)f.part, f.inner_tol2,
+                           f.pc);
+        LAT_LAUNCH_CHECK();
+        if (f.inner_tol2 > 0.0) {
+            // relative inner tolerance: stop launching once the sub-solve has converged or broken down
+            int32_t flags[2];
+            LAT_HIP(hipMemcpyAsync(flags, &f.pc->stop, sizeof(flags), hipMemcpyDeviceToHost, f.s));
+            LAT_HIP(hipStreamSynchronize(f.s));
+            if (flags[0] || flags[1]) break;
+        }
         hipLaunchKernelGGL(k_pcg_p, dim3(bl), dim3(NB), 0, f.s, n, (const PcgCtl *)f.pc, (const double *)f.pz, f.pp);
         LAT_LAUNCH_CHECK();
     }
@@ -1863,6 +1877,7 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
     if (n_r < 1 || n_r > P->cap) return LAT_E_SHAPE;
     if (opts->enrich < 0 || opts->max_enrich < opts->enrich || opts->inner_it < 0 || opts->restart < 1 ||
         opts->restart > 512 || opts->maxit < 1 || !(opts->tol > 0.0) || opts->n_delta < 0 || opts->indefinite < 0 ||
+        !(opts->inner_tol >= 0.0) || !std::isfinite(opts->inner_tol) ||
         opts->indefinite > 1 || opts->coords < 0 || opts->coords > 1 || (opts->coords == 1 && !R) ||
         (opts->prec != LAT_F64 && opts->prec != LAT_F32) || (opts->prec == LAT_F32 && opts->coords != 1))
         return LAT_E_ARG;
@@ -1871,6 +1886,7 @@ lat_status lat_feti_solve(const lat_plan *P, const double *K, int32_t n_r, const
     f.P = P; f.s = stream; f.d = P->dim; f.n_r = n_r; f.K = K; f.alpha = alpha;
     f.nd = opts->n_delta == 0 ? n_r : std::min<int>(opts->n_delta, n_r);
     f.inner_it = opts->inner_it;
+    f.inner_tol2 = opts->inner_tol * opts->inner_tol;
     f.indef_mode = opts->indefinite;
     f.coords = opts->coords;
     f.g32 = opts->prec == LAT_F32;

@@ -1284,7 +1284,7 @@ lat_status lat_newton_solve(const lat_plan *P, const double *mu, const double *l
                 // inexact FETI-DP (Sec. 3.3); a solve that stops short (an indefinite tangent) hands
                 // the step to MINRES
                 lat_feti_opts fo{};
-                fo.n_delta = o->feti_n_delta; fo.enrich = 0; fo.max_enrich = 3; fo.inner_it = 8; fo.restart = 60;
+                fo.n_delta = o->feti_n_delta; fo.enrich = 0; fo.max_enrich = 3; fo.inner_it = 32; fo.inner_tol = 1e-2; fo.restart = 60;
                 fo.maxit = std::min(o->cg_maxit, 600); fo.materialize = w.ops != nullptr; fo.indefinite = 0;
                 fo.coords = 1;
                 fo.tol = o->cg_tol;

@@ -132,6 +132,24 @@ def test_solve_matches_direct_solve(graded, n_delta, coords):
     _check_solution(nc, Ko, b, x3, _direct(nc, Ko, b))
 
 
+def test_inner_tolerance(graded):
+    # the interface sub-solve stopping at a relative reduction (cap 32 steps): the same solution
+    nc = graded
+    cfg = nc.cfg
+    u = L.make_displacement(cfg.with_(strain=0.01, pert_amp=1e-3))[nc.orc.g2bg]
+    K, n_r, g, Ko = _rom(nc, u, 1e-4, 16)
+    b = np.random.default_rng(37).standard_normal((nc.P.nglobal, cfg.dim))
+    b_t = torch.from_numpy(b).to(nc.dev)
+    kw = dict(R=g["R"], nu=g["nu"], beta=g["beta"], tol=1e-11, maxit=400)
+    x8, st8, i8 = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, inner_it=8, **kw)
+    xt, stt, it_ = nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, inner_it=32, inner_tol=1e-2, **kw)
+    print(f"[feti] inner 8: {i8['iters']} iterations; inner tol 1e-2 (cap 32): {it_['iters']}", flush=True)
+    assert st8 == stt == nc.B.LAT_OK and it_["relres"] <= 1e-11
+    _check_solution(nc, Ko, b, xt, _direct(nc, Ko, b))
+    with pytest.raises(nc.B.LatError):
+        nc.P.feti_solve(K, n_r, g["alpha"], g["S"], nc.fixed_t, b_t, inner_tol=-1.0, **kw)
+
+
 def test_fp32_local_blocks(graded):
     # the reduced-precision inner apply: FP32 G_r in the preconditioner, FP64 operator and residual;
     # the solution still meets the FP64 tolerance
