@@ -1170,6 +1170,7 @@ struct Feti {
     bool g32 = false;
     double *G = nullptr, *Phi = nullptr, *Spp = nullptr, *Fdd = nullptr, *Sdd = nullptr, *Phid = nullptr;
     double *delta = nullptr, *Sc = nullptr;   // [ld][nd], coarse inverse [nPgd]^2
+    double *cmv = nullptr;                    // chunk partials of the coarse product [nPgd / CMV_W][nPgd]
     // scratch
     double *As = nullptr, *xm = nullptr, *T1 = nullptr, *hl = nullptr, *hP = nullptr, *uP = nullptr, *el = nullptr;
     double *qd = nullptr, *vd = nullptr;
@@ -1257,6 +1258,31 @@ lat_status op_apply(Feti &f, const double *w, double *out)
     return LAT_OK;
 }
 
+// y = A x for the coarse inverse A (n x n, column-major): workgroups of 256 rows x one chunk of CMV_W
+// columns (about a thousand of them for the coarse sizes here, where a library matrix-vector
+// product launches a few dozen and streams the matrix at a tenth of the chip's bandwidth), each
+// thread summing its row over the chunk in column order; k_cmv_sum adds the chunks in order.
+constexpr int CMV_W = 64;
+__global__ __launch_bounds__(256) void k_cmv_part(int64_t n, const double *__restrict__ A, const double *__restrict__ x,
+                                                  double *__restrict__ part)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * CMV_W, j1 = j0 + CMV_W < n ? j0 + CMV_W : n;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t j = j0; j < j1; ++j) s = fma(A[j * n + i], x[j], s);
+    part[(int64_t)blockIdx.y * n + i] = s;
+}
+
+__global__ void k_cmv_sum(int64_t n, int nc, const double *__restrict__ part, double *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s += part[(int64_t)c * n + i];
+    y[i] = s;
+}
+
 // coarse part shared by K~rom^-1 and F~: given t = sum_r delta_r Phi_r^T g (per cell, [nP][ld])
 // in f.T1 layout, h_P = base + assembled, u_P = Sc^-1 h_P, el = gathered u_P
 lat_status coarse_part(Feti &f, const double *base)
@@ -1271,9 +1297,12 @@ lat_status coarse_part(Feti &f, const double *base)
                        f.pd.pg_lane, f.pd.pg_p, f.liveP, f.hl, base, f.hP);
     LAT_LAUNCH_CHECK();
     if (f.nPgd > 0) {
-        const double one = 1.0, zero = 0.0;
-        RBCHK(rocblas_dgemv(f.h, rocblas_operation_none, (rocblas_int)f.nPgd, (rocblas_int)f.nPgd, &one, f.Sc,
-                            (rocblas_int)f.nPgd, f.hP, 1, &zero, f.uP, 1));
+        const int64_t nc = lat_cdiv(f.nPgd, CMV_W);
+        hipLaunchKernelGGL(k_cmv_part, dim3((unsigned)lat_cdiv(f.nPgd, 256), (unsigned)nc), dim3(256), 0, f.s, f.nPgd,
+                           (const double *)f.Sc, (const double *)f.hP, f.cmv);
+        hipLaunchKernelGGL(k_cmv_sum, dim3(blocks(f.nPgd)), dim3(NB), 0, f.s, f.nPgd, (int)nc, (const double *)f.cmv,
+                           f.uP);
+        LAT_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_gather_P, dim3(blocks((int64_t)f.pt.nPn * f.ld)), dim3(NB), 0, f.s, f.d, f.pt.nPn, f.ld,
                        f.pd.prim_g, f.liveP, f.uP, f.el);
@@ -1831,6 +1860,7 @@ lat_status setup_level(Feti &f, FArena &ar, const std::vector<int32_t> &h_l2g, c
     FCHK(ar.get(&f.T1, f.nPr * nd * f.ld));
     FCHK(ar.get(&f.hl, f.nPr * f.ld)); FCHK(ar.get(&f.el, f.nPr * f.ld));
     FCHK(ar.get(&f.hP, f.nPgd)); FCHK(ar.get(&f.uP, f.nPgd));
+    FCHK(ar.get(&f.cmv, std::max<int64_t>(lat_cdiv(f.nPgd, CMV_W) * f.nPgd, 1)));
     FCHK(ar.get(&f.qd, f.nDr * f.ld)); FCHK(ar.get(&f.vd, f.nDr * f.ld));
     FCHK(ar.get(&f.pc, 1));
     FCHK(ar.get(&f.px, f.L)); FCHK(ar.get(&f.pr, f.L)); FCHK(ar.get(&f.pz, f.L)); FCHK(ar.get(&f.pp, f.L));
