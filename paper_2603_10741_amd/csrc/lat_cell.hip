@@ -573,7 +573,9 @@ __global__ __launch_bounds__(576) void k_cell3(CellArgs A)
 // Trilinear shape-function gradients at the 2 x 2 x 2 Gauss points of the unit cube (before the 1/h
 // scaling): g[q][c][J], q = qx + 2 qy + 4 qz, c = cx + 2 cy + 4 cz; and L[m] = sum_q g_a(q) . g_b(q)
 // for corners with a ^ b = m (the sum depends on which axes the corners differ in only: reflecting
-// the cube in an axis maps the Gauss points onto themselves).
+// the cube in an axis maps the Gauss points onto themselves).  The node-line kernel reads L; it forms
+// the gradients themselves from the 1D coordinates (the same products, so the same values), which
+// keeps them out of the scalar registers.
 struct G3Table {
     double g[8][8][3];
     double L[8];
@@ -682,6 +684,14 @@ __global__ __launch_bounds__(512) void k_tan3(CellArgs A)
         // the accumulation waves read the previous element from LDS; between two barriers they are
         // written to LDS.  The next element's corner displacements are loaded before that.
         const int gw = w - 4;
+        // 1D Gauss coordinates (1/2 -+ 1/(2 sqrt 3)) of this wave's points in x and y, and the
+        // products phi_x phi_y of the gradients' z components (the same for both points)
+        constexpr double GX0 = 0.21132486540518711775, GX1 = 0.78867513459481288225;
+        const double px1 = (gw & 1) ? GX1 : GX0, px0 = 1.0 - px1;
+        const double py1 = (gw >> 1) ? GX1 : GX0, py0 = 1.0 - py1;
+        double Cxy[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Cxy[t] = ((t & 1) ? px1 : px0) * ((t >> 1) ? py1 : py0);
         uint64_t m = pmask;
         double u[8][3];
         auto load_u = [&](int sl) __attribute__((always_inline)) {
@@ -703,20 +713,46 @@ __global__ __launch_bounds__(512) void k_tan3(CellArgs A)
             const int dy = sl & 1, dz = (sl >> 1) & 1;
             const int kA = 2 * (1 - dy) + 4 * (1 - dz);          // corner of node x = ex (x = ex + 1: kA + 1)
             const double wk = ((kmask >> sl) & 1) ? wq : 0.0;
+            // corner differences along each axis, shared by the two points: dX[y + 2z] = u(1,y,z) - u(0,y,z), ...
+            double dX[4][3], dY[4][3], dZ[4][3];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int t0 = t & 1, t1 = t >> 1;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    dX[t][i] = u[1 + 2 * t0 + 4 * t1][i] - u[2 * t0 + 4 * t1][i];
+                    dY[t][i] = u[t0 + 2 + 4 * t1][i] - u[t0 + 4 * t1][i];
+                    dZ[t][i] = u[t0 + 2 * t1 + 4][i] - u[t0 + 2 * t1][i];
+                }
+            }
+            const int ay = 1 - dy, az = 1 - dz;                  // the line's corner bits in the element
             double out[2][PV];
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
-                const int q = gw + 4 * h2;
+                // gradients at point (qx, qy, qz) = (gw & 1, gw >> 1, h2): for corner c = x + 2y + 4z,
+                // ghat_c = (s(x) Ayz[y + 2z], s(y) B[x + 2z], s(z) Cxy[x + 2y]), s(b) = b ? 1 : -1,
+                // Ayz = phi_y phi_z, Bxz = phi_x phi_z, Cxy = phi_x phi_y (the products in the table's order)
+                const double pz1 = h2 ? GX1 : GX0, pz0 = 1.0 - pz1;
+                double Ayz[4], Bxz[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    Ayz[t] = ((t & 1) ? py1 : py0) * ((t >> 1) ? pz1 : pz0);
+                    Bxz[t] = ((t & 1) ? px1 : px0) * ((t >> 1) ? pz1 : pz0);
+                }
                 double F[3][3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
+                for (int i = 0; i < 3; ++i) {
+                    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
 #pragma unroll
-                    for (int J = 0; J < 3; ++J) {
-                        double g = 0.0;
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) g = fma(u[c][i], c_g3.g[q][c][J], g);
-                        F[i][J] = i == J ? fma(invh, g, 1.0) : invh * g;
+                    for (int t = 0; t < 4; ++t) {
+                        g0 = fma(Ayz[t], dX[t][i], g0);
+                        g1 = fma(Bxz[t], dY[t][i], g1);
+                        g2 = fma(Cxy[t], dZ[t][i], g2);
                     }
+                    F[i][0] = i == 0 ? fma(invh, g0, 1.0) : invh * g0;
+                    F[i][1] = i == 1 ? fma(invh, g1, 1.0) : invh * g1;
+                    F[i][2] = i == 2 ? fma(invh, g2, 1.0) : invh * g2;
+                }
                 // cofactors and J with every product-sum fused explicitly: the full and the sampled sweeps
                 // then round identically whatever else the compiler sees around them
                 double C[3][3];
@@ -734,22 +770,34 @@ __global__ __launch_bounds__(512) void k_tan3(CellArgs A)
                 if (Jd > 0.0 && isfinite(Jd)) lnJ = log(Jd);
                 else if (wk != 0.0) lat_flag(A.st, isfinite(Jd) ? LAT_E_INVERTED : LAT_E_NONFINITE, cell);
                 const double rh = invh / Jd;                            // p_c = (C / J)(ghat_c / h)
+                double Ch[3][3];
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) Ch[i][J] = C[i][J] * rh;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+                    const double g0 = cx ? Ayz[cy + 2 * cz] : -Ayz[cy + 2 * cz];
+                    const double g1 = cy ? Bxz[cx + 2 * cz] : -Bxz[cx + 2 * cz];
+                    const double g2 = cz ? Cxy[cx + 2 * cy] : -Cxy[cx + 2 * cy];
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
-                        out[h2][(c & 1) * 12 + (c >> 1) * 3 + i] =
-                            fma(C[i][0], c_g3.g[q][c][0], fma(C[i][1], c_g3.g[q][c][1], C[i][2] * c_g3.g[q][c][2])) * rh;
+                        out[h2][cx * 12 + (c >> 1) * 3 + i] = fma(Ch[i][0], g0, fma(Ch[i][1], g1, Ch[i][2] * g2));
+                }
                 out[h2][24] = wk * fma(-lam, lnJ, mu);
                 if (forces) {
-                    // force terms of the two line nodes: w P g_a = w (mu (F g_a - p_a) + lam ln J p_a)
+                    // force terms of the two line nodes (corners x + 2 ay + 4 az, x = 0, 1):
+                    // w P g_a = w (mu (F g_a - p_a) + lam ln J p_a)
+                    const double Aa = az ? (ay ? Ayz[3] : Ayz[2]) : (ay ? Ayz[1] : Ayz[0]);
 #pragma unroll
                     for (int x = 0; x < 2; ++x) {
-                        const int ka = kA + x;
-                        const double g0 = c_g3.g[q][ka][0], g1 = c_g3.g[q][ka][1], g2 = c_g3.g[q][ka][2];
+                        const double Ba = az ? Bxz[x + 2] : Bxz[x];
+                        const double Ca = ay ? Cxy[x + 2] : Cxy[x];
+                        const double g0 = x ? Aa : -Aa, g1 = ay ? Ba : -Ba, g2 = az ? Ca : -Ca;
 #pragma unroll
                         for (int i = 0; i < 3; ++i) {
-                            const double pa = fma(C[i][0], g0, fma(C[i][1], g1, C[i][2] * g2)) * rh;   // p of corner ka
+                            const double pa = fma(Ch[i][0], g0, fma(Ch[i][1], g1, Ch[i][2] * g2));
                             const double Fg = invh * fma(F[i][0], g0, fma(F[i][1], g1, F[i][2] * g2));
                             out[h2][25 + 3 * x + i] = wk * fma(mu, Fg - pa, lam * lnJ * pa);
                         }
