@@ -526,7 +526,13 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 //     2w, 2w+1 (X masked to owned neighbour DOFs).
 // Both LDS buffers are double-buffered (33 KB each for 64 principal cells), so one barrier per
 // step suffices and two workgroups fit on a CU.
+// Node order: each XCD takes one contiguous eighth of the runs, in bands of APPLY3_BAND workgroups
+// (what one XCD holds at once); a band covers the packed nodes of its runs and its workgroup j
+// takes nodes j, j + nb, j + 2 nb, ... of them (nb = workgroups in the band), so the nodes in
+// flight on an XCD at any moment are one compact stretch whose shared neighbour X blocks meet in
+// its L2.
 constexpr int APPLY3_RUN = 16;
+constexpr int APPLY3_BAND = 32;
 
 template <int NR, int MODE, int LP>
 __global__ __launch_bounds__(512) void k_apply3d_mfma(
@@ -553,22 +559,27 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     if (A.gate && *A.gate == 0) return;                  // a refinement pass that is not needed
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int l = threadIdx.x & 63, tid = threadIdx.x;
-    const int run = lat_xcd_block(blockIdx.x, gridDim.x);
-    const int q0 = run * APPLY3_RUN;
-    const int q1 = min(npacked, q0 + APPLY3_RUN);
-    if (q0 >= q1) return;
+    // XCD x (blocks b with b % 8 == x) owns the runs [rx0, rx0 + nrx); its s-th block is in band
+    // s / APPLY3_BAND of them
+    const int ng = (int)gridDim.x, x8 = (int)blockIdx.x & 7, s8 = (int)blockIdx.x >> 3;
+    const int rx0 = x8 * (ng >> 3) + min(x8, ng & 7), nrx = (ng >> 3) + (x8 < (ng & 7) ? 1 : 0);
+    const int bnd = s8 / APPLY3_BAND;
+    const int qs = min(APPLY3_BAND, nrx - bnd * APPLY3_BAND);              // node stride
+    const int qb = (rx0 + bnd * APPLY3_BAND) * APPLY3_RUN + s8 % APPLY3_BAND; // first node of this workgroup
+    if (qb >= npacked) return;
+    const int cnt = min(APPLY3_RUN, (npacked - qb + qs - 1) / qs);       // nodes qb + qs t, t < cnt
     const int nn = A.nn, m = A.m, cap = A.cap;
     const int ct = w & 3, et = w >> 2;                   // formation tile of this wave
     const int r0 = A.rb + 2 * w;                         // this wave's right-hand sides (apply)
     const int nrw = max(0, min(2, A.mc - 2 * w));
-    const int nsl = (q1 - q0) * NSL;
+    const int nsl = cnt * NSL;
     const int ssamp = SAMPLE && A.errp ? nsl / 2 : -1;
-    // ---- principal block slice sl (node q0 + sl / 9, offsets 3 (sl % 9) ..): coalesced fetch
+    // ---- principal block slice sl (node t = sl / 9, offsets 3 (sl % 9) ..): coalesced fetch
     double kpre[SPT];
     bool kval[SPT];
     auto fetch = [&](int sl) __attribute__((always_inline)) {
         const bool live = sl < nsl;
-        const int a = live ? unode[q0 + sl / NSL] : 0;
+        const int a = live ? unode[qb + qs * (sl / NSL)] : 0;
         const int h = sl % NSL;
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
@@ -607,9 +618,9 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
             }
         }
     };
-    // neighbour table of node q, one offset per lane: packed index and owner mask
-    auto nbr_load = [&](int q, int &nbv, uint32_t &mlo, uint32_t &mhi) __attribute__((always_inline)) {
-        nbv = (q < q1 && l < NO) ? unbr[(int64_t)q * NO + l] : -1;
+    // neighbour table of the workgroup's node t, one offset per lane: packed index and owner mask
+    auto nbr_load = [&](int t, int &nbv, uint32_t &mlo, uint32_t &mhi) __attribute__((always_inline)) {
+        nbv = (t < cnt && l < NO) ? unbr[(int64_t)(qb + qs * t) * NO + l] : -1;
         const uint64_t mk = nbv >= 0 ? umask[nbv] : 0ull;
         mlo = (uint32_t)mk;
         mhi = (uint32_t)(mk >> 32);
@@ -620,7 +631,7 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     lat_bf16x8 cB[NLV][NKB];
     int nbv, nbv_n;
     uint32_t mlo, mhi, mlo_n, mhi_n;
-    nbr_load(q0, nbv, mlo, mhi);
+    nbr_load(0, nbv, mlo, mhi);
     // X of a slice's three neighbour nodes for this wave's right-hand sides (raw), issued one
     // slice step before it is used
     double xn[3][3][2];
@@ -649,7 +660,8 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
     store(0, 0);
     fetch(1);
     __syncthreads();
-    for (int q = q0; q < q1; ++q) {
+    for (int q = qb; q < qb + qs * cnt; q += qs) {
+        const int t = (q - qb) / qs;
         const int g = qgroup[q];
         if (g != gcur) {                                 // alpha of this group as the B operand
             gcur = g;
@@ -676,13 +688,13 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
                 }
             }
         }
-        nbr_load(q + 1, nbv_n, mlo_n, mhi_n);            // next node's table, used one node later
+        nbr_load(t + 1, nbv_n, mlo_n, mhi_n);            // next node's table, used one node later
         double acc[3][2];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int r = 0; r < 2; ++r) acc[i][r] = 0.0;
-        const int sl0 = (q - q0) * NSL;
+        const int sl0 = t * NSL;
 #pragma unroll
         for (int h = 0; h < NSL; ++h) {
             const int buf = (sl0 + h) & 1;
@@ -785,7 +797,7 @@ __global__ __launch_bounds__(512) void k_apply3d_mfma(
         // the sampled slice once more in FP64 (output rows l / 16 + 4 r): each wave its formation tile,
         // against the reduced-precision values kept in kts; rows past the slice's 27 entries are padding
         __syncthreads();
-        const int gs = qgroup[q0 + ssamp / NSL];
+        const int gs = qgroup[qb + qs * (ssamp / NSL)];
         const int c16 = ct * 16 + (l & 15);
         v4d c = {0.0, 0.0, 0.0, 0.0};
         const double *pa = &kb64[(16 * et + (l & 15)) * KR + (l >> 4)];
