@@ -140,51 +140,117 @@ __global__ void k_sqrt(int64_t ld, const double *__restrict__ sq, double *__rest
     if (p < ld) nu[p] = sqrt(sq[p]);
 }
 
-// beta partials: Delta . zeta
+// Lagged residuals.  Iteration it works on Delta^(it) = Delta^(f) - sum_{k=f}^{it-1} beta_k zeta_k^T,
+// f = it - it % LAT_GREEDY_LAG: T holds Delta^(f) and the NP = it - f pending updates are replayed
+// on load, x = fma(-beta_k, zeta_k[j], x) for k = f, f+1, ..., exactly the operations the
+// eager update would have applied one pass at a time, so every value is the eager one bit for
+// bit.  Only the update that completes a multiple of LAT_GREEDY_LAG writes Delta back: a pass
+// reads T once and writes it one iteration in LAT_GREEDY_LAG.
+template <int NP>
+struct Lag {
+    double nb[NP > 0 ? NP : 1];
+    const double *z[NP > 0 ? NP : 1];
+    __device__ __forceinline__ Lag(const double *__restrict__ zring, int64_t nsnap, int f,
+                                   const double *__restrict__ beta_pl, int64_t bstride, int64_t p)
+    {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            nb[k] = -beta_pl[p * bstride + f + k];
+            z[k] = zring + (int64_t)((f + k) % LAT_GREEDY_LAG) * nsnap;
+        }
+    }
+    __device__ __forceinline__ double replay(double x, int64_t j) const
+    {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) x = fma(nb[k], z[k][j], x);
+        return x;
+    }
+};
+
+// beta partials: Delta^(it) . zeta_it, it = f + NP
+template <int NP>
 __global__ __launch_bounds__(256) void k_dot(const double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
-                                             const double *__restrict__ zeta, const int32_t *__restrict__ ictl,
-                                             double *__restrict__ pdot)
+                                             const double *__restrict__ zring, int f,
+                                             const double *__restrict__ beta_pl, int64_t bstride,
+                                             const int32_t *__restrict__ ictl, double *__restrict__ pdot)
 {
     if (ictl[C_DONE]) return;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t b = chunk_id();
     if (p >= ld || b >= nchunk) return;
     const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
+    const Lag<NP> lag(zring, nsnap, f, beta_pl, bstride, p);
+    const double *__restrict__ zeta = zring + (int64_t)((f + NP) % LAT_GREEDY_LAG) * nsnap;
     double s = 0.0;
     #pragma unroll 16
-    for (int64_t j = j0; j < j1; ++j) s = fma(T[j * ld + p], zeta[j], s);
+    for (int64_t j = j0; j < j1; ++j) s = fma(lag.replay(T[j * ld + p], j), zeta[j], s);
     pdot[b * ld + p] = s;
 }
 
-// Delta <- Delta - beta zeta, with sq / inf partials of the updated Delta (batched like k_normalize)
+// Delta^(it+1) = Delta^(it) - beta_it zeta_it (it = f + NP) with its sq / inf partials; WB: written
+// back (it + 1 a multiple of LAT_GREEDY_LAG; batched like k_normalize), else only measured
+template <int NP, bool WB>
 __global__ __launch_bounds__(256) void k_update(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
-                                                const double *__restrict__ zeta, const double *__restrict__ beta,
-                                                int64_t bstride, const int32_t *__restrict__ ictl,
-                                                double *__restrict__ psq, double *__restrict__ pinf)
+                                                const double *__restrict__ zring, int f,
+                                                const double *__restrict__ beta_pl, int64_t bstride,
+                                                const int32_t *__restrict__ ictl, double *__restrict__ psq,
+                                                double *__restrict__ pinf)
 {
     if (ictl[C_DONE]) return;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t b = chunk_id();
     if (p >= ld || b >= nchunk) return;
     const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
-    const double nb = -beta[p * bstride];
+    const Lag<NP> lag(zring, nsnap, f, beta_pl, bstride, p);
+    const double *__restrict__ zeta = zring + (int64_t)((f + NP) % LAT_GREEDY_LAG) * nsnap;
+    const double nb = -beta_pl[p * bstride + f + NP];
     double s = 0.0, m = 0.0;
-    for (int64_t jb = j0; jb < j1; jb += GB) {
-        double v[GB];
+    if (WB) {
+        for (int64_t jb = j0; jb < j1; jb += GB) {
+            double v[GB];
 #pragma unroll
-        for (int t = 0; t < GB; ++t) v[t] = jb + t < j1 ? T[(jb + t) * ld + p] : 0.0;
+            for (int t = 0; t < GB; ++t) v[t] = jb + t < j1 ? T[(jb + t) * ld + p] : 0.0;
 #pragma unroll
-        for (int t = 0; t < GB; ++t) {
-            if (jb + t < j1) {
-                const double x = fma(nb, zeta[jb + t], v[t]);
-                T[(jb + t) * ld + p] = x;
-                s = fma(x, x, s);
-                m = fmax(m, fabs(x));
+            for (int t = 0; t < GB; ++t) {
+                if (jb + t < j1) {
+                    const double x = fma(nb, zeta[jb + t], lag.replay(v[t], jb + t));
+                    T[(jb + t) * ld + p] = x;
+                    s = fma(x, x, s);
+                    m = fmax(m, fabs(x));
+                }
             }
+        }
+    } else {
+        #pragma unroll 16
+        for (int64_t j = j0; j < j1; ++j) {
+            const double x = fma(nb, zeta[j], lag.replay(T[j * ld + p], j));
+            s = fma(x, x, s);
+            m = fmax(m, fabs(x));
         }
     }
     psq[b * ld + p] = s;
     pinf[b * ld + p] = m;
+}
+
+// After the loop: the updates still pending at exit (n_r - f of them, f = n_r - n_r % LAT_GREEDY_LAG)
+// go into T, so that T holds Delta^(n_r) as the eager loop leaves it
+__global__ __launch_bounds__(256) void k_flush(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
+                                               const double *__restrict__ zring, const double *__restrict__ beta_pl,
+                                               int64_t bstride, const int32_t *__restrict__ ictl)
+{
+    const int nr = ictl[C_NR];
+    const int f = nr - nr % LAT_GREEDY_LAG, np = nr - f;
+    if (np == 0) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = chunk_id();
+    if (p >= ld || b >= nchunk) return;
+    const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
+    for (int64_t j = j0; j < j1; ++j) {
+        double x = T[j * ld + p];
+        for (int k = 0; k < np; ++k)
+            x = fma(-beta_pl[p * bstride + f + k], zring[(int64_t)((f + k) % LAT_GREEDY_LAG) * nsnap + j], x);
+        T[j * ld + p] = x;
+    }
 }
 
 // Arg-max of the inf-norms over the lanes (ties -> lowest canonical cell), stop test, and the
@@ -242,15 +308,20 @@ __global__ __launch_bounds__(1024) void k_select(int64_t ld, const int32_t *__re
     }
 }
 
-// zeta_i = Delta^{s_i} / ||Delta^{s_i}||_2  (and the basis row Z[i])
+// zeta_it = Delta^(it)[:, s_it] / ||Delta^(it)[:, s_it]||_2 (it = f + NP; the column replays the
+// pending updates like the passes) into its ring slot, and the basis row Z[it]
+template <int NP>
 __global__ void k_zeta(const double *__restrict__ T, int64_t nsnap, int64_t ld, const int32_t *__restrict__ ictl,
-                       const double *__restrict__ dctl, double *__restrict__ zeta, double *__restrict__ Zrow)
+                       const double *__restrict__ dctl, double *__restrict__ zring, int f,
+                       const double *__restrict__ beta_pl, int64_t bstride, double *__restrict__ Zrow)
 {
     if (ictl[C_DONE]) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nsnap) return;
-    const double z = T[j * ld + ictl[C_SEL]] / dctl[D_RHO];
-    zeta[j] = z;
+    const int64_t sel = ictl[C_SEL];
+    const Lag<NP> lag(zring, nsnap, f, beta_pl, bstride, sel);
+    const double z = lag.replay(T[j * ld + sel], j) / dctl[D_RHO];
+    zring[(int64_t)((f + NP) % LAT_GREEDY_LAG) * nsnap + j] = z;
     if (Zrow) Zrow[j] = z;
 }
 
@@ -423,19 +494,38 @@ extern "C" lat_status lat_select_principal_rows(const lat_plan *Pp, double *snap
                            P->ictl, P->dctl, S, n_r, dev_status);
         LAT_LAUNCH_CHECK();
         if (it == cap) break;
-        hipLaunchKernelGGL(k_zeta, dim3((unsigned)lat_cdiv(ns, 256)), dim3(256), 0, stream, snap, ns, ld, P->ictl,
-                           P->dctl, P->zeta, Z ? Z + (int64_t)it * P->nsnap : nullptr);
-        hipLaunchKernelGGL(k_dot, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->ictl, P->g_dot);
+        static_assert(LAT_GREEDY_LAG == 8, "the pass dispatch below covers 0..7 pending updates");
+        const int np = it % LAT_GREEDY_LAG, f = it - np;
+        const bool wb = np == LAT_GREEDY_LAG - 1;
+        double *zrow = Z ? Z + (int64_t)it * P->nsnap : nullptr;
+#define LAGGED(NPV)                                                                                                    \
+    case NPV:                                                                                                          \
+        hipLaunchKernelGGL(k_zeta<NPV>, dim3((unsigned)lat_cdiv(ns, 256)), dim3(256), 0, stream, snap, ns, ld, P->ictl, \
+                           P->dctl, P->zeta, f, P->beta_pl, P->cap, zrow);                                             \
+        hipLaunchKernelGGL(k_dot<NPV>, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, f, P->beta_pl, P->cap,    \
+                           P->ictl, P->g_dot);                                                                          \
+        break;
+        switch (np) { LAGGED(0) LAGGED(1) LAGGED(2) LAGGED(3) LAGGED(4) LAGGED(5) LAGGED(6) LAGGED(7) }
+#undef LAGGED
         LAT_LAUNCH_CHECK();
         // beta_i lands directly in its column of the plan-order coordinate matrix
         if ((st = tree2(P->g_dot, 0, P->beta_pl, P->cap, it, nullptr, 0, nullptr, nc, ld, P->g_t1, P->g_t2, nullptr,
                         nullptr, P->ictl + C_DONE, stream)) != LAT_OK) return st;
-        hipLaunchKernelGGL(k_update, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->beta_pl + it, P->cap,
-                           P->ictl, P->g_sq, P->g_inf);
+#define LAGGED(NPV)                                                                                                    \
+    case NPV:                                                                                                          \
+        if (wb) hipLaunchKernelGGL((k_update<NPV, true>), cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, f,     \
+                                   P->beta_pl, P->cap, P->ictl, P->g_sq, P->g_inf);                                    \
+        else hipLaunchKernelGGL((k_update<NPV, false>), cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, f,       \
+                                P->beta_pl, P->cap, P->ictl, P->g_sq, P->g_inf);                                       \
+        break;
+        switch (np) { LAGGED(0) LAGGED(1) LAGGED(2) LAGGED(3) LAGGED(4) LAGGED(5) LAGGED(6) LAGGED(7) }
+#undef LAGGED
         LAT_LAUNCH_CHECK();
         if ((st = tree2(P->g_sq, 0, P->v_sq, 1, 0, P->g_inf, 1, P->v_inf, nc, ld, P->g_t1, P->g_t2, P->g_t3, P->g_t4,
                         P->ictl + C_DONE, stream)) != LAT_OK) return st;
     }
+    hipLaunchKernelGGL(k_flush, cg, dim3(256), 0, stream, snap, ns, ld, nc, P->zeta, P->beta_pl, P->cap, P->ictl);
+    LAT_LAUNCH_CHECK();
     // R, alpha (canonical order), beta, nu, achieved
     hipLaunchKernelGGL(k_build_R, dim3((unsigned)P->cap), dim3(64), 0, stream, P->cap, P->cap, P->ictl, S, P->lane,
                        P->v_nu, P->beta_pl, R);

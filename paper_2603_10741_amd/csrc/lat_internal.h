@@ -14,6 +14,10 @@
 #define LAT_TREE 256           // rows reduced per tree-kernel launch
 #define LAT_MAX_CAP 64
 
+// The greedy writes its residuals back every LAT_GREEDY_LAG iterations; the passes in between
+// replay the pending updates on load (the basis rows they need are kept in a ring of this length).
+constexpr int LAT_GREEDY_LAG = 8;
+
 struct lat_plan {
     int dim, nel, nn, nloc, nelem, no, E, nc;
     int ncell[3];
@@ -52,7 +56,7 @@ struct lat_plan {
     double *g_t3 = nullptr, *g_t4 = nullptr;   // second-array tree scratch
     double *v_sq = nullptr, *v_inf = nullptr, *v_beta = nullptr, *v_nu = nullptr;   // [ld]
     double *beta_pl = nullptr;     // [ld][cap] plan-order coordinates
-    double *zeta = nullptr;        // [nsnap]
+    double *zeta = nullptr;        // [LAT_GREEDY_LAG][nsnap] ring of the latest basis rows
     int32_t *ictl = nullptr;       // small control block: done, sel lane, n_r, ...
     double *dctl = nullptr;        // rho, achieved, ...
     double *form_part = nullptr;   // [napc][ld][cap] adjoint form partials

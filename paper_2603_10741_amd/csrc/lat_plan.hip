@@ -393,7 +393,7 @@ int ws_items(const lat_plan *P, lat_plan *V, int call, WsItem *it)
         add(&V->v_beta, ld, 8, 0);
         add(&V->v_nu, ld, 8, 0);
         add(&V->beta_pl, ld * cap, 8, 0);
-        add(&V->zeta, P->nsnap, 8, 0);
+        add(&V->zeta, LAT_GREEDY_LAG * P->nsnap, 8, 0);
         add(&V->ictl, 64, 4, 0);
         add(&V->dctl, 64, 8, 0);
         break;
@@ -655,7 +655,7 @@ lat_status lat_plan_create(int32_t dim, const int32_t ncell[3], int32_t nel, con
     ALLOC(P->g_t4, tree_elems);
     ALLOC(P->v_sq, ld); ALLOC(P->v_inf, ld); ALLOC(P->v_beta, ld); ALLOC(P->v_nu, ld);
     ALLOC(P->beta_pl, ld * cap);
-    ALLOC(P->zeta, P->nsnap);
+    ALLOC(P->zeta, LAT_GREEDY_LAG * P->nsnap);
     ALLOC(P->ictl, 64);
     ALLOC(P->dctl, 64);
     ALLOC(P->form_part, (int64_t)P->napc * ld * cap);
