@@ -234,10 +234,27 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ T, int64_t 
 
 // After the loop: the updates still pending at exit (n_r - f of them, f = n_r - n_r % LAT_GREEDY_LAG)
 // go into T, so that T holds Delta^(n_r) as the eager loop leaves it
+template <int NP>
+__device__ __forceinline__ void flush_rows(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t j0, int64_t j1,
+                                           int64_t p, const double *__restrict__ zring, int f,
+                                           const double *__restrict__ beta_pl, int64_t bstride)
+{
+    const Lag<NP> lag(zring, nsnap, f, beta_pl, bstride, p);
+    for (int64_t jb = j0; jb < j1; jb += GB) {
+        double v[GB];
+#pragma unroll
+        for (int t = 0; t < GB; ++t) v[t] = jb + t < j1 ? T[(jb + t) * ld + p] : 0.0;
+#pragma unroll
+        for (int t = 0; t < GB; ++t)
+            if (jb + t < j1) T[(jb + t) * ld + p] = lag.replay(v[t], jb + t);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_flush(double *__restrict__ T, int64_t nsnap, int64_t ld, int64_t nchunk,
                                                const double *__restrict__ zring, const double *__restrict__ beta_pl,
                                                int64_t bstride, const int32_t *__restrict__ ictl)
 {
+    static_assert(LAT_GREEDY_LAG == 8, "the cases below cover 1..7 pending updates");
     const int nr = ictl[C_NR];
     const int f = nr - nr % LAT_GREEDY_LAG, np = nr - f;
     if (np == 0) return;
@@ -245,11 +262,14 @@ __global__ __launch_bounds__(256) void k_flush(double *__restrict__ T, int64_t n
     const int64_t b = chunk_id();
     if (p >= ld || b >= nchunk) return;
     const int64_t j0 = b * LAT_CHUNK, j1 = j0 + LAT_CHUNK < nsnap ? j0 + LAT_CHUNK : nsnap;
-    for (int64_t j = j0; j < j1; ++j) {
-        double x = T[j * ld + p];
-        for (int k = 0; k < np; ++k)
-            x = fma(-beta_pl[p * bstride + f + k], zring[(int64_t)((f + k) % LAT_GREEDY_LAG) * nsnap + j], x);
-        T[j * ld + p] = x;
+    switch (np) {
+    case 1: flush_rows<1>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
+    case 2: flush_rows<2>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
+    case 3: flush_rows<3>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
+    case 4: flush_rows<4>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
+    case 5: flush_rows<5>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
+    case 6: flush_rows<6>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
+    default: flush_rows<7>(T, nsnap, ld, j0, j1, p, zring, f, beta_pl, bstride); break;
     }
 }
 
