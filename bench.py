@@ -117,6 +117,20 @@ def cpu_baseline(cfg, keep, mu, lam, u_bg, X, budget_s=12.0):
         {"S": g["S"], "n_r": g["n_r"]}
 
 
+
+def adjoint_roof(nbytes, nflops, t):
+    """Roofline of the adjoint stage against the nearer of its two roofs: HBM for its algorithmic
+    bytes, the FP64 matrix cores for its dense contractions; the other fraction rides along."""
+    f_hbm = nbytes / t / 1e9 / HBM_PEAK_GBS
+    f_mfma = nflops / t / 1e12 / FP64_MFMA_PEAK_TF
+    if f_mfma > f_hbm:
+        return {"bound": "mfma", "achieved": round(nflops / t / 1e12, 2), "peak": FP64_MFMA_PEAK_TF, "unit": "TFLOP/s",
+                "frac": round(f_mfma, 4), "algorithmic_flops": int(nflops), "hbm_frac": round(f_hbm, 4),
+                "algorithmic_bytes": int(nbytes)}
+    return {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(f_hbm, 4), "algorithmic_bytes": int(nbytes), "mfma_frac": round(f_mfma, 4),
+            "algorithmic_flops": int(nflops)}
+
 def apply_stage(index, m=16, reps=10, cpu_budget=4.0, sample_n=12, seed=7):
     """Apply-stage record of one workload (outside the timed steps of the main line): after
     snapshots, greedy and principal tangents, the ROM apply in FP64 and with bf16 slices (two
@@ -233,6 +247,10 @@ def apply_stage(index, m=16, reps=10, cpu_budget=4.0, sample_n=12, seed=7):
     b_rom = 16.0 * dofs_rhs + stack_b
     b_plain = 16.0 * dofs_rhs + 8.0 * E * lane_nodes
     b_adj = 24.0 * dofs_rhs + 3 * stack_b
+    # the adjoint's dense work: the transposed apply's combination and application, the products
+    # W = X * Ybar summed over the right-hand sides (2 m flops per snapshot entry of a cell) and the
+    # three stacks' contractions of W (2 N_r flops per entry each)
+    adj_flops = flops + 2.0 * E * m * lane_nodes + 3 * 2.0 * E * n_r * lane_nodes
     t = {k: v * 1e-3 for k, v in ms.items()}
     gd = {k: round(dofs_rhs / t[k] / 1e9, 3) for k in calls}
     roof = {
@@ -245,9 +263,7 @@ def apply_stage(index, m=16, reps=10, cpu_budget=4.0, sample_n=12, seed=7):
         "plain_f64": {"bound": "hbm", "achieved": round(b_plain / t["plain_f64"] / 1e9, 1), "peak": HBM_PEAK_GBS,
                       "unit": "GB/s", "frac": round(b_plain / t["plain_f64"] / 1e9 / HBM_PEAK_GBS, 4),
                       "algorithmic_bytes": int(b_plain)},
-        "adjoint_f64": {"bound": "hbm", "achieved": round(b_adj / t["adjoint_f64"] / 1e9, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(b_adj / t["adjoint_f64"] / 1e9 / HBM_PEAK_GBS, 4),
-                        "algorithmic_bytes": int(b_adj)},
+        "adjoint_f64": adjoint_roof(b_adj, adj_flops, t["adjoint_f64"]),
         # the snapshot matrix written once (8 B per stencil entry per cell) is the tangent's floor
         "residual_tangent": {"bound": "hbm", "achieved": round(8.0 * P.nsnap * P.ncells / t["residual_tangent"] / 1e9, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -459,6 +475,12 @@ def main():
     t_adj = ms_stage["adjoint"] * 1e-3
     adj_bytes = (24.0 * dofs_rhs + 3 * 8.0 * P.nloc * P.E * n_r + 8.0 * P.ncells * n_r
                  + 3 * 8.0 * P.nsnap * P.ncells + 8.0 * n_r * P.nsnap + 2 * 8.0 * P.nloc * cfg.dim * P.ncells)
+    # and its dense work over the active snapshot entries (E per active lane-node): the transposed
+    # apply's combination and application, W = X * Ybar over the right-hand sides, the three stacks'
+    # contractions of W and the coefficient adjoint's four row contractions (Z^T T^mu, Z^T T^lam,
+    # Delta^T T^mu_S, Delta^T T^lam_S), 2 N_r flops per entry each
+    adj_ent = P.E * active_dofs / cfg.dim
+    adj_flops = 2.0 * adj_ent * (n_r + m) + 2.0 * adj_ent * m + 7 * 2.0 * adj_ent * n_r
 
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 8
@@ -552,11 +574,9 @@ def main():
                      "kernel": ("k_apply2d_rw<2,32,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
                      + " (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(alg_bytes)},
         "cpu_baseline": cpu,
-        "adjoint_roofline": {"bound": "hbm", "achieved": round(adj_bytes / t_adj / 1e9, 1), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": round(adj_bytes / t_adj / 1e9 / HBM_PEAK_GBS, 4),
-                             "algorithmic_bytes": int(adj_bytes), "ms": round(ms_stage["adjoint"], 4),
-                             "stage": "ROM apply adjoint (Xbar, alpha_bar, mu/lam through the principal "
-                                      "tangents) + coefficient adjoint + residual adjoint"},
+        "adjoint_roofline": dict(adjoint_roof(adj_bytes, adj_flops, t_adj), ms=round(ms_stage["adjoint"], 4),
+                                 stage="ROM apply adjoint (Xbar, alpha_bar, mu/lam through the principal "
+                                       "tangents) + coefficient adjoint + residual adjoint"),
         "plain_apply_gdofs": round(dofs_rhs / t_plain / 1e9, 3),
         "rom_over_plain_speedup": round(t_plain / t_apply, 3),
         "reduced_precision": {"kernel": ("k_apply2d_rw" if cfg.dim == 2 else "k_apply3d_mfma")
