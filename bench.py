@@ -468,6 +468,18 @@ def main():
     alg_bytes = 16.0 * dofs_rhs + 8.0 * P.ncells * n_r + 8.0 * P.nloc * P.E * n_r
     achieved = alg_bytes / t_apply / 1e9
     traffic = measured_traffic(cfg.name)
+    rom_roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": ("k_apply2d_rw<2,32,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
+                + " (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": int(alg_bytes)}
+    if cfg.dim == 3:
+        # in 3D the FP64 combination (2 E (N_r + m) flops per active lane-node: combine, then apply;
+        # 16 flop per byte, past the ridge) binds the apply to the FP64 matrix cores
+        rom_flops = 2.0 * P.E * (n_r + m) * active_dofs / cfg.dim
+        rom_roof.update(bound="mfma", achieved=round(rom_flops / t_apply / 1e12, 2), peak=FP64_MFMA_PEAK_TF,
+                        unit="TFLOP/s", frac=round(rom_flops / t_apply / 1e12 / FP64_MFMA_PEAK_TF, 4),
+                        algorithmic_flops_per_launch=int(rom_flops), hbm_frac=round(achieved / HBM_PEAK_GBS, 4))
     # the whole reverse-mode stage against the bytes the method has to move once: X and Ybar read
     # and Xbar written (24 B per active DOF and RHS), the three principal stacks and alpha, the
     # greedy's Delta and both snapshot parts (3 x 8 B per snapshot entry per cell) with Z, and the
@@ -569,10 +581,7 @@ def main():
         "config": {"workload": cfg.name, "cells": P.ncells, "elements_per_cell": f"{cfg.nel}^{cfg.dim}",
                    "right_hand_sides": m, "principal_cap": cfg.cap, "tol": cfg.tol, "n_r": n_r,
                    "active_local_dofs": active_dofs, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": ("k_apply2d_rw<2,32,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
-                     + " (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": int(alg_bytes)},
+        "roofline": rom_roof,
         "cpu_baseline": cpu,
         "adjoint_roofline": dict(adjoint_roof(adj_bytes, adj_flops, t_adj), ms=round(ms_stage["adjoint"], 4),
                                  stage="ROM apply adjoint (Xbar, alpha_bar, mu/lam through the principal "
