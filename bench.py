@@ -470,9 +470,8 @@ def main():
     traffic = measured_traffic(cfg.name)
     rom_roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ("k_apply2d_rw<2,32,0,0> (ROM apply; the stage is this kernel alone)" if cfg.dim == 2 else
-                           "k_apply3d_mfma<NR,0,0> (ROM apply; stage time includes the alpha interleave)"),
-                "traffic_unit": "bytes per launch",
+                "kernel": ("k_apply2d_rw<2,32,0,0>" if cfg.dim == 2 else "k_apply3d_mfma<NR,0,0>")
+                + " (ROM apply; stage time includes the alpha interleave)", "traffic_unit": "bytes per launch",
                 "algorithmic_bytes_per_launch": int(alg_bytes)}
     if cfg.dim == 3:
         # in 3D the FP64 combination (2 E (N_r + m) flops per active lane-node: combine, then apply;

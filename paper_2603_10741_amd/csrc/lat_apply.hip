@@ -32,8 +32,6 @@ struct ApplyArgs {
     const uint64_t *umask;
     const double *K;          // principal stack [(a*E+e)*cap + k]  or plain ops [(q*E+e)*64 + l]
     const double *alpha_il;   // [cap][ld]
-    const double *alpha;      // 2D walks: the coefficients as given, [cell][cap] (canonical order)
-    const int32_t *perm;      // lane -> canonical cell, or -1
     const double *X;
     const double *Ybar;       // forms only
     double *Y;                // apply output, or form partials [chunk][ld*cap]
@@ -171,7 +169,7 @@ template <int MW, int NR, int MODE, int LP, bool IDLE = false>
 __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *__restrict__ goff,
                                                     const int32_t *__restrict__ uidx,
                                                     const uint64_t *__restrict__ umask, const double *__restrict__ K,
-                                                    const double *__restrict__ alpha, const double *__restrict__ X,
+                                                    const double *__restrict__ alpha_il, const double *__restrict__ X,
                                                     double *__restrict__ Y)
 {
     constexpr int E = 36, NW = 8;
@@ -207,19 +205,14 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
     const int e0 = (w * E) / NW, e1 = ((w + 1) * E) / NW;   // this wave's share of the entries
     const int32_t *ui = uidx + (int64_t)g * nloc;
     const int gq = goff[g];
-    // coefficient k of the cell on lane q, read from the caller's [cell][cap] array: zero past n_r
-    // and on padding lanes
-    auto coef = [&](int k, int64_t q) __attribute__((always_inline)) {
-        const int c = A.perm[q];
-        return (c >= 0 && k < A.n_r) ? alpha[(int64_t)c * cap + k] : 0.0;
-    };
     // alpha as the B operand of v_mfma_f64_16x16x4: wave w combines for cells ct*16 .. ct*16+15
     // (ct = w & 3); lane l holds alpha[k = 4 s + l / 16][cell = ct*16 + l % 16] in aB[s]
     const int ct = w & 3;
     double aB[MODE == 2 || BFS ? 1 : NR / 4];
     if (MODE != 2 && !BFS) {
 #pragma unroll
-        for (int s = 0; s < NR / 4; ++s) aB[s] = coef(4 * s + (l >> 4), (int64_t)g * LAT_WAVE + ct * 16 + (l & 15));
+        for (int s = 0; s < NR / 4; ++s)
+            aB[s] = alpha_il[(int64_t)(4 * s + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)];
     }
     // BFS: the coefficients as bf16 slices, B operand of v_mfma_f32_16x16x32_bf16: lane l holds
     // c[k = 32 kb + 8 (l / 16) .. + 7][cell = ct*16 + l % 16] in cB[slice][kb]
@@ -232,7 +225,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int k = 32 * kb + 8 * (l >> 4) + t;
-                const double c = k < NR ? coef(k, (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)) : 0.0;
+                const double c = k < NR ? alpha_il[(int64_t)k * A.ld + (int64_t)g * LAT_WAVE + ct * 16 + (l & 15)] : 0.0;
                 uint16_t b3[3];
                 lat_slice3(c, b3);
 #pragma unroll
@@ -496,7 +489,7 @@ __global__ __launch_bounds__(512) void k_apply2d_rw(ApplyArgs A, const int32_t *
                 const int er = 16 * et + (l & 15) < E ? 16 * et + (l & 15) : E - 1;
                 const double *rp = kb64 + er * KSTR + (l >> 4);
                 for (int s2 = 0; s2 < NR / 4; ++s2) {
-                    const double a64 = coef(4 * s2 + (l >> 4), (int64_t)g * LAT_WAVE + c16);
+                    const double a64 = alpha_il[(int64_t)(4 * s2 + (l >> 4)) * A.ld + (int64_t)g * LAT_WAVE + c16];
                     c = __builtin_amdgcn_mfma_f64_16x16x4f64(rp[4 * s2], a64, c, 0, 0, 0);
                 }
                 for (int r = 0; r < 4; ++r) {
@@ -1176,7 +1169,7 @@ lat_status launch_rowwalk_nr(const lat_plan *P, const ApplyArgs &A, hipStream_t 
     B.nseg = rowwalk_nseg(P);
     dim3 grid((unsigned)rowwalk_grid(P)), block(512);
 #define RW(NRV) hipLaunchKernelGGL((k_apply2d_rw<MW, NRV, MODE, LP, IDLE>), grid, block, 0, s, B, P->goff, P->uidx, \
-                                   P->umask, A.K, A.alpha, A.X, A.Y)
+                                   P->umask, A.K, A.alpha_il, A.X, A.Y)
     if (MODE == 2 || A.n_r <= 8) RW(8);
     else if (A.n_r <= 16) RW(16);
     else if (A.n_r <= 32) RW(32);
@@ -1225,7 +1218,6 @@ ApplyArgs base_args(const lat_plan *P, int m, int nch)
     A.rb = 0; A.mc = m;
     A.chunks_per_group = (int)lat_cdiv(std::max(P->maxunion, 1), nch);
     A.goff = P->goff; A.unode = P->unode; A.unbr = P->unbr; A.umask = P->umask;
-    A.perm = P->perm;
     return A;
 }
 
@@ -1281,9 +1273,7 @@ lat_status run_apply(const lat_plan *P, int mode, const double *K, int n_r, cons
     ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
     A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
     lat_status st;
-    // the 2D row walks read the coefficients as given; the other ROM kernels their [k][lane] copy
-    A.alpha = alpha;
-    if (mode != 2 && !(P->dim == 2 && P->nn >= 3)) {
+    if (mode != 2) {
         if ((st = interleave_alpha(P, n_r, alpha, s)) != LAT_OK) return st;
         A.alpha_il = P->alpha_il;
     }
@@ -1367,11 +1357,8 @@ lat_status run_apply_lowp(const lat_plan *P, int mode, const double *K, int n_r,
     }
     ApplyArgs A = base_args(P, m, APPLY_NODES_PER_WAVE);
     A.K = K; A.X = X; A.Y = Y; A.n_r = n_r;
-    A.alpha = coef;
-    if (P->dim == 3) {
-        if ((st = interleave_alpha(P, n_r, coef, s)) != LAT_OK) return st;
-        A.alpha_il = P->alpha_il;
-    }
+    if ((st = interleave_alpha(P, n_r, coef, s)) != LAT_OK) return st;
+    A.alpha_il = P->alpha_il;
     const int64_t nblk = P->dim == 2 ? rowwalk_grid(P) : apply3d_grid(P);
     int lev = prec == LAT_F32 ? 4 : (refine_tol >= 0x1p-8 ? 1 : (refine_tol >= 0x1p-16 ? 2 : 3));
     const int32_t *gate = nullptr;
