@@ -122,6 +122,34 @@ def test_greedy_lagged_residuals(case, cap):
     np.testing.assert_array_equal(case.canon_T(T_cil), go["Delta"])
 
 
+@pytest.mark.parametrize("cap", [5, 13])
+def test_greedy_lagged_rows(case, cap):
+    """The greedy on the leading rows only (the sampled-entry entry point), stopped between
+    write-backs: the ring of basis rows is then strided by the row count.  The outputs are the
+    oracle's greedy on those rows bit for bit, Z is zero past them, and the rows past them are
+    left as they were."""
+    P, cfg = case.P, case.cfg
+    cap = min(cap, P.cap)
+    T = case.orc["T"]
+    rows = P.nsnap // 3 + 7
+    T_cil = case.to_cil_T(T)
+    P.reset_status()
+    g = P.select_principal(T_cil, cfg.tol, cap=cap, keep_Z=True, rows=rows)
+    go = O.greedy(np.ascontiguousarray(T[:, :rows]), cfg.tol, cap, keep_Z=True)
+    P.check_status()
+    assert int(g["n_r"].item()) == go["n_r"]
+    np.testing.assert_array_equal(g["S"].cpu().numpy()[:cap], go["S"][:cap])
+    np.testing.assert_array_equal(g["beta"].cpu().numpy()[:, :cap], go["beta"][:, :cap])
+    np.testing.assert_array_equal(g["alpha"].cpu().numpy()[:, :cap], go["alpha"][:, :cap])
+    Z = g["Z"].cpu().numpy()
+    np.testing.assert_array_equal(Z[:cap, :rows], go["Z"][:cap])
+    assert not Z[:, rows:].any()
+    assert g["achieved"].item() == go["achieved"]
+    D = case.canon_T(T_cil)
+    np.testing.assert_array_equal(D[:, :rows], go["Delta"])
+    np.testing.assert_array_equal(D[:, rows:], T[:, rows:])
+
+
 def test_greedy_end_to_end(case):
     """GPU snapshots -> GPU greedy vs oracle snapshots -> oracle greedy: the same principal cells
     unless the arg-max margin at the diverging step is below the snapshots' rounding level."""
